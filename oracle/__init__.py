@@ -1,0 +1,150 @@
+"""FP64 CPU oracle for polar stroking -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously-correct implementation of the paper's method
+(Kilgard, "Polar Stroking", ACM TOG 2020), written in C++ (polar_oracle.cpp)
+and bound here with ctypes.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The GPU library never
+calls it and shares no code with it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "polar_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "libpolar_oracle.so")
+_lib = None
+
+ROLE_SEGMENT, ROLE_JOIN, ROLE_START_CAP, ROLE_END_CAP = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_int] + [P] * 8 + [ctypes.c_double, P, ctypes.c_int]
+        lib.oracle_count.restype = ctypes.c_int
+        lib.oracle_emit.argtypes = ([ctypes.c_int, ctypes.c_int] + [P] * 8 + [ctypes.c_double, P]
+                                    + [P] * 6 + [ctypes.c_int])
+        lib.oracle_emit.restype = ctypes.c_int
+        lib.oracle_segment_intervals.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double,
+                                                 P, P, P, P, P, ctypes.c_int]
+        lib.oracle_segment_intervals.restype = ctypes.c_int
+        lib.oracle_dash.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
+                                    P, P, P, P, ctypes.c_int64, ctypes.c_int64, P]
+        lib.oracle_dash.restype = ctypes.c_int64
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _batch_args(b):
+    return [b.n_paths, b.n_segs, _p(b.seg_begin), _p(b.kind), _p(b.cx), _p(b.cy), _p(b.conic_w),
+            _p(b.width), _p(b.join), _p(b.cap)]
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def count(b, q: float | None = None, nthreads: int = 0) -> np.ndarray:
+    """Ribs per link slot, int32 [2*S + P]."""
+    q = b.q if q is None else q
+    out = np.zeros(b.n_links, np.int32)
+    rc = _load().oracle_count(*_batch_args(b), ctypes.c_double(q), _p(out), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle_count failed ({rc})")
+    return out
+
+
+def offsets(link_ribs: np.ndarray) -> np.ndarray:
+    """Exclusive prefix sum, int64 [L+1]."""
+    off = np.zeros(link_ribs.shape[0] + 1, np.int64)
+    np.cumsum(link_ribs, dtype=np.int64, out=off[1:])
+    return off
+
+
+def emit(b, off: np.ndarray, q: float | None = None, nthreads: int = 0) -> dict:
+    """Vertices (vx, vy: [2R], N then P per rib), arc length vs [R], and per-rib
+    t, psi and role."""
+    q = b.q if q is None else q
+    R = int(off[-1])
+    vx = np.zeros(2 * R); vy = np.zeros(2 * R); vs = np.zeros(R)
+    t = np.zeros(R); psi = np.zeros(R); role = np.zeros(R, np.uint8)
+    off = np.ascontiguousarray(off, np.int64)
+    rc = _load().oracle_emit(*_batch_args(b), ctypes.c_double(q), _p(off), _p(vx), _p(vy), _p(vs),
+                             _p(t), _p(psi), _p(role), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle_emit failed ({rc})")
+    return dict(vx=vx, vy=vy, vs=vs, t=t, psi=psi, role=role)
+
+
+def stroke(b, q: float | None = None, nthreads: int = 0) -> dict:
+    ribs = count(b, q, nthreads)
+    off = offsets(ribs)
+    out = emit(b, off, q, nthreads)
+    out.update(link_ribs=ribs, offsets=off)
+    return out
+
+
+def path_rib_begin(b, off: np.ndarray) -> np.ndarray:
+    """First rib of every path (and the total at the end), int64 [P+1]."""
+    p = np.arange(b.n_paths + 1, dtype=np.int64)
+    return np.ascontiguousarray(off[2 * b.seg_begin.astype(np.int64) + p])
+
+
+def segment_intervals(kind: int, pts, q: float, w: float = 1.0):
+    """Intervals of one segment: list of (t0, t1, psi0, delta, steps)."""
+    px = np.zeros(4); py = np.zeros(4)
+    for i, (x, y) in enumerate(pts):
+        px[i], py[i] = np.float32(x), np.float32(y)
+    cap = 8
+    t0 = np.zeros(cap); t1 = np.zeros(cap); p0 = np.zeros(cap); d = np.zeros(cap)
+    st = np.zeros(cap, np.int32)
+    n = _load().oracle_segment_intervals(kind, _p(px), _p(py), ctypes.c_double(np.float32(w)),
+                                         ctypes.c_double(q), _p(t0), _p(t1), _p(p0), _p(d), _p(st), cap)
+    return [(t0[k], t1[k], p0[k], d[k], int(st[k])) for k in range(n)]
+
+
+def dash(rib_begin: np.ndarray, vx: np.ndarray, vy: np.ndarray, vs: np.ndarray, pattern,
+         phase: float = 0.0) -> dict:
+    """Dash an FP32 rib stream: returns dx, dy ([2R']), ds ([R']) and ranges [D,2]."""
+    vx = np.ascontiguousarray(vx, np.float32); vy = np.ascontiguousarray(vy, np.float32)
+    vs = np.ascontiguousarray(vs, np.float32)
+    rib_begin = np.ascontiguousarray(rib_begin, np.int64)
+    pat = np.ascontiguousarray(pattern, np.float64)
+    cap = 16
+    while True:
+        dx = np.zeros(2 * cap); dy = np.zeros(2 * cap); ds = np.zeros(cap)
+        rng = np.zeros(2 * cap, np.int64)
+        nd = np.zeros(1, np.int64)
+        n = _load().oracle_dash(len(rib_begin) - 1, _p(rib_begin), _p(vx), _p(vy), _p(vs), _p(pat),
+                                len(pat), ctypes.c_double(phase), _p(dx), _p(dy), _p(ds), _p(rng),
+                                cap, cap, _p(nd))
+        if n == -1 and len(pat) < 2:
+            raise ValueError("bad dash pattern")
+        if n >= 0 and nd[0] <= cap:
+            return dict(dx=dx[:2 * n], dy=dy[:2 * n], ds=ds[:n], ranges=rng[:2 * nd[0]].reshape(-1, 2))
+        cap = max(2 * cap, int(abs(n)) + 1, int(nd[0]) + 1)

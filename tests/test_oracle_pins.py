@@ -1,0 +1,398 @@
+"""Pins for the FP64 oracle (CPU only).
+
+Each test checks the oracle against something other than itself: hand-derived
+cases (tests/golden), closed forms, brute-force sampling of the curve with an
+independent de Casteljau evaluator (tests/geom_ref.py), and invariants the paper
+states.  A plausible slip in the oracle -- a dropped term, a wrong sign, a
+swapped index, a transposed operand -- fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_00308_amd import workloads as W
+from tests import geom_ref as G
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_derived.json")))["cases"]
+
+
+def gold(name):
+    return next(c for c in GOLD if c["name"] == name)
+
+
+def stroke1(kind, pts, q, w=1.0, width=2.0, join=W.JOIN_ROUND, cap=W.CAP_BUTT):
+    b = W.single(kind, pts, w=w, width=width, q=q, join=join, cap=cap)
+    return b, oracle.stroke(b)
+
+
+def seg_ribs(o, b, seg=0, path=0):
+    slot = 2 * seg + path + 1
+    return slice(int(o["offsets"][slot]), int(o["offsets"][slot + 1]))
+
+
+def angdiff(a, b):
+    return (a - b + np.pi) % (2 * np.pi) - np.pi
+
+
+# ---------------------------------------------------------------- golden cases
+def test_golden_cusp():
+    c = gold("exact cusp cubic")
+    q = math.radians(c["q_deg"])
+    iv = oracle.segment_intervals(c["kind"], c["points"], q)
+    assert len(iv) == c["intervals"]
+    assert [v[4] for v in iv] == c["steps"]
+    b, o = stroke1(c["kind"], c["points"], q, width=c["width"])
+    sl = seg_ribs(o, b)
+    t = o["t"][sl]
+    assert len(t) == c["ribs"]
+    lo, hi = c["fan_ribs"]
+    fan = np.abs(t - c["cusp_t"]) < 1e-12
+    assert np.all(fan[lo:hi + 1]), np.nonzero(~fan[lo:hi + 1])
+    assert not fan[lo - 1] and not fan[hi + 1]
+    # the fan normals sweep pi in steps of at most q
+    psi = o["psi"][sl][lo - 1:hi + 2]
+    assert psi[-1] - psi[0] >= math.pi
+    assert np.all(np.abs(np.diff(psi)) <= q * (1 + 1e-9))
+
+
+def test_golden_line():
+    c = gold("line segment")
+    b, o = stroke1(c["kind"], c["points"], math.radians(c["q_deg"]), width=c["width"])
+    assert o["link_ribs"].tolist() == [0, c["ribs"], 0]
+    v = np.column_stack([o["vx"][0::2], o["vy"][0::2], o["vx"][1::2], o["vy"][1::2]])
+    # vertex order per rib: N = G - (w/2) n, P = G + (w/2) n, n = (-sin psi, cos psi)
+    np.testing.assert_allclose(v, np.array(c["vertices"])[:, [2, 3, 0, 1]], atol=1e-12)
+    assert o["vs"][-1] == pytest.approx(c["length"], abs=1e-12)
+
+
+def test_golden_quarter_circle():
+    c = gold("quarter circle as a conic")
+    q = math.radians(c["q_deg"])
+    b, o = stroke1(c["kind"], c["points"], q, w=c["w"], width=c["width"])
+    assert o["link_ribs"][1] == c["ribs"]
+    Gx = 0.5 * (o["vx"][0::2] + o["vx"][1::2]); Gy = 0.5 * (o["vy"][0::2] + o["vy"][1::2])
+    r = np.hypot(Gx, Gy)
+    # FP32 rounding of the weight moves the conic off the circle by ~r*1e-8
+    np.testing.assert_allclose(r, c["radius"], atol=1e-5)
+    rN = np.hypot(o["vx"][0::2], o["vy"][0::2]); rP = np.hypot(o["vx"][1::2], o["vy"][1::2])
+    np.testing.assert_allclose(np.sort(np.r_[rN, rP]),
+                               np.sort(np.r_[np.full(len(r), c["radius"] - c["width"] / 2),
+                                             np.full(len(r), c["radius"] + c["width"] / 2)]), atol=1e-5)
+    # rib centres at uniform angles j*theta/N
+    ang = np.arctan2(Gy, Gx)
+    np.testing.assert_allclose(ang, np.linspace(0, math.pi / 2, c["ribs"]), atol=1e-7)
+    assert o["vs"][-1] == pytest.approx(c["chord_sum"], abs=1e-5)
+
+
+def test_golden_join():
+    c = gold("right-angle round join")
+    segs = [(k, pts, 1.0) for k, pts in c["segments"]]
+    b = W.path(segs, width=c["width"], q=math.radians(c["q_deg"]), join=c["join"], cap=c["cap"])
+    o = oracle.stroke(b)
+    assert o["link_ribs"].tolist() == c["link_ribs"]
+    j = slice(2, 35)
+    # pivot at the shared point; outer vertex at w/2 on the outside (N side for a left turn)
+    d_out = np.hypot(o["vx"][0::2][j] - 100, o["vy"][0::2][j] - 0)
+    d_in = np.hypot(o["vx"][1::2][j] - 100, o["vy"][1::2][j] - 0)
+    np.testing.assert_allclose(d_out, c["width"] / 2, atol=1e-12)
+    np.testing.assert_allclose(d_in, 0, atol=1e-12)
+    # the outer vertex lies outside the turn: below/right of the corner
+    assert np.all(o["vx"][0::2][j] >= 100 - 1e-9) and np.all(o["vy"][0::2][j] <= 1e-9)
+
+
+@pytest.mark.parametrize("cap", [0, 1, 2, 3])
+def test_golden_caps(cap):
+    c = gold("caps")
+    b, o = stroke1(c["kind"], c["points"], math.radians(c["q_deg"]), width=c["width"], cap=cap)
+    J = c["cap_ribs"][str(cap)]
+    assert o["link_ribs"].tolist() == [J, 2, J]
+    if J == 0:
+        return
+    r = c["width"] / 2
+    # start cap: outer vertices on the N side, behind the start point (x <= 0)
+    sN = np.column_stack([o["vx"][0:2 * J:2], o["vy"][0:2 * J:2]])
+    sP = np.column_stack([o["vx"][1:2 * J:2], o["vy"][1:2 * J:2]])
+    np.testing.assert_allclose(sP, 0, atol=1e-12)
+    assert np.all(sN[:, 0] <= 1e-9)
+    d = np.hypot(sN[:, 0], sN[:, 1])
+    if cap == W.CAP_SQUARE:
+        np.testing.assert_allclose(d, [r, r * math.sqrt(2), r, r * math.sqrt(2), r], atol=1e-12)
+        np.testing.assert_allclose(sN[2], [-r, 0], atol=1e-12)
+    else:
+        np.testing.assert_allclose(d, r, atol=1e-12)
+    # the start cap ends on the N vertex of the segment's first rib (no twist)
+    np.testing.assert_allclose(sN[-1], [o["vx"][2 * J], o["vy"][2 * J]], atol=1e-12)
+    # end cap: outer vertices on the P side, ahead of the end point (x >= 50)
+    e0 = J + 2
+    eP = np.column_stack([o["vx"][2 * e0 + 1::2], o["vy"][2 * e0 + 1::2]])
+    assert np.all(eP[:, 0] >= 50 - 1e-9)
+    np.testing.assert_allclose(eP[0], [o["vx"][2 * e0 - 1], o["vy"][2 * e0 - 1]], atol=1e-12)
+
+
+# ------------------------------------------------------ closed forms over ranges
+@pytest.mark.parametrize("deg", [1.0, 30.0, 89.0, 90.0, 135.0, 170.0])
+def test_circular_arc_counts_and_radii(deg):
+    theta = math.radians(deg)
+    q = math.pi / 64
+    r, cx, cy, a0 = 200.0, 300.0, 250.0, 0.3
+    P0 = (cx + r * math.cos(a0), cy + r * math.sin(a0))
+    P2 = (cx + r * math.cos(a0 + theta), cy + r * math.sin(a0 + theta))
+    m = r / math.cos(theta / 2)
+    P1 = (cx + m * math.cos(a0 + theta / 2), cy + m * math.sin(a0 + theta / 2))
+    b, o = stroke1(W.KIND_K, [P0, P1, P2], q, w=math.cos(theta / 2), width=6.0)
+    N = o["link_ribs"][1] - 1
+    # the FP32 inputs perturb the exact turning by ~1e-7 rad
+    x = theta / q
+    if abs(x - round(x)) > 1e-5:
+        assert N == max(1, math.ceil(x))
+    Gx = 0.5 * (o["vx"][0::2] + o["vx"][1::2]) - cx; Gy = 0.5 * (o["vy"][0::2] + o["vy"][1::2]) - cy
+    np.testing.assert_allclose(np.hypot(Gx, Gy), r, rtol=2e-6)
+    expect = 2 * r * N * math.sin(theta / (2 * N))
+    # FP32 input rounding moves the end points by up to ~3e-5 px here
+    assert o["vs"][-1] == pytest.approx(expect, rel=2e-6, abs=1e-4)
+    assert o["vs"][-1] <= r * theta * (1 + 1e-6)
+
+
+def test_parabola_t_matches_dense_tangents():
+    pts = [(0, 0), (300, 400), (700, -50)]
+    q = math.pi / 90
+    b, o = stroke1(W.KIND_Q, pts, q)
+    sl = seg_ribs(o, b)
+    t, psi = o["t"][sl], o["psi"][sl]
+    d, _ = G.tangent_dirs(W.KIND_Q, pts, t)
+    err = np.abs(angdiff(np.arctan2(d[:, 1], d[:, 0]), psi))
+    assert err.max() < 1e-6
+    # total turning = angle between the two legs of the control polygon
+    turn = abs(angdiff(math.atan2(-450, 400), math.atan2(400, 300)))
+    assert len(t) - 1 == math.ceil(turn / q - 1e-9)
+
+
+# ------------------------------------------------------------------ brute force
+TINY = [
+    (W.KIND_C, [(0, 0), (1, 2), (3, 2), (4, 0)], 1.0),          # arch
+    (W.KIND_C, [(0, 0), (4, 3), (-1, 3), (3, 0)], 1.0),         # loop
+    (W.KIND_C, [(0, 0), (2, 3), (2, -3), (4, 0)], 1.0),         # serpentine, 1 inflection
+    (W.KIND_C, [(0, 0), (3, 2), (-1, 2), (2, 0)], 1.0),         # loop-ish
+    (W.KIND_C, [(0, 0), (2, 2), (-2, -2), (5, 1)], 1.0),        # 2 inflections
+    (W.KIND_C, [(0, 0), (1, 1), (0, 1), (1, 0)], 1.0),          # exact cusp
+    (W.KIND_Q, [(0, 0), (5, 5), (10, -1)], 1.0),
+    (W.KIND_K, [(0, 0), (5, 5), (10, -1)], 0.3),                # internal ellipse
+    (W.KIND_K, [(0, 0), (5, 5), (10, -1)], 3.0),                # internal hyperbola
+    (W.KIND_K, [(0, 0), (0, 7), (7, 7)], 1.0),                  # parabola as conic
+]
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_brute_force_turning_and_reversals(case):
+    kind, pts, w = TINY[case]
+    q = math.pi / 128
+    iv = oracle.segment_intervals(kind, pts, q, w=w)
+    total = sum(abs(v[3]) for v in iv)
+    dense, da = G.dense_turning(kind, pts, w=w)
+    assert total == pytest.approx(dense, abs=2e-3)
+    # reversals = sign changes of the sampled turning (ignoring cusp jumps),
+    # sampled coarsely so finite-difference noise near an inflection cannot flip it
+    _, da = G.dense_turning(kind, pts, w=w, n=20_001)
+    small = da[np.abs(da) < 0.5]
+    sg = np.sign(small[np.abs(small) > 1e-9])
+    flips = int(np.sum(sg[1:] != sg[:-1]))
+    # interior boundaries that are not half-angle splits
+    bounds = [v[0] for v in iv[1:]]
+    splits = sum(1 for k in range(1, len(iv)) if abs(iv[k][3] - iv[k - 1][3]) < 1e-15
+                 and abs(iv[k][2] - (iv[k - 1][2] + iv[k - 1][3])) < 1e-12
+                 and np.sign(iv[k][3]) == np.sign(iv[k - 1][3]))
+    assert flips == len(bounds) - splits
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_brute_force_rib_directions(case):
+    kind, pts, w = TINY[case]
+    q = math.pi / 64
+    b, o = stroke1(kind, pts, q, w=w)
+    sl = seg_ribs(o, b)
+    t, psi = o["t"][sl], o["psi"][sl]
+    d, speed = G.tangent_dirs(kind, pts, t, w=w)
+    ok = speed > 1e-3
+    err = np.abs(angdiff(np.arctan2(d[ok, 1], d[ok, 0]), psi[ok]))
+    assert err.max() < 1e-5
+    # ribs with no usable tangent sit on a cusp found by sampling
+    if np.any(~ok):
+        ts = np.linspace(0, 1, 1_000_001)
+        _, sp = G.tangent_dirs(kind, pts, ts, w=w, h=1e-7)
+        tc = ts[np.argmin(sp)]
+        assert np.all(np.abs(t[~ok] - tc) < 1e-6)
+    # consecutive rib tangents differ by at most q
+    assert np.all(np.abs(np.diff(psi)) <= q * (1 + 1e-9))
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_rib_points_on_curve_and_width(case):
+    kind, pts, w = TINY[case]
+    b, o = stroke1(kind, pts, math.pi / 64, w=w, width=0.5)
+    sl = seg_ribs(o, b)
+    t = o["t"][sl]
+    Nx, Ny = o["vx"][0::2][sl], o["vy"][0::2][sl]
+    Px, Py = o["vx"][1::2][sl], o["vy"][1::2][sl]
+    ref = G.point(kind, pts, t, w)
+    np.testing.assert_allclose(0.5 * (Nx + Px), ref[:, 0], atol=1e-12)
+    np.testing.assert_allclose(0.5 * (Ny + Py), ref[:, 1], atol=1e-12)
+    np.testing.assert_allclose(np.hypot(Px - Nx, Py - Ny), 0.5, atol=1e-12)
+    # P lies to the left of the tangent psi
+    psi = o["psi"][sl]
+    side = (Px - Nx) * -np.sin(psi) + (Py - Ny) * np.cos(psi)
+    assert np.all(side > 0)
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_arc_length_bounds(case):
+    kind, pts, w = TINY[case]
+    q = math.pi / 64
+    b, o = stroke1(kind, pts, q, w=w)
+    L = G.arc_length(kind, pts, w=w)
+    S = o["vs"][-1]
+    assert L * math.cos(q / 2) * (1 - 1e-9) <= S <= L * (1 + 1e-9)
+    # converges as q shrinks
+    _, o2 = stroke1(kind, pts, q / 8, w=w)
+    assert abs(o2["vs"][-1] - L) < abs(S - L) + 1e-12
+
+
+def test_conic_derivative_direction():
+    # the closed-form t-solve of the conic must agree with dense sampling
+    for w in (0.05, 0.5, 2.0, 20.0):
+        pts = [(0, 0), (50, 80), (120, 10)]
+        b, o = stroke1(W.KIND_K, pts, math.pi / 64, w=w)
+        sl = seg_ribs(o, b)
+        d, sp = G.tangent_dirs(W.KIND_K, pts, o["t"][sl], w=w, h=1e-8)
+        ok = sp > 1e-6
+        err = np.abs(angdiff(np.arctan2(d[ok, 1], d[ok, 0]), o["psi"][sl][ok]))
+        assert err.max() < 1e-5, w
+
+
+def test_collinear_fold_is_a_cusp():
+    # a cubic running 0 -> 10, back to ~-3, then to 5 along the x axis
+    pts = [(0, 0), (20, 0), (-15, 0), (5, 0)]
+    q = math.pi / 16
+    iv = oracle.segment_intervals(W.KIND_C, pts, q)
+    # flat, pivot, flat, pivot, flat
+    assert [v[4] for v in iv] == [1, 16, 1, 16, 1]
+    assert [v[3] for v in iv] == [0.0, math.pi, 0.0, math.pi, 0.0]
+    # the folds are where the sampled x velocity changes sign
+    ts = np.linspace(0, 1, 1_000_001)
+    x = G.point(W.KIND_C, pts, ts)[:, 0]
+    turns = ts[1:-1][np.sign(np.diff(x))[1:] != np.sign(np.diff(x))[:-1]]
+    np.testing.assert_allclose([iv[1][0], iv[3][0]], turns, atol=2e-6)
+
+
+@pytest.mark.parametrize("pts", [
+    [(0, 0), (0, 0), (40, 30), (80, 0)],        # P1 = P0
+    [(0, 0), (40, 30), (80, 0), (80, 0)],       # P2 = P3
+    [(0, 0), (0, 0), (80, 0), (80, 0)],         # P1 = P0 and P2 = P3 (a line)
+    [(0, 0), (50, 50), (50, 50), (50, 50)],     # P1 = P2 = P3
+    [(0, 0), (0, 0), (0, 0), (30, -40)],        # P0 = P1 = P2
+])
+def test_end_tangent_fallbacks_match_motion(pts):
+    # first and last rib tangents, and the tangents the round caps pivot from,
+    # equal the direction of motion just inside the ends
+    b, o = stroke1(W.KIND_C, pts, math.pi / 32, cap=W.CAP_ROUND)
+    sl = seg_ribs(o, b)
+    psi = o["psi"][sl]
+    cap0 = o["psi"][int(o["offsets"][1]) - 1]          # last rib of the start cap
+    cap1 = o["psi"][int(o["offsets"][2])]              # first rib of the end cap
+    assert abs(angdiff(cap0, psi[0])) < 1e-12 and abs(angdiff(cap1, psi[-1])) < 1e-12
+    # chords over the first and last 1e-3 of t (the speed may vanish at an end)
+    p = G.point(W.KIND_C, pts, np.array([0.0, 1e-3, 1 - 1e-3, 1.0]))
+    d0 = p[1] - p[0]; d1 = p[3] - p[2]
+    assert abs(angdiff(math.atan2(d0[1], d0[0]), psi[0])) < 2e-2
+    assert abs(angdiff(math.atan2(d1[1], d1[0]), psi[-1])) < 2e-2
+
+
+def test_zero_length_segments_are_transparent():
+    segs = [(W.KIND_L, [(0, 0), (10, 0)], 1.0),
+            (W.KIND_C, [(10, 0), (10, 0), (10, 0), (10, 0)], 1.0),
+            (W.KIND_L, [(10, 0), (10, 10)], 1.0)]
+    b = W.path(segs, width=2.0, q=math.pi / 8, cap=W.CAP_SQUARE)
+    o = oracle.stroke(b)
+    # slots: cap, L, join(L->L across the point), point, join(empty), L, cap
+    assert o["link_ribs"].tolist() == [5, 2, 5, 0, 0, 2, 5]
+
+
+# ------------------------------------------------------------- invariants
+def _batch_invariants(b):
+    o = oracle.stroke(b)
+    q = b.q
+    off = o["offsets"]
+    assert off[0] == 0 and np.all(np.diff(off) == o["link_ribs"])
+    role = o["role"]
+    for p in range(b.n_paths):
+        s0, s1 = b.seg_begin[p], b.seg_begin[p + 1]
+        for slot in range(2 * s0 + p, 2 * s1 + p + 1):
+            a, e = int(off[slot]), int(off[slot + 1])
+            if e - a < 2:
+                assert e == a
+                continue
+            psi = o["psi"][a:e]
+            assert np.all(np.abs(np.diff(psi)) <= q * (1 + 1e-9) + 1e-12)
+            if role[a] == oracle.ROLE_SEGMENT:
+                N = np.column_stack([o["vx"][2 * a:2 * e:2], o["vy"][2 * a:2 * e:2]])
+                P = np.column_stack([o["vx"][2 * a + 1:2 * e:2], o["vy"][2 * a + 1:2 * e:2]])
+                np.testing.assert_allclose(np.hypot(*(P - N).T), b.width[p], rtol=1e-12)
+    return o
+
+
+def test_invariants_random_batch():
+    b = W.random_mixed(7, n_paths=40, max_segs=12, extent=512.0)
+    _batch_invariants(b)
+
+
+def test_count_invariance_under_exact_transforms():
+    b = W.random_mixed(11, n_paths=30, max_segs=10, extent=256.0)
+    base = oracle.count(b)
+    # rotation by 90 degrees, translation on the grid, scale by 2: all exact in FP32
+    for f in (lambda x, y: (-y, x), lambda x, y: (x + 1024.0, y - 512.0), lambda x, y: (2 * x, 2 * y)):
+        nx, ny = f(b.cx.astype(np.float64), b.cy.astype(np.float64))
+        b2 = W.Batch(b.seg_begin, b.kind, nx.astype(np.float32), ny.astype(np.float32), b.conic_w,
+                     b.width, b.join, b.cap, q=b.q)
+        np.testing.assert_array_equal(oracle.count(b2), base)
+
+
+def test_count_invariance_under_segment_reversal():
+    b = W.random_mixed(13, n_paths=200, max_segs=1, extent=512.0, cusp_frac=0.1)
+    base = oracle.count(b)
+    cx, cy = b.cx.copy(), b.cy.copy()
+    for i in range(b.n_segs):
+        n = W.NPTS[int(b.kind[i])]
+        cx[:n, i] = cx[:n, i][::-1]
+        cy[:n, i] = cy[:n, i][::-1]
+    b2 = W.Batch(b.seg_begin, b.kind, cx, cy, b.conic_w, b.width, b.join, b.cap, q=b.q)
+    rev = oracle.count(b2)
+    seg_slots = 2 * np.arange(b.n_segs) + np.arange(b.n_paths).repeat(1) + 1
+    np.testing.assert_array_equal(rev[seg_slots], base[seg_slots])
+
+
+# ------------------------------------------------------------------ dashing
+def test_dash_straight_line():
+    # one path, ribs along x with s = x: dash [10 on, 5 off]
+    xs = np.array([0.0, 7.0, 12.0, 31.0, 33.0, 33.0, 40.0], np.float32)
+    vx = np.repeat(xs, 2); vy = np.tile([-1.0, 1.0], len(xs)).astype(np.float32)
+    d = oracle.dash(np.array([0, len(xs)]), vx, vy, xs, [10.0, 5.0])
+    starts = d["ds"][d["ranges"][:, 0]]
+    ends = d["ds"][d["ranges"][:, 1] - 1]
+    np.testing.assert_allclose(starts, [0, 15, 30])
+    np.testing.assert_allclose(ends, [10, 25, 40])
+    # boundary ribs interpolate both vertices
+    np.testing.assert_allclose(d["dx"][0::2], d["ds"])
+    assert np.all(d["dy"][0::2] == -1) and np.all(d["dy"][1::2] == 1)
+
+
+def test_dash_phase_and_restart():
+    xs = np.linspace(0, 50, 11).astype(np.float32)
+    vx = np.repeat(xs, 2); vy = np.zeros_like(vx)
+    rb = np.array([0, 11, 22])
+    d = oracle.dash(rb, np.r_[vx, vx], np.r_[vy, vy], np.r_[xs, xs], [4.0, 6.0], phase=7.0)
+    # pattern position 7 at s=0 is in the gap (4..10): first dash starts at s=3
+    starts = d["ds"][d["ranges"][:, 0]]
+    np.testing.assert_allclose(starts, [3, 13, 23, 33, 43, 3, 13, 23, 33, 43])
