@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark: batched polar-stroking tessellation on one MI355X.
+
+Workload (one "step" = count -> scan -> emit with arc length, the whole hot
+path, over one batch): 4,096 open paths with log-uniform [1,512] segments
+(60/25/15 % cubic/quadratic/conic, 5 % cusp and 5 % coincident-point cubics),
+coordinates in [0,4096)^2, width log-uniform [0.5,64], q = pi/64, round joins,
+butt caps; synthetic, seeded.  The batched form replays one hipGraph per step.
+
+Prints one JSON line: stroke vertices/s of the batched form, the emit kernel's
+HBM roofline fraction, the per-path form on the same GPU, the FP64 CPU oracle
+timed on the host, and the maximum vertex / arc-length error against it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(V: int, S: int, P: int) -> int:
+    # each vertex written once as x, y, s (FP32); control data read once per
+    # segment (4 x,y FP32 points, kind, weight); path data (CSR, width, styles)
+    return 12 * V + 37 * S + 10 * P
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32_fixup", choices=["fp32", "fp32_fixup", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-per-path", action="store_true", help="skip the per-path form")
+    ap.add_argument("--profile", action="store_true", help="few steps, no oracle (for rocprofv3)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        return 2
+    if args.profile:
+        args.no_cpu = True
+        args.no_per_path = True
+
+    import torch
+    import paper_2007_00308_amd as ps
+    from paper_2007_00308_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prec = {"fp32": ps.PS_PREC_FP32, "fp32_fixup": ps.PS_PREC_FP32_FIXUP, "fp64": ps.PS_PREC_FP64}[args.precision]
+
+    t0 = time.time()
+    b = W.config2_fast()
+    log(f"workload {b.name}: {b.n_paths} paths, {b.n_segs} segments ({time.time() - t0:.1f}s)")
+    db = ps.DeviceBatch(b, device=dev)
+
+    # size the outputs from one counting pass (outside the timed region)
+    first = ps.stroke(db, b.q, precision=prec)
+    R = first["total_ribs"]
+    V = 2 * R
+    cap = V
+    log(f"ribs {R}, vertices {V}")
+    del first
+    torch.cuda.synchronize()
+
+    plan = ps.Plan(db, b.q, vertex_capacity=cap, precision=prec)
+    K, waves = plan.config()
+    log(f"plan: autotuned emit mapping K={K} waves/group={waves}")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_step = 1e3 * t_total / args.steps
+    st = plan.status()
+    assert st.flags == 0, f"status flags {st.flags}"
+    assert st.total_ribs == R
+    vps = V / (ms_step * 1e-3)
+    B_alg = algorithmic_bytes(V, b.n_segs, b.n_paths)
+    log(f"batched: {ms_step:.3f} ms/step, {vps / 1e9:.2f} G vertices/s, "
+        f"{B_alg / (ms_step * 1e-3) / 1e9:.0f} GB/s; fix-ups {st.fixups}")
+
+    # the emit kernel alone, timed with HIP events on the stream it runs on
+    reps = max(5, args.steps)
+    ps.ps_set_emit_config(K, waves)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, cap, plan.ws)
+    ev0.record(stream)
+    for _ in range(reps):
+        ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, cap, plan.ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    emit_ms = ev0.elapsed_time(ev1) / reps
+    emit_bytes = algorithmic_bytes(V, b.n_segs, b.n_paths)
+    emit_gbs = emit_bytes / (emit_ms * 1e-3) / 1e9
+    log(f"emit call: {emit_ms:.3f} ms, {emit_gbs:.0f} GB/s algorithmic ({emit_gbs / HBM_PEAK_GBS:.1%} of peak)")
+
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calib} MiB read + written")
+
+    per_path = None
+    if not args.no_per_path:
+        # plain per-path form: count, scan, emit launched per path into the same output
+        log("per-path form ...")
+        off = plan.offsets.cpu().numpy()
+        sb = b.seg_begin.astype(np.int64)
+        subs = []
+        max_ws = 0
+        for p in range(b.n_paths):
+            sub = ps.DeviceBatch(b.subset([p]), device=dev)
+            r0 = int(off[2 * sb[p] + p]); r1 = int(off[2 * sb[p + 1] + p + 1])
+            subs.append((sub, r0, r1))
+            max_ws = max(max_ws, ps.ps_workspace_bytes(sub, plan.params, 2 * (r1 - r0)))
+        ws = ps.alloc_workspace(max_ws, dev)
+        lr = torch.empty(2 * int(np.diff(sb).max()) + 1, dtype=torch.int32, device=dev)
+        of = torch.empty(lr.numel() + 1, dtype=torch.int64, device=dev)
+        px, py, pv = torch.empty_like(plan.vx), torch.empty_like(plan.vy), torch.empty_like(plan.vs)
+
+        def run_per_path():
+            for sub, r0, r1 in subs:
+                ps.ps_count(sub, plan.params, lr, ws)
+                ps.ps_scan(lr, sub.n_links, of, ws)
+                ps.ps_emit(sub, plan.params, of, px[2 * r0:], py[2 * r0:], pv[2 * r0:], 2 * (r1 - r0), ws)
+
+        run_per_path()
+        torch.cuda.synchronize()
+        steps_pp = 2
+        t1 = time.perf_counter()
+        for _ in range(steps_pp):
+            run_per_path()
+        torch.cuda.synchronize()
+        pp_ms = 1e3 * (time.perf_counter() - t1) / steps_pp
+        same = bool(torch.equal(px[:V], plan.vx[:V]) and torch.equal(pv[:V], plan.vs[:V]))
+        per_path = {"value": V / (pp_ms * 1e-3), "unit": "vertices/s", "ms_per_step": pp_ms,
+                    "launches_per_step": 7 * b.n_paths, "identical_output": same}
+        log(f"per-path: {pp_ms:.1f} ms/step ({V / (pp_ms * 1e-3) / 1e9:.3f} G vertices/s), "
+            f"identical output: {same}")
+
+    cpu = None
+    errors = None
+    if not args.no_cpu:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        log(f"oracle on the host, {threads} threads ...")
+        t2 = time.perf_counter()
+        ref = oracle.stroke(b, nthreads=threads)
+        cpu_s = time.perf_counter() - t2
+        cpu = {"value": V / cpu_s, "unit": "vertices/s", "cores": threads, "kind": "oracle",
+               "sample": f"the full workload ({b.n_paths} paths, {V} vertices), one pass, "
+                         f"{cpu_s:.2f} s"}
+        log(f"oracle: {cpu_s:.2f} s ({V / cpu_s / 1e6:.1f} M vertices/s)")
+        counts_equal = bool(np.array_equal(plan.link_ribs[:db.n_links].cpu().numpy(), ref["link_ribs"]))
+        vx = plan.vx[:V].cpu().numpy(); vy = plan.vy[:V].cpu().numpy(); vs = plan.vs[:V].cpu().numpy()
+        verr = np.hypot(vx - ref["vx"], vy - ref["vy"])
+        serr = np.abs(vs[0::2] - ref["vs"])
+        rel = serr / np.maximum(ref["vs"], 1.0)
+        errors = {"counts_bit_exact": counts_equal, "max_vertex_err_px": float(verr.max()),
+                  "p99999_vertex_err_px": float(np.quantile(verr, 0.99999)),
+                  "max_arclen_err_px": float(serr.max()), "max_arclen_rel_err": float(rel.max()),
+                  "fixup_ribs": int(st.fixups), "fixup_frac": float(st.fixups) / max(1, R)}
+        log(f"errors: {errors}")
+        del ref
+
+    result = {
+        "metric": "stroke vertices/s & % HBM peak, batched vs per-path, <=2e-3 px vs FP64 oracle",
+        "value": vps,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == ps.PS_PREC_FP32 else ("f64" if prec == ps.PS_PREC_FP64 else "f32+f64"),
+        "data": "synthetic",
+        "config": {"workload": "batched: 4096 paths, log-uniform [1,512] segments, 60/25/15% C/Q/K, "
+                               "q=pi/64, round joins, butt caps",
+                   "paths": b.n_paths, "segments": b.n_segs, "ribs": R, "vertices": V,
+                   "precision": args.precision, "emit_K": K, "emit_waves_per_group": waves},
+        "gb_per_s": B_alg / (ms_step * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": emit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": emit_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "emit (prepare + persistent emit, one ps_emit call)",
+                     "ms_per_launch": emit_ms, "algorithmic_bytes_per_launch": emit_bytes},
+        "per_path": per_path,
+        "cpu_baseline": cpu,
+        "errors": errors,
+    }
+    plan.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

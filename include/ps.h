@@ -1,0 +1,237 @@
+/*
+ * ps.h -- C ABI of the MI355X polar-stroking tessellator.
+ *
+ * Method: M. J. Kilgard, "Polar Stroking: New Theory and Methods for Stroking
+ * Paths", ACM TOG 39(4) art. 145, 2020.  A stroked path is tessellated into a
+ * quad strip by stepping every segment, join and cap in uniform steps of
+ * tangent angle q, with the number of steps known before any vertex is made.
+ *
+ * The pipeline is   ps_count -> ps_scan -> ps_emit (vertices + arc length)
+ *                                         -> ps_dash (optional)
+ * or the same chain captured once in a hipGraph by ps_plan_create.
+ *
+ * Conventions for every entry point:
+ *  - All array pointers are DEVICE pointers unless marked "host", owned by the
+ *    caller, and must stay valid until the stream work that uses them ends.
+ *    The library allocates nothing per call and keeps no pointer after a call
+ *    returns (a ps_plan keeps the pointers it was created with).
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.  Every
+ *    call is stream-ordered and asynchronous; no call synchronises the device
+ *    except ps_read_status and ps_plan_create.
+ *  - Return value: PS_OK (0) or a negative PS_E_* code.  Argument errors are
+ *    found on the host before any work is queued; nothing is launched then.
+ *    ps_last_error() gives a message for the last failing call of the thread.
+ *  - Errors found on the device (capacity exceeded, non-finite input, an
+ *    unsupported value) set bits of a status word kept in the workspace; read
+ *    it with ps_read_status after the stream work.  On overflow no vertex is
+ *    written past the capacity given.
+ *  - The workspace `ws` (size from ps_workspace_bytes) carries per-link setup
+ *    records from ps_count to ps_emit: pass the same ws, batch and params to
+ *    both.  Calls that share a workspace must not overlap.
+ */
+#ifndef PS_POLAR_STROKE_H
+#define PS_POLAR_STROKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Segment forms (Table "path segment forms"): line, quadratic Bezier,
+ * rational quadratic conic with middle weight w_B, cubic Bezier. */
+enum { PS_KIND_LINE = 0, PS_KIND_QUAD = 1, PS_KIND_CONIC = 2, PS_KIND_CUBIC = 3 };
+/* Join styles (Sec. "Easy Joins"): J = 0, 1, 2 or ceil(|delta|/q) steps. */
+enum { PS_JOIN_NONE = 0, PS_JOIN_BEVEL = 1, PS_JOIN_ROUND = 2, PS_JOIN_TRIANGLE = 3 };
+/* Cap styles (Secs. "Easy Caps", "Harder Caps"): J = 0, ceil(pi/q), 4, 2. */
+enum { PS_CAP_BUTT = 0, PS_CAP_ROUND = 1, PS_CAP_SQUARE = 2, PS_CAP_TRIANGLE = 3 };
+/* Arithmetic of the per-rib tangent-angle solve (Eq. angle2t):
+ *   FP32        single precision only;
+ *   FP32_FIXUP  single precision, re-solved in double where the FP32 answer
+ *               is ill-conditioned (default);
+ *   FP64        double precision for every rib. */
+enum { PS_PREC_FP32 = 0, PS_PREC_FP32_FIXUP = 1, PS_PREC_FP64 = 2 };
+
+enum {
+  PS_OK = 0,
+  PS_E_ARG = -1,          /* invalid argument (null pointer, size, q, ...)     */
+  PS_E_WORKSPACE = -2,    /* workspace smaller than ps_workspace_bytes        */
+  PS_E_HIP = -3,          /* a HIP runtime call failed                        */
+  PS_E_NOMEM = -4,        /* host allocation for a plan failed                */
+  PS_E_UNSUPPORTED = -5   /* option not implemented                           */
+};
+
+/* Device status bits (ps_status.flags). */
+enum {
+  PS_STATUS_OVERFLOW = 1u,       /* 2 * total ribs > vertex capacity: no emit  */
+  PS_STATUS_NONFINITE = 2u,      /* a control point, weight or width not finite */
+  PS_STATUS_BAD_VALUE = 4u,      /* unknown kind/style, w_B <= 0, width <= 0    */
+  PS_STATUS_DASH_OVERFLOW = 8u,  /* dash output exceeded its capacity           */
+  PS_STATUS_INTERVALS = 16u      /* a segment needed more than 5 intervals      */
+};
+
+/*
+ * A batch of paths (Sec. "Path Preliminaries": a path is a sequence of
+ * segments g_f(t), t in [0,1]; here successive segments of a path are taken
+ * to share end points).  Structure-of-arrays, device memory:
+ *   seg_begin [n_paths+1]  CSR: path p owns segments [seg_begin[p], seg_begin[p+1])
+ *   kind      [n_segs]     PS_KIND_*
+ *   cx, cy    [4*n_segs]   control point k of segment i at [k*n_segs + i];
+ *                          a line uses k<2, a quadratic or conic k<3
+ *   conic_w   [n_segs]     w_B of conics (> 0); ignored for other kinds
+ *   width     [n_paths]    stroke width w (> 0)
+ *   join, cap [n_paths]    PS_JOIN_*, PS_CAP_*
+ */
+typedef struct {
+  int32_t n_paths;
+  int32_t n_segs;
+  const int32_t* seg_begin;
+  const uint8_t* kind;
+  const float* cx;
+  const float* cy;
+  const float* conic_w;
+  const float* width;
+  const uint8_t* join;
+  const uint8_t* cap;
+} ps_batch;
+
+/*
+ * Parameters: q is the maximum tangent-angle step (Sec. "Uniform Tangent Angle
+ * Step Tessellation"), in radians, 1e-4 <= q <= pi.  precision is PS_PREC_*.
+ * Dashing (Sec. "Dashing"): n_dash on/off lengths (even count >= 2, all >= 0,
+ * positive sum) in the HOST array dash, starting at pattern position
+ * dash_phase >= 0 at arc length 0 of every path; n_dash = 0 disables it.
+ */
+typedef struct {
+  double q;
+  int32_t precision;
+  int32_t n_dash;
+  const double* dash;
+  double dash_phase;
+} ps_params;
+
+/* Status read back from a workspace. */
+typedef struct {
+  uint32_t flags;       /* PS_STATUS_* bits                                */
+  uint32_t reserved;
+  int64_t total_ribs;   /* ribs of the last ps_scan (2 vertices per rib)   */
+  int64_t fixups;       /* ribs re-solved in FP64 by the last ps_emit      */
+  int64_t dash_ribs;    /* ribs written by the last ps_dash                */
+  int64_t dash_count;   /* dashes written by the last ps_dash              */
+} ps_status;
+
+/*
+ * Number of link slots, 2*n_segs + n_paths (Sec. "Complete Algorithm": a path
+ * is divided into links, one per segment, cap and join).  Fixed slot layout:
+ * path p with segments [b,e) owns slots 2b+p (start cap), 2i+p+1 (segment i)
+ * and 2i+p+2 (the join after segment i, or the end cap after the last).  A
+ * zero-length segment has no ribs and joins are made across it.
+ */
+int64_t ps_num_links(const ps_batch* batch);
+
+/* Bytes of workspace needed for this batch and a vertex capacity (host only). */
+size_t ps_workspace_bytes(const ps_batch* batch, const ps_params* params,
+                          int64_t vertex_capacity);
+
+/*
+ * ps_count -- per-link setup and a-priori step counts (Eqs. p-value, Psi,
+ * continuous-delta, Delta_i, DeltaSigmaK; Sec. "Tessellation Approach for Caps
+ * and Joins").  Writes link_ribs[ps_num_links(batch)] (int32, device): the rib
+ * count of every link slot, N+1 for a segment of N steps and J+1 for a join or
+ * cap of J steps (0 when J = 0 or the segment has zero length).  The setup in
+ * FP64 (end gradients, reversal parameters, tangent angles, interval splits)
+ * is kept in ws for ps_emit.  Resets the status word.
+ */
+int ps_count(const ps_batch* batch, const ps_params* params, int32_t* link_ribs,
+             void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ps_scan -- exclusive prefix sum of link_ribs[n_links] (int32, device) into
+ * offsets[n_links+1] (int64, device); offsets[n_links] is the total rib count
+ * R, also stored in the status word.  The counts are known a priori (Sec.
+ * "The Polar Stroking Method"), so these are the output positions of every
+ * link.  Integer arithmetic: the result is exact.
+ */
+int ps_scan(const int32_t* link_ribs, int64_t n_links, int64_t* offsets, void* ws,
+            size_t ws_bytes, void* stream);
+
+/*
+ * ps_emit -- rib vertices (Eqs. func_t, func_N, RibVertices-N, RibVertices-P;
+ * Sec. "Complete Algorithm") and, when vs is not NULL, cumulative arc length
+ * (Eq. arc-length-approximation; Sec. "Cumulative Arc Length Texturing").
+ * Rib r of link l is rib j = r - offsets[l] of that link; its vertices go to
+ * vertex 2r (N = G - r_N n) and 2r+1 (P = G + r_P n), n = (-sin psi, cos psi):
+ * vx, vy [vertex_capacity] float.  vs [vertex_capacity] float receives the arc
+ * length at the rib for both of its vertices: a chord sum from 0 at the first
+ * rib of each path, constant across joins and caps, with a step whose t
+ * decreases adding nothing.  Consecutive ribs of a path form its quads.
+ * Requires ws from ps_count (same batch and params) and offsets from ps_scan.
+ * If 2*R > vertex_capacity nothing is written and PS_STATUS_OVERFLOW is set.
+ */
+int ps_emit(const ps_batch* batch, const ps_params* params, const int64_t* offsets,
+            float* vx, float* vy, float* vs, int64_t vertex_capacity, void* ws,
+            size_t ws_bytes, void* stream);
+
+/*
+ * ps_arclen -- the arc-length output of ps_emit alone: fills vs as ps_emit
+ * would, without writing vertices (same requirements as ps_emit).
+ */
+int ps_arclen(const ps_batch* batch, const ps_params* params, const int64_t* offsets,
+              float* vs, int64_t vertex_capacity, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ps_dash -- dashing by arc length (Sec. "Dashing").  Reads the rib stream of
+ * ps_emit (vx, vy, vs of vertex_capacity entries, the capacity the workspace
+ * was sized with; offsets from ps_scan) and writes the "on" pieces: dx, dy
+ * [2*rib_capacity] and ds [2*rib_capacity] in the same vertex layout, and
+ * dash_range [2*dash_capacity] int64 pairs [first rib, end rib) per dash.  A
+ * pattern boundary s_b inside a step (s_{j-1}, s_j] inserts a rib interpolated
+ * linearly in s; steps of zero length hold no boundary; the pattern restarts
+ * at every path.  Totals go to the status word; on overflow nothing past the
+ * capacities is written and PS_STATUS_DASH_OVERFLOW is set.
+ */
+int ps_dash(const ps_batch* batch, const ps_params* params, const int64_t* offsets,
+            const float* vx, const float* vy, const float* vs, int64_t vertex_capacity,
+            float* dx, float* dy, float* ds, int64_t* dash_range, int64_t rib_capacity,
+            int64_t dash_capacity, void* ws, size_t ws_bytes, void* stream);
+
+/* Copy the status word of ws to the host (synchronises `stream`). */
+int ps_read_status(const void* ws, ps_status* out, void* stream);
+
+/*
+ * Batched form: ps_plan_create picks the emit mapping for this batch (it runs
+ * the pipeline several times on `stream` and times it), then captures
+ * count -> scan -> emit (-> dash when params->n_dash > 0) into one hipGraph
+ * bound to these buffers.  ps_plan_launch replays it; ps_plan_destroy frees
+ * it.  link_ribs [ps_num_links], offsets [ps_num_links+1]; the dash buffers
+ * may be NULL when dashing is off.  The plan keeps all pointers given here.
+ */
+typedef struct ps_plan ps_plan;
+int ps_plan_create(const ps_batch* batch, const ps_params* params, int32_t* link_ribs,
+                   int64_t* offsets, float* vx, float* vy, float* vs, int64_t vertex_capacity,
+                   float* dx, float* dy, float* ds, int64_t* dash_range, int64_t dash_rib_capacity,
+                   int64_t dash_capacity, void* ws, size_t ws_bytes, void* stream,
+                   ps_plan** out);
+int ps_plan_launch(ps_plan* plan, void* stream);
+int ps_plan_destroy(ps_plan* plan);
+/* The emit mapping a plan chose: ribs per lane K and waves per workgroup. */
+int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_per_group);
+
+/*
+ * Emit tuning for the unplanned calls: K consecutive 64-rib iterations per
+ * wave tile (1..32) and waves per workgroup (1..16).  0 keeps the default.
+ */
+int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* ps_last_error(void);
+
+/* Library version string. */
+const char* ps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PS_POLAR_STROKE_H */

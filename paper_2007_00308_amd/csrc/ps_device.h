@@ -1,0 +1,311 @@
+// Device-side geometry of the polar-stroking tessellator (gfx950).
+//
+// Method: Kilgard, "Polar Stroking", ACM TOG 2020.  Every segment form is
+// written through one hodograph: g'(t) is a positive multiple of
+//     H(t) = (1-t)^2 E0 + 2(1-t)t E1 + t^2 E2
+// with (a = P1-P0, b = P2-P1, c = P3-P2)
+//     cubic      E0 = a,      E1 = b,          E2 = c        (factor 3)
+//     quadratic  E0 = a,      E1 = (P2-P0)/2,  E2 = b        (factor 2)
+//     conic      E0 = w a,    E1 = (P2-P0)/2,  E2 = w b      (factor 2/den^2)
+//     line       E0 = E1 = E2 = P1-P0                        (factor 1)
+// so the tangent-angle solve g'(t).N = 0 (Eq. angle2t) is the same quadratic
+// for every kind and a wavefront never diverges on the segment form there.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ps.h"
+
+namespace psd {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+constexpr double kCountEps = 1e-9;     // step count = ceil(|delta|/q - eps)
+constexpr double kUnwrapGuard = 1e-12; // |short-way turn| below this is never unwrapped
+constexpr int kMaxIv = 5;              // intervals per segment (collinear: 3 flat + 2 folds)
+
+enum Role : uint8_t { ROLE_SEG = 0, ROLE_JOIN = 1, ROLE_SCAP = 2, ROLE_ECAP = 3, ROLE_EMPTY = 255 };
+
+// Per-link setup record, written by the count kernel and read by emit.
+// 128 bytes, one per link slot.
+struct alignas(16) LinkRec {
+  uint8_t role;      // Role
+  uint8_t n_iv;      // intervals (segments); 1 for pivots
+  uint8_t kind;      // segment form (segments)
+  uint8_t cap;       // cap style (caps), for square-cap corner radii
+  int32_t path;
+  int32_t seg;       // segment the link belongs to (segments)
+  int32_t dsum[kMaxIv];   // cumulative steps Delta_Sigma(1..n_iv); pivots: dsum[0] = J
+  double p[kMaxIv - 1];   // interior interval boundaries p_1..p_{n_iv-1}
+  double psi[kMaxIv + 1]; // unwrapped Psi_0..Psi_{n_iv}; pivots psi[0], psi[1] = psi[0] + delta
+  float px, py;           // pivot point (joins and caps)
+  float pad[2];
+};
+static_assert(sizeof(LinkRec) == 128, "LinkRec must stay 128 bytes");
+
+// Device status word kept at the start of the workspace.
+struct DevStatus {
+  unsigned int flags;
+  unsigned int pad;
+  unsigned long long total_ribs;
+  unsigned long long fixups;
+  unsigned long long dash_ribs;
+  unsigned long long dash_count;
+  unsigned long long tile_counter;
+  unsigned long long dash_tile_counter;
+  unsigned long long reserved[1];
+};
+
+// ---------------------------------------------------------------------------
+// Segments in FP64 (inputs are FP32 and taken as exact)
+// ---------------------------------------------------------------------------
+struct Seg {
+  int kind;
+  int npts;
+  double x[4], y[4];
+  double w;
+};
+
+__device__ __forceinline__ int npts_of(int kind) {
+  return kind == PS_KIND_CUBIC ? 4 : (kind == PS_KIND_LINE ? 2 : 3);
+}
+
+__device__ inline Seg load_seg(const ps_batch& B, int i) {
+  Seg s;
+  s.kind = B.kind[i];
+  s.npts = npts_of(s.kind);
+  const int64_t S = B.n_segs;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < s.npts) {
+      s.x[k] = (double)B.cx[k * S + i];
+      s.y[k] = (double)B.cy[k * S + i];
+    } else {
+      s.x[k] = s.x[s.npts - 1];
+      s.y[k] = s.y[s.npts - 1];
+    }
+  }
+  s.w = (s.kind == PS_KIND_CONIC) ? (double)B.conic_w[i] : 1.0;
+  return s;
+}
+
+__device__ __forceinline__ bool seg_is_point(const Seg& s) {
+  bool same = true;
+  for (int k = 1; k < s.npts; ++k) same = same && s.x[k] == s.x[0] && s.y[k] == s.y[0];
+  return same;
+}
+
+__device__ __forceinline__ bool seg_finite(const Seg& s) {
+  bool ok = isfinite(s.w);
+  for (int k = 0; k < s.npts; ++k) ok = ok && isfinite(s.x[k]) && isfinite(s.y[k]);
+  return ok;
+}
+
+__device__ __forceinline__ double sgn_d(double v) { return (double)((v > 0) - (v < 0)); }
+
+// ===========================================================================
+// Setup arithmetic (count kernel).  FMA contraction is off so the step counts
+// come out of plain IEEE operations.
+// ===========================================================================
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ double crs(double ax, double ay, double bx, double by) {
+  return ax * by - ay * bx;
+}
+
+// Start / end gradient directions (unnormalised) by the fallbacks of the table
+// of segment forms: difference successive control points until nonzero.
+__device__ inline void start_dir(const Seg& s, double& dx, double& dy) {
+  dx = s.x[1] - s.x[0]; dy = s.y[1] - s.y[0];
+  if (s.kind == PS_KIND_CUBIC) {
+    if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+    if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[0]; dy = s.y[3] - s.y[0]; }
+  } else if (s.kind != PS_KIND_LINE) {
+    // quadratic, conic (w_B > 0 here, so sgn(w_B) = +1)
+    if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+  }
+}
+
+__device__ inline void end_dir(const Seg& s, double& dx, double& dy) {
+  const int e = s.npts - 1;
+  if (s.kind == PS_KIND_LINE) { dx = s.x[1] - s.x[0]; dy = s.y[1] - s.y[0]; return; }
+  dx = s.x[e] - s.x[e - 1]; dy = s.y[e] - s.y[e - 1];
+  if (s.kind == PS_KIND_CUBIC) {
+    if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[1]; dy = s.y[3] - s.y[1]; }
+    if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[0]; dy = s.y[3] - s.y[0]; }
+  } else {
+    if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+  }
+}
+
+__device__ __forceinline__ double unit_angle(double dx, double dy) {
+  // the direction of (dx,dy) after normalisation (Eq. Psi uses tan^-1 of the
+  // normalised gradient)
+  const double inv = 1.0 / sqrt(dx * dx + dy * dy);
+  return atan2(inv * dy, inv * dx);
+}
+
+// relative angle difference (-)
+__device__ __forceinline__ double adiff(double a, double b) {
+  double d = a - b;
+  if (d > kPi) return d - kTwoPi;
+  if (d < -kPi) return d + kTwoPi;
+  return d;
+}
+
+__device__ __forceinline__ int steps_of(double abs_turn, double q) {
+  double x = ceil(abs_turn / q - kCountEps);
+  return x < 1.0 ? 1 : (int)x;
+}
+
+// Simple real roots in (0,1) of A t^2 + B1 t + C, sorted, distinct.  A double
+// root is not returned (it is no sign change).
+__device__ inline int simple_roots01(double A, double B1, double C, double r[2]) {
+  int n = 0;
+  double t0 = 0, t1 = 0;
+  if (A == 0.0) {
+    if (B1 != 0.0) { t0 = -C / B1; n = 1; }
+  } else {
+    double disc = B1 * B1 - 4 * A * C;
+    if (disc > 0) {
+      double sq = sqrt(disc);
+      double qq = -0.5 * (B1 + (B1 >= 0 ? sq : -sq));
+      t0 = qq / A;
+      t1 = C / qq;
+      n = 2;
+    }
+  }
+  int m = 0;
+  if (n >= 1 && t0 > 0 && t0 < 1) r[m++] = t0;
+  if (n >= 2 && t1 > 0 && t1 < 1) r[m++] = t1;
+  if (m == 2) {
+    if (r[0] > r[1]) { double tmp = r[0]; r[0] = r[1]; r[1] = tmp; }
+    else if (r[0] == r[1]) m = 1;
+  }
+  return m;
+}
+
+// Cubic curvature sign: g' x g'' ~ (1-t)^2 X + (1-t) t Y + t^2 Z.
+__device__ __forceinline__ double cubic_curv(double X, double Y, double Z, double t) {
+  double u = 1 - t;
+  return u * u * X + u * t * Y + t * t * Z;
+}
+
+#pragma clang fp contract(on)
+
+// ===========================================================================
+// Hodograph and the tangent-angle solve (Eq. angle2t), FP32 or FP64
+// ===========================================================================
+template <typename F>
+struct Hodo {
+  F e0x, e0y, e1x, e1y, e2x, e2y;
+};
+
+template <typename F>
+__device__ __forceinline__ Hodo<F> hodo_of(int kind, const float* X, const float* Y, F w) {
+  Hodo<F> h;
+  const F ax = (F)X[1] - (F)X[0], ay = (F)Y[1] - (F)Y[0];
+  if (kind == PS_KIND_CUBIC) {
+    h.e0x = ax; h.e0y = ay;
+    h.e1x = (F)X[2] - (F)X[1]; h.e1y = (F)Y[2] - (F)Y[1];
+    h.e2x = (F)X[3] - (F)X[2]; h.e2y = (F)Y[3] - (F)Y[2];
+  } else if (kind == PS_KIND_LINE) {
+    h.e0x = h.e1x = h.e2x = ax; h.e0y = h.e1y = h.e2y = ay;
+  } else {
+    const F bx = (F)X[2] - (F)X[1], by = (F)Y[2] - (F)Y[1];
+    const F ww = (kind == PS_KIND_CONIC) ? w : (F)1;
+    h.e0x = ww * ax; h.e0y = ww * ay;
+    h.e1x = (F)0.5 * ((F)X[2] - (F)X[0]); h.e1y = (F)0.5 * ((F)Y[2] - (F)Y[0]);
+    h.e2x = ww * bx; h.e2y = ww * by;
+  }
+  return h;
+}
+
+template <typename F>
+__device__ __forceinline__ void hodo_eval(const Hodo<F>& h, F t, F& gx, F& gy) {
+  const F u = (F)1 - t;
+  const F a = u * u, b = (F)2 * u * t, c = t * t;
+  gx = a * h.e0x + b * h.e1x + c * h.e2x;
+  gy = a * h.e0y + b * h.e1y + c * h.e2y;
+}
+
+template <typename F>
+struct SolveOut {
+  F t;
+  bool found;   // a root inside [lo, hi] was taken (else the endpoint rule)
+  F hx, hy;     // H(t)
+  F dh;         // |d/dt (H(t).N)|
+};
+
+// Roots of (1-t)^2 al + 2(1-t)t be + t^2 ga = 0 inside [lo, hi]; the one whose
+// gradient points along T wins (a cusp root scores 0, a reversed one < 0).
+// With none inside, the paper's endpoint rule: the end with smaller |g'.N|.
+template <typename F>
+__device__ __forceinline__ SolveOut<F> solve_t(const Hodo<F>& h, F nx, F ny, F tx, F ty, F lo,
+                                               F hi) {
+  const F al = h.e0x * nx + h.e0y * ny;
+  const F be = h.e1x * nx + h.e1y * ny;
+  const F ga = h.e2x * nx + h.e2y * ny;
+  const F A = al - (F)2 * be + ga, B1 = (F)2 * (be - al), C = al;
+  F r0 = (F)-1, r1 = (F)-1;
+  if (A != (F)0) {
+    const F disc = B1 * B1 - (F)4 * A * C;
+    if (disc >= (F)0) {
+      const F sq = sqrt(disc);
+      const F qq = (F)-0.5 * (B1 + (B1 >= (F)0 ? sq : -sq));
+      r0 = qq / A;
+      r1 = (qq != (F)0) ? C / qq : r0;
+    }
+  } else if (B1 != (F)0) {
+    r0 = r1 = -C / B1;
+  }
+  SolveOut<F> o;
+  o.found = false;
+  o.t = hi;
+  F best = (F)0;
+  if (r0 >= lo && r0 <= hi) {
+    F gx, gy;
+    hodo_eval(h, r0, gx, gy);
+    best = gx * tx + gy * ty;
+    o.t = r0; o.found = true;
+  }
+  if (r1 >= lo && r1 <= hi && r1 != r0) {
+    F gx, gy;
+    hodo_eval(h, r1, gx, gy);
+    const F sc = gx * tx + gy * ty;
+    if (!o.found || sc > best) { o.t = r1; o.found = true; }
+  }
+  if (!o.found) {
+    const F ul = (F)1 - lo, uh = (F)1 - hi;
+    const F hl = ul * ul * al + (F)2 * ul * lo * be + lo * lo * ga;
+    const F hh = uh * uh * al + (F)2 * uh * hi * be + hi * hi * ga;
+    o.t = (fabs(hl) < fabs(hh)) ? lo : hi;
+  }
+  hodo_eval(h, o.t, o.hx, o.hy);
+  o.dh = fabs((F)2 * A * o.t + B1);
+  return o;
+}
+
+// g(t) in FP64: cubic Bernstein, or a rational quadratic (quadratic: w = 1,
+// line: middle point at the chord midpoint).
+__device__ __forceinline__ void eval_point(int kind, const float* X, const float* Y, double w,
+                                           double t, double& gx, double& gy) {
+  const double u = 1.0 - t;
+  if (kind == PS_KIND_CUBIC) {
+    const double b0 = u * u * u, b1 = 3.0 * u * u * t, b2 = 3.0 * u * t * t, b3 = t * t * t;
+    gx = b0 * X[0] + b1 * X[1] + b2 * X[2] + b3 * X[3];
+    gy = b0 * Y[0] + b1 * Y[1] + b2 * Y[2] + b3 * Y[3];
+  } else if (kind == PS_KIND_LINE) {
+    gx = u * X[0] + t * X[1];
+    gy = u * Y[0] + t * Y[1];
+  } else {
+    const double ww = (kind == PS_KIND_CONIC) ? w : 1.0;
+    const double b0 = u * u, b1 = 2.0 * u * t * ww, b2 = t * t;
+    const double den = b0 + b1 + b2;
+    gx = (b0 * X[0] + b1 * X[1] + b2 * X[2]) / den;
+    gy = (b0 * Y[0] + b1 * Y[1] + b2 * Y[2]) / den;
+  }
+}
+
+}  // namespace psd

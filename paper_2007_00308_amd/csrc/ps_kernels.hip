@@ -1,0 +1,1417 @@
+// Polar-stroking kernels for gfx950 (MI355X) and the host side of the C ABI.
+//
+// Method: Kilgard, "Polar Stroking", ACM TOG 2020.
+//   count  one thread per segment: FP64 interval setup, a-priori step counts,
+//          the join or end cap after the segment; one thread per path: the
+//          start cap
+//   scan   3-phase exclusive scan of int32 counts into int64 offsets
+//   emit   persistent wavefront tiles of 64*K - 1 ribs taken in ticket order;
+//          per rib: link lookup, tangent angle, t solve (FP32, FP32 with an
+//          FP64 fix-up, or FP64), FP64 point evaluation, coalesced stores;
+//          the chord-sum arc length is scanned inside the tile and carried
+//          between tiles by a decoupled look-back on fixed-point sums, so the
+//          result does not depend on scheduling
+//   dash   per-rib boundary counts, two scans, emission of the "on" pieces
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ps_device.h"
+
+using namespace psd;
+
+#define PS_VERSION "0.2.0"
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;                        // items per thread
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096 items per block
+constexpr int kMinTileRibs = 64 * 1 - 1;              // smallest emit tile (K = 1)
+constexpr double kFix = 16777216.0;                   // arc-length fixed point: 2^-24 px
+constexpr unsigned long long kValMask = (1ull << 61) - 1;
+constexpr int kMaxDash = 64;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ===========================================================================
+// Workspace
+// ===========================================================================
+struct WsLayout {
+  size_t status, rec, scan, tile_link, desc, dash_r, dash_d, dash_rpos, dash_dpos, dash_scan, total;
+  int64_t max_tiles, n_links, max_ribs, nb_links, nb_ribs;
+};
+
+// Offsets of the workspace parts.  Status, records and the link-scan scratch
+// come first and depend only on the batch, so ps_count and ps_scan (which are
+// not told the vertex capacity) carve the same prefix as ps_emit.
+WsLayout ws_layout(int64_t n_links, int64_t vertex_capacity, int n_dash) {
+  WsLayout w;
+  w.n_links = n_links;
+  w.max_ribs = vertex_capacity / 2;
+  w.max_tiles = w.max_ribs / kMinTileRibs + 2;
+  w.nb_links = (n_links + kScanTile - 1) / kScanTile + 1;
+  w.nb_ribs = (w.max_ribs + kScanTile - 1) / kScanTile + 1;
+  size_t o = 0;
+  w.status = o; o = align_up(o + 256, 256);
+  w.rec = o; o = align_up(o + (size_t)n_links * sizeof(LinkRec), 256);
+  w.scan = o; o = align_up(o + (size_t)(w.nb_links + 1) * 8, 256);
+  w.tile_link = o; o = align_up(o + (size_t)(w.max_tiles + 1) * 4, 256);
+  w.desc = o; o = align_up(o + (size_t)w.max_tiles * 8, 256);
+  w.dash_r = w.dash_d = w.dash_rpos = w.dash_dpos = w.dash_scan = o;
+  if (n_dash > 0) {
+    w.dash_r = o; o = align_up(o + (size_t)(w.max_ribs + 1) * 4, 256);
+    w.dash_d = o; o = align_up(o + (size_t)(w.max_ribs + 1) * 4, 256);
+    w.dash_rpos = o; o = align_up(o + (size_t)(w.max_ribs + 1) * 8, 256);
+    w.dash_dpos = o; o = align_up(o + (size_t)(w.max_ribs + 1) * 8, 256);
+    w.dash_scan = o; o = align_up(o + (size_t)(w.nb_ribs + 1) * 8, 256);
+  }
+  w.total = o;
+  return w;
+}
+
+// ===========================================================================
+// Count (Eqs. p-value, Psi, continuous-delta, Delta_i; joins and caps)
+// ===========================================================================
+struct CountArgs {
+  ps_batch B;
+  double q;
+  int32_t* link_ribs;
+  LinkRec* rec;
+  DevStatus* st;
+};
+
+__device__ __forceinline__ void set_flag(DevStatus* st, unsigned f) { atomicOr(&st->flags, f); }
+
+__device__ __forceinline__ int path_of_seg(const int32_t* seg_begin, int n_paths, int i) {
+  // largest p with seg_begin[p] <= i (the path that owns segment i)
+  int a = 0, b = n_paths - 1;
+  while (a < b) {
+    const int m = (a + b + 1) >> 1;
+    if (seg_begin[m] <= i) a = m; else b = m - 1;
+  }
+  return a;
+}
+
+// A segment contributes ribs if its values are finite and valid and it is
+// not a single point (a zero-length segment strokes nothing).
+__device__ inline bool seg_usable(const ps_batch& B, int i, DevStatus* st, bool report) {
+  const int k = B.kind[i];
+  if (k > PS_KIND_CUBIC) { if (report) set_flag(st, PS_STATUS_BAD_VALUE); return false; }
+  const Seg s = load_seg(B, i);
+  if (!seg_finite(s)) { if (report) set_flag(st, PS_STATUS_NONFINITE); return false; }
+  if (k == PS_KIND_CONIC && !(s.w > 0)) { if (report) set_flag(st, PS_STATUS_BAD_VALUE); return false; }
+  return !seg_is_point(s);
+}
+
+#pragma clang fp contract(off)
+
+// Intervals of one usable segment, written into rec.  Returns the step count N
+// (the segment has N+1 ribs), or -1 if it needs more than kMaxIv intervals.
+__device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, DevStatus* st) {
+  const Seg s = load_seg(B, i);
+  float X[4], Y[4];
+  const int64_t S = B.n_segs;
+  for (int k = 0; k < 4; ++k) {
+    const int kk = k < s.npts ? k : s.npts - 1;
+    X[k] = B.cx[kk * S + i];
+    Y[k] = B.cy[kk * S + i];
+  }
+  double sx, sy;
+  start_dir(s, sx, sy);
+  const double psi0 = unit_angle(sx, sy);
+  const double ax = s.x[1] - s.x[0], ay = s.y[1] - s.y[0];
+  const double bx = s.x[2] - s.x[1], by = s.y[2] - s.y[1];
+  const double cx = s.x[3] - s.x[2], cy = s.y[3] - s.y[2];
+  bool collinear;
+  double X3 = 0, Y3 = 0, Z3 = 0;
+  if (s.kind == PS_KIND_LINE) {
+    collinear = true;
+  } else if (s.kind == PS_KIND_CUBIC) {
+    X3 = crs(ax, ay, bx, by); Y3 = crs(ax, ay, cx, cy); Z3 = crs(bx, by, cx, cy);
+    collinear = (X3 == 0 && Y3 == 0 && Z3 == 0);
+  } else {
+    collinear = crs(ax, ay, bx, by) == 0;
+  }
+
+  int n = 0, N = 0;
+  double psi_run = psi0;
+  rec.psi[0] = psi0;
+  if (collinear) {
+    // flat pieces of one step, split by +pi pivots at the simple roots of
+    // g'(t).d where the segment reverses along its line (a cusp)
+    const double inv = 1.0 / sqrt(sx * sx + sy * sy);
+    const double dx = inv * sx, dy = inv * sy;
+    double A = 0, B1 = 0, C = 0;
+    if (s.kind == PS_KIND_CUBIC) {
+      const double al = ax * dx + ay * dy, be = bx * dx + by * dy, ga = cx * dx + cy * dy;
+      A = al - 2 * be + ga; B1 = 2 * (be - al); C = al;
+    } else if (s.kind == PS_KIND_QUAD) {
+      const double al = ax * dx + ay * dy, be = bx * dx + by * dy;
+      B1 = be - al; C = al;
+    } else if (s.kind == PS_KIND_CONIC) {
+      const double al = ax * dx + ay * dy, be = bx * dx + by * dy, w = s.w;
+      A = w * al - (al + be) + w * be; B1 = (al + be) - 2 * w * al; C = w * al;
+    }
+    double f[2];
+    const int nf = (s.kind == PS_KIND_LINE) ? 0 : simple_roots01(A, B1, C, f);
+    const int flat = steps_of(0.0, q), fold = steps_of(kPi, q);
+    for (int k = 0; k < nf; ++k) {
+      N += flat; rec.dsum[n] = N; rec.p[n] = f[k]; rec.psi[n + 1] = psi_run; ++n;
+      N += fold; rec.dsum[n] = N; rec.p[n] = f[k];
+      psi_run = psi_run + kPi; rec.psi[n + 1] = psi_run; ++n;
+    }
+    N += flat; rec.dsum[n] = N; rec.psi[n + 1] = psi_run; ++n;
+    rec.n_iv = (uint8_t)n;
+    return N;
+  }
+
+  // reversal parameters: simple roots of the cubic curvature sign
+  double pr[4];
+  int M = 1;
+  pr[0] = 0.0;
+  if (s.kind == PS_KIND_CUBIC) {
+    double r[2];
+    const int nr = simple_roots01(X3 - Y3 + Z3, Y3 - 2 * X3, X3, r);
+    for (int k = 0; k < nr; ++k) pr[M++] = r[k];
+  }
+  pr[M] = 1.0;
+  double Psi[4];
+  Psi[0] = psi0;
+  for (int k = 1; k < M; ++k) {
+    const double t = pr[k], u = 1 - t;
+    const double gx = u * u * ax + 2 * u * t * bx + t * t * cx;
+    const double gy = u * u * ay + 2 * u * t * by + t * t * cy;
+    Psi[k] = atan2(gy, gx);
+  }
+  double ex, ey;
+  end_dir(s, ex, ey);
+  Psi[M] = unit_angle(ex, ey);
+  const double crsQ = crs(ax, ay, bx, by);
+  for (int k = 1; k <= M; ++k) {
+    double d = adiff(Psi[k], Psi[k - 1]);   // the short way round
+    double sigma = 0;                       // rotation sense of the interval
+    if (s.kind == PS_KIND_CUBIC) {
+      const double fr[3] = {0.5, 0.25, 0.75};
+      for (int m = 0; m < 3 && sigma == 0; ++m)
+        sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + fr[m] * (pr[k] - pr[k - 1])));
+    } else {
+      sigma = sgn_d(crsQ);
+    }
+    if (sigma != 0 && d != 0 && sgn_d(d) != sigma && fabs(d) > kUnwrapGuard) d += kTwoPi * sigma;
+    if (fabs(d) >= kPi) {
+      if (n + 2 > kMaxIv) { set_flag(st, PS_STATUS_INTERVALS); rec.n_iv = 0; return -1; }
+      // split at the middle angle; its parameter from the FP64 solve
+      const double psi_s = psi_run + 0.5 * d;
+      const Hodo<double> h = hodo_of<double>(s.kind, X, Y, s.w);
+      double sn, cs;
+      sincos(psi_s, &sn, &cs);
+      const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, pr[k - 1], pr[k]);
+      const int half = steps_of(fabs(0.5 * d), q);
+      N += half; rec.dsum[n] = N; rec.p[n] = so.t; rec.psi[n + 1] = psi_s; ++n;
+      N += half; rec.dsum[n] = N; if (k < M) rec.p[n] = pr[k];
+      psi_run = psi_s + 0.5 * d; rec.psi[n + 1] = psi_run; ++n;
+    } else {
+      if (n + 1 > kMaxIv) { set_flag(st, PS_STATUS_INTERVALS); rec.n_iv = 0; return -1; }
+      N += steps_of(fabs(d), q); rec.dsum[n] = N; if (k < M) rec.p[n] = pr[k];
+      psi_run = psi_run + d; rec.psi[n + 1] = psi_run; ++n;
+    }
+  }
+  rec.n_iv = (uint8_t)n;
+  return N;
+}
+
+__device__ int join_steps(int style, double delta, double q) {
+  if (delta == 0.0) return 0;
+  if (style == PS_JOIN_BEVEL) return 1;
+  if (style == PS_JOIN_TRIANGLE) return 2;
+  if (style == PS_JOIN_ROUND) {
+    const double x = ceil(fabs(delta) / q - kCountEps);
+    return x < 0 ? 0 : (int)x;
+  }
+  return 0;
+}
+
+__device__ int cap_steps(int style, double q) {
+  if (style == PS_CAP_TRIANGLE) return 2;
+  if (style == PS_CAP_SQUARE) return 4;
+  if (style == PS_CAP_ROUND) return (int)ceil(kPi / q - kCountEps);
+  return 0;
+}
+
+__device__ inline double seg_start_angle(const ps_batch& B, int i) {
+  const Seg s = load_seg(B, i);
+  double dx, dy;
+  start_dir(s, dx, dy);
+  return unit_angle(dx, dy);
+}
+
+__device__ inline double seg_end_angle(const ps_batch& B, int i) {
+  const Seg s = load_seg(B, i);
+  double dx, dy;
+  end_dir(s, dx, dy);
+  return unit_angle(dx, dy);
+}
+
+#pragma clang fp contract(on)
+
+__device__ inline void clear_rec(LinkRec& r) {
+  r.role = ROLE_EMPTY; r.n_iv = 0; r.kind = 0; r.cap = 0; r.path = 0; r.seg = 0;
+  for (int k = 0; k < kMaxIv; ++k) r.dsum[k] = 0;
+  for (int k = 0; k < kMaxIv - 1; ++k) r.p[k] = 0;
+  for (int k = 0; k <= kMaxIv; ++k) r.psi[k] = 0;
+  r.px = r.py = 0; r.pad[0] = r.pad[1] = 0;
+}
+
+// A pivot link (join or cap) with J steps from psi0 through psi0 + delta.
+__device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slot, uint8_t role,
+                                   int path, int seg, double psi0, double delta, int J, float px,
+                                   float py, uint8_t cap) {
+  LinkRec r;
+  clear_rec(r);
+  r.role = J > 0 ? role : (uint8_t)ROLE_EMPTY;
+  r.n_iv = 1; r.cap = cap; r.path = path; r.seg = seg;
+  r.dsum[0] = J; r.psi[0] = psi0; r.psi[1] = psi0 + delta;
+  r.px = px; r.py = py;
+  rec[slot] = r;
+  link_ribs[slot] = J > 0 ? J + 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
+  const ps_batch& B = A.B;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int S = B.n_segs, P = B.n_paths;
+  if (tid < S) {
+    const int i = (int)tid;
+    const int p = path_of_seg(B.seg_begin, P, i);
+    const int e = B.seg_begin[p + 1];
+    const int64_t slot = 2 * (int64_t)i + p + 1;
+    const float wd = B.width[p];
+    const bool wok = isfinite(wd) && wd > 0;
+    const bool sok = (B.join[p] <= PS_JOIN_TRIANGLE) && (B.cap[p] <= PS_CAP_TRIANGLE);
+    if (!isfinite(wd)) set_flag(A.st, PS_STATUS_NONFINITE);
+    else if (!wok || !sok) set_flag(A.st, PS_STATUS_BAD_VALUE);
+    const bool usable = wok && sok && seg_usable(B, i, A.st, true);
+    LinkRec r;
+    clear_rec(r);
+    r.kind = B.kind[i]; r.path = p; r.seg = i;
+    int ribs = 0;
+    if (usable) {
+      const int N = segment_setup(B, i, A.q, r, A.st);
+      if (N > 0) { ribs = N + 1; r.role = ROLE_SEG; }
+    }
+    A.rec[slot] = r;
+    A.link_ribs[slot] = ribs;
+    // the join after this segment, or the end cap
+    const int64_t jslot = slot + 1;
+    if (!usable) {
+      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, p, i, 0, 0, 0, 0, 0, 0);
+      return;
+    }
+    const int n = npts_of(B.kind[i]);
+    const float ex = B.cx[(int64_t)(n - 1) * S + i], ey = B.cy[(int64_t)(n - 1) * S + i];
+    const double psi_e = seg_end_angle(B, i);
+    for (int k = i + 1; k < e; ++k) {
+      if (!seg_usable(B, k, A.st, false)) continue;
+      double d = adiff(seg_start_angle(B, k), psi_e);
+      if (d == -kPi) d = kPi;   // antiparallel: turn +pi
+      const int J = join_steps(B.join[p], d, A.q);
+      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, p, i, psi_e, d, J, ex, ey, 0);
+      return;
+    }
+    const int J = cap_steps(B.cap[p], A.q);
+    write_pivot(A.rec, A.link_ribs, jslot, ROLE_ECAP, p, i, psi_e, -kPi, J, ex, ey, B.cap[p]);
+    return;
+  }
+  if (tid < (int64_t)S + P) {
+    const int p = (int)(tid - S);
+    const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
+    const int64_t slot = 2 * (int64_t)b + p;
+    const float wd = B.width[p];
+    const bool ok = isfinite(wd) && wd > 0 && B.cap[p] <= PS_CAP_TRIANGLE &&
+                    B.join[p] <= PS_JOIN_TRIANGLE;
+    if (ok) {
+      for (int k = b; k < e; ++k) {
+        if (!seg_usable(B, k, A.st, false)) continue;
+        const double psi_s = seg_start_angle(B, k);
+        const int J = cap_steps(B.cap[p], A.q);
+        // start cap: from the reversed start tangent, +pi round to it
+        write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, p, k, psi_s - kPi, kPi, J, B.cx[k], B.cy[k],
+                    B.cap[p]);
+        return;
+      }
+    }
+    write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, p, b, 0, 0, 0, 0, 0, 0);
+  }
+}
+
+__global__ void reset_status_kernel(DevStatus* st) {
+  if (threadIdx.x == 0) {
+    st->flags = 0; st->total_ribs = 0; st->fixups = 0; st->dash_ribs = 0; st->dash_count = 0;
+    st->tile_counter = 0; st->dash_tile_counter = 0;
+  }
+}
+
+// ===========================================================================
+// Scan
+// ===========================================================================
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread across a block of kScanThreads.
+__device__ __forceinline__ long long block_excl_scan(long long v, long long* total) {
+  __shared__ long long wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long incl = wave_incl_scan(v);
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  long long base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    const long long s = wsum[k];
+    if (k < wv) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - v;
+}
+
+// The item count is n_max, or min(*n_dev, n_max) when n_dev is given (a
+// length produced on the device, such as the rib total).
+__device__ __forceinline__ int64_t scan_len(int64_t n_max, const int64_t* n_dev) {
+  if (!n_dev) return n_max;
+  const int64_t n = *n_dev;
+  return n < n_max ? n : n_max;
+}
+
+template <typename TIn>
+__global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const TIn* in, int64_t n_max,
+                                                                   const int64_t* n_dev,
+                                                                   long long* block_sums) {
+  const int64_t n = scan_len(n_max, n_dev);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    if (i < n) s += (long long)in[i];
+  }
+  long long tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) scan_blocks_kernel(long long* block_sums, int64_t nb) {
+  __shared__ long long wsum[16];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const long long v = i < nb ? block_sums[i] : 0;
+    const long long incl = wave_incl_scan(v);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    long long base = carry, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wv) base += wsum[k];
+      tot += wsum[k];
+    }
+    if (i < nb) block_sums[i] = base + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_sums[nb] = carry;
+}
+
+template <typename TIn>
+__global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const TIn* in, int64_t n_max,
+                                                                  const int64_t* n_dev,
+                                                                  const long long* block_sums,
+                                                                  int64_t* out, int64_t nb,
+                                                                  unsigned long long* total_out) {
+  const int64_t n = scan_len(n_max, n_dev);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out[n] = block_sums[nb];
+    if (total_out) *total_out = (unsigned long long)block_sums[nb];
+  }
+  if ((int64_t)blockIdx.x * kScanTile >= n) return;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  long long v[kScanItems];
+  long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    v[k] = i < n ? (long long)in[i] : 0;
+    s += v[k];
+  }
+  long long tot;
+  long long ex = block_excl_scan(s, &tot) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    if (i < n) out[i] = ex;
+    ex += v[k];
+  }
+}
+
+// ===========================================================================
+// Emit (Eqs. func_t, func_N, RibVertices-N/P, arc-length-approximation)
+// ===========================================================================
+struct EmitArgs {
+  ps_batch B;
+  const LinkRec* rec;
+  const int64_t* off;
+  int64_t n_links;
+  float* vx;
+  float* vy;
+  float* vs;
+  int64_t capacity;
+  const int32_t* tile_link;
+  unsigned long long* desc;
+  DevStatus* st;
+  int64_t max_tiles;
+};
+
+__device__ __forceinline__ int link_of(const int64_t* off, int lo, int hi, int64_t r) {
+  // largest l in [lo, hi] with off[l] <= r: the link (with ribs) holding rib r
+  while (lo < hi) {
+    const int m = (lo + hi + 1) >> 1;
+    if (off[m] <= r) lo = m; else hi = m - 1;
+  }
+  return lo;
+}
+
+// Tile T stores ribs [T*TS, (T+1)*TS) and also reads rib T*TS - 1.  Writes the
+// link holding each tile's first-read rib, clears the look-back descriptors
+// and the tile ticket.
+__global__ void __launch_bounds__(256) emit_prepare_kernel(const int64_t* off, int64_t n_links,
+                                                           int TS, int32_t* tile_link,
+                                                           unsigned long long* desc,
+                                                           DevStatus* st, int64_t capacity,
+                                                           int64_t max_tiles) {
+  const int64_t R = off[n_links];
+  const int64_t n_tiles = (R + TS - 1) / TS;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) st->tile_counter = 0;
+  if (2 * R > capacity || n_tiles > max_tiles) {
+    if (tid == 0) atomicOr(&st->flags, (unsigned)PS_STATUS_OVERFLOW);
+    return;
+  }
+  for (int64_t T = tid; T <= n_tiles; T += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rib = T * TS - 1;
+    if (rib < 0) rib = 0;
+    if (rib > R - 1) rib = R - 1;
+    tile_link[T] = R > 0 ? link_of(off, 0, (int)n_links - 1, rib) : 0;
+    if (T < n_tiles) desc[T] = 0ull;
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ F reduce_angle(double psi) {
+  return (F)(psi - kTwoPi * rint(psi * (1.0 / kTwoPi)));
+}
+
+struct RibOut {
+  double gx, gy, t;
+  float Nx, Ny, Px, Py;
+  bool chord_ok;
+  bool path_start;
+  bool fixed;
+};
+
+// One rib: Eq. func_t / func_N for segments (t from the tangent-angle solve),
+// a pivot for joins and caps, then Eqs. RibVertices-N/P.
+template <int PREC>
+__device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r, RibOut& o) {
+  const LinkRec* rp = A.rec + l;
+  const int j = (int)(r - A.off[l]);
+  const uint8_t role = rp->role;
+  const int path = rp->path;
+  const double rad = 0.5 * (double)A.B.width[path];
+  o.path_start = (r == A.off[2 * (int64_t)A.B.seg_begin[path] + path]);
+  o.fixed = false;
+  double nx = 0, ny = 1;   // n(psi) = (-sin psi, cos psi)
+  double rN = rad, rP = rad;
+  if (role == ROLE_SEG) {
+    const int seg = rp->seg;
+    const int kind = rp->kind;
+    const int n_iv = rp->n_iv;
+    const int64_t S = A.B.n_segs;
+    const int npts = npts_of(kind);
+    float X[4], Y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int kk = k < npts ? k : npts - 1;
+      X[k] = A.B.cx[kk * S + seg];
+      Y[k] = A.B.cy[kk * S + seg];
+    }
+    const float wf = (kind == PS_KIND_CONIC) ? A.B.conic_w[seg] : 1.0f;
+    // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]
+    int k = 1, d0 = 0;
+    while (k < n_iv && j > rp->dsum[k - 1]) { d0 = rp->dsum[k - 1]; ++k; }
+    const int d1 = rp->dsum[k - 1];
+    const double lo = (k == 1) ? 0.0 : rp->p[k - 2];
+    const double hi = (k == n_iv) ? 1.0 : rp->p[k - 1];
+    const double psa = rp->psi[k - 1], psb = rp->psi[k];
+    double t, psi;
+    bool have_n = false;
+    if (j == d0) { t = lo; psi = psa; }
+    else if (j == d1) { t = hi; psi = psb; }
+    else {
+      psi = psa + (psb - psa) * (double)(j - d0) / (double)(d1 - d0);
+      t = lo;
+      if (lo != hi) {
+        bool need64 = (PREC == PS_PREC_FP64);
+        if (PREC != PS_PREC_FP64) {
+          float sn, cs;
+          sincosf(reduce_angle<float>(psi), &sn, &cs);
+          const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
+          const SolveOut<float> so = solve_t<float>(h, -sn, cs, cs, sn, (float)lo, (float)hi);
+          t = (double)so.t;
+          nx = -(double)sn; ny = (double)cs;
+          have_n = true;
+          if (PREC == PS_PREC_FP32_FIXUP) {
+            // position error of the FP32 root: |g'| dt, with dt from the
+            // rounding of the angle and coefficients over the slope of g'.N
+            const float hn = sqrtf(so.hx * so.hx + so.hy * so.hy);
+            const float sum_e = fabsf(h.e0x) + fabsf(h.e0y) + 2.0f * (fabsf(h.e1x) + fabsf(h.e1y)) +
+                                fabsf(h.e2x) + fabsf(h.e2y);
+            float fk = 3.0f;
+            if (kind == PS_KIND_QUAD) fk = 2.0f;
+            else if (kind == PS_KIND_LINE) fk = 1.0f;
+            else if (kind == PS_KIND_CONIC) {
+              const float u = 1.0f - so.t;
+              const float den = u * u + 2.0f * u * so.t * wf + so.t * so.t;
+              fk = 2.0f / (den * den);
+            }
+            const float dt = (hn + sum_e) * 2.4e-7f / fmaxf(so.dh, 1e-30f) + 6e-8f;
+            const float est = fk * hn * dt;
+            need64 = !so.found || !(est < 4e-4f);
+          }
+        }
+        if (need64) {
+          double sn, cs;
+          sincos(psi, &sn, &cs);
+          const Hodo<double> h = hodo_of<double>(kind, X, Y, (double)wf);
+          const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, lo, hi);
+          t = so.t;
+          nx = -sn; ny = cs;
+          have_n = true;
+          o.fixed = (PREC == PS_PREC_FP32_FIXUP);
+        }
+      }
+    }
+    if (!have_n) {
+      if (PREC == PS_PREC_FP64) {
+        double sn, cs;
+        sincos(psi, &sn, &cs);
+        nx = -sn; ny = cs;
+      } else {
+        float s32, c32;
+        sincosf(reduce_angle<float>(psi), &s32, &c32);
+        nx = -(double)s32; ny = (double)c32;
+      }
+    }
+    eval_point(kind, X, Y, (double)wf, t, o.gx, o.gy);
+    o.t = t;
+    o.chord_ok = (j > 0);
+  } else {
+    // join or cap: a pivot at a fixed point (Sec. "Tessellation Approach for
+    // Caps and Joins"); only the side away from the turn keeps its radius
+    const int J = rp->dsum[0];
+    const double psa = rp->psi[0], psb = rp->psi[1];
+    const double psi = psa + (psb - psa) * (double)j / (double)J;
+    if (PREC == PS_PREC_FP64) {
+      double sn, cs;
+      sincos(psi, &sn, &cs);
+      nx = -sn; ny = cs;
+    } else {
+      float s32, c32;
+      sincosf(reduce_angle<float>(psi), &s32, &c32);
+      nx = -(double)s32; ny = (double)c32;
+    }
+    double rout = rad;
+    if ((role == ROLE_SCAP || role == ROLE_ECAP) && rp->cap == PS_CAP_SQUARE && (j == 1 || j == 3))
+      rout = rad * 1.41421356237309504880;
+    const bool left_turn = (psb - psa) > 0;
+    rN = left_turn ? rout : 0.0;
+    rP = left_turn ? 0.0 : rout;
+    o.gx = (double)rp->px; o.gy = (double)rp->py;
+    o.t = 0.0;
+    o.chord_ok = false;
+  }
+  o.Nx = (float)(o.gx - rN * nx); o.Ny = (float)(o.gy - rN * ny);
+  o.Px = (float)(o.gx + rP * nx); o.Py = (float)(o.gy + rP * ny);
+}
+
+// Persistent emit.  Tile T covers ribs [T*TS, (T+1)*TS), TS = 64*K - 1; lane
+// slot (k, lane) handles rib T*TS - 1 + 64k + lane, so slot (0,0) re-reads the
+// previous tile's last rib for the first chord and stores nothing.
+template <int K, int PREC, bool WXY, bool WS>
+__global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t L = A.n_links;
+  const int64_t R = A.off[L];
+  constexpr int TS = 64 * K - 1;
+  const int64_t n_tiles = (R + TS - 1) / TS;
+  if (2 * R > A.capacity || n_tiles > A.max_tiles) return;
+  unsigned long long fixups = 0;
+  for (;;) {
+    unsigned int tk = 0;
+    if (lane == 0) tk = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
+    const int64_t tile = (int64_t)__shfl(tk, 0, 64);
+    if (tile >= n_tiles) break;
+    const int64_t r0 = tile * TS;
+    const int lhi = A.tile_link[tile + 1];
+    int l = A.tile_link[tile];
+    double run = 0.0;           // chord sum since the tile start or its last path start
+    bool seen_start = false;
+    double cgx = 0, cgy = 0, ct = 0;   // the previous iteration's last rib
+    double srel[K];
+    unsigned int need_prefix = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t r = r0 - 1 + 64 * k + lane;
+      const bool valid = (r >= 0) && (r < R);
+      const bool mine = valid && (r >= r0);
+      RibOut o;
+      o.gx = o.gy = o.t = 0; o.chord_ok = false; o.path_start = false; o.fixed = false;
+      if (valid) {
+        l = link_of(A.off, l, lhi, r);
+        compute_rib<PREC>(A, l, r, o);
+        if (WXY && mine) {
+          *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
+          *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
+        }
+        fixups += o.fixed ? 1 : 0;
+      }
+      // chord from the previous rib; zero when t decreases
+      double pgx = __shfl_up(o.gx, 1, 64), pgy = __shfl_up(o.gy, 1, 64), pt = __shfl_up(o.t, 1, 64);
+      if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
+      double c = 0.0;
+      if (mine && o.chord_ok && o.t >= pt) {
+        const double dx = o.gx - pgx, dy = o.gy - pgy;
+        c = sqrt(dx * dx + dy * dy);
+      }
+      int f = (mine && o.path_start) ? 1 : 0;
+      // segmented inclusive scan across the wave: a path start resets the sum
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const double cu = __shfl_up(c, d, 64);
+        const int fu = __shfl_up(f, d, 64);
+        if (lane >= d) {
+          c = f ? c : c + cu;
+          f = f | fu;
+        }
+      }
+      srel[k] = f ? c : run + c;
+      if (!(f || seen_start)) need_prefix |= (1u << k);
+      const double c63 = __shfl(c, 63, 64);
+      const int f63 = __shfl(f, 63, 64);
+      run = f63 ? c63 : run + c63;
+      seen_start = seen_start || (f63 != 0);
+      cgx = __shfl(o.gx, 63, 64); cgy = __shfl(o.gy, 63, 64); ct = __shfl(o.t, 63, 64);
+    }
+    if (WS) {
+      // decoupled look-back over tile sums in fixed point: integer additions
+      // are associative, so every run gives the same bits
+      const unsigned long long agg = (unsigned long long)llrint(run * kFix) & kValMask;
+      unsigned long long prefix = 0;
+      if (lane == 0) {
+        if (seen_start) {
+          __hip_atomic_store(&A.desc[tile], (2ull << 62) | agg, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          __hip_atomic_store(&A.desc[tile], (1ull << 62) | agg, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          int64_t T = tile - 1;
+          while (T >= 0) {
+            const unsigned long long w =
+                __hip_atomic_load(&A.desc[T], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned stt = (unsigned)(w >> 62);
+            if (stt == 0) { __builtin_amdgcn_s_sleep(2); continue; }
+            prefix += w & kValMask;
+            if (stt == 2 || ((w >> 61) & 1ull)) break;
+            --T;
+          }
+          __hip_atomic_store(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask),
+                             __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      const unsigned int plo = __shfl((unsigned int)(prefix & 0xffffffffu), 0, 64);
+      const unsigned int phi = __shfl((unsigned int)(prefix >> 32), 0, 64);
+      const double pre = (double)(((unsigned long long)phi << 32) | plo) * (1.0 / kFix);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int64_t r = r0 - 1 + 64 * k + lane;
+        if (r >= r0 && r < R) {
+          const float s = (float)(((need_prefix >> k) & 1u) ? pre + srel[k] : srel[k]);
+          *reinterpret_cast<float2*>(A.vs + 2 * r) = make_float2(s, s);
+        }
+      }
+    }
+  }
+  if (PREC == PS_PREC_FP32_FIXUP) {
+    unsigned long long v = fixups;
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0 && v) atomicAdd(&A.st->fixups, v);
+  }
+}
+
+// ===========================================================================
+// Dash (Sec. "Dashing")
+// ===========================================================================
+struct DashArgs {
+  const int64_t* off;        // link offsets [n_links+1]
+  int64_t n_links;
+  const int32_t* seg_begin;
+  int n_paths;
+  const float* vx;
+  const float* vy;
+  const float* vs;
+  int32_t* cnt_r;            // per rib: ribs written
+  int32_t* cnt_d;            // per rib: dashes started
+  const int64_t* rib_pos;    // exclusive scans of the two
+  const int64_t* dash_pos;
+  float* dx;
+  float* dy;
+  float* ds;
+  int64_t* range;
+  int64_t rib_cap;
+  int64_t dash_cap;
+  DevStatus* st;
+  double phase;
+  int n_pat;
+  double cum[kMaxDash + 1];  // cumulative pattern, cum[n_pat] = period
+};
+
+__device__ __forceinline__ int64_t path_first_rib(const DashArgs& A, int p) {
+  return A.off[2 * (int64_t)A.seg_begin[p] + p];
+}
+
+__device__ __forceinline__ int rib_path(const DashArgs& A, int64_t r) {
+  // largest p whose first rib is <= r
+  int a = 0, b = A.n_paths - 1;
+  while (a < b) {
+    const int m = (a + b + 1) >> 1;
+    if (path_first_rib(A, m) <= r) a = m; else b = m - 1;
+  }
+  return a;
+}
+
+// pattern state at position u: "on" when u mod period lies in an even entry
+__device__ __forceinline__ bool dash_on(const DashArgs& A, double u) {
+  const double per = A.cum[A.n_pat];
+  const double m = floor(u / per);
+  const double x = u - m * per;
+  int idx = 0;
+  while (idx + 1 < A.n_pat && A.cum[idx + 1] <= x) ++idx;
+  return (idx & 1) == 0;
+}
+
+// visit the boundaries u_b = m*period + cum[i] with u0 < u_b <= u1 in order
+// Steps longer than kMaxDashPeriods periods, or non-finite, are left undashed
+// (and flagged) so the loop is always bounded.
+constexpr double kMaxDashPeriods = 1048576.0;
+
+template <class Fn>
+__device__ __forceinline__ void dash_boundaries(const DashArgs& A, double u0, double u1, Fn fn) {
+  if (!(u1 > u0)) return;
+  const double per = A.cum[A.n_pat];
+  if (!isfinite(u0) || !isfinite(u1) || (u1 - u0) > kMaxDashPeriods * per) {
+    atomicOr(&A.st->flags, (unsigned)PS_STATUS_DASH_OVERFLOW);
+    return;
+  }
+  for (double m = floor(u0 / per);; m += 1.0) {
+    for (int i = 0; i < A.n_pat; ++i) {
+      const double ub = m * per + A.cum[i];
+      if (ub <= u0) continue;
+      if (ub > u1) return;
+      fn(ub);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) dash_count_kernel(DashArgs A) {
+  const int64_t R = A.off[A.n_links];
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int p = rib_path(A, r);
+    const double u1 = (double)A.vs[2 * r] + A.phase;
+    int ribs = 0, starts = 0;
+    if (r == path_first_rib(A, p)) {
+      if (dash_on(A, u1)) { ribs = 1; starts = 1; }
+    } else {
+      const double u0 = (double)A.vs[2 * (r - 1)] + A.phase;
+      bool on = dash_on(A, u0);
+      dash_boundaries(A, u0, u1, [&](double) {
+        ++ribs;           // every boundary rib is written
+        on = !on;
+        if (on) ++starts; // a boundary that turns the pattern on starts a dash
+      });
+      if (on) ++ribs;
+    }
+    A.cnt_r[r] = ribs;
+    A.cnt_d[r] = starts;
+  }
+}
+
+__global__ void __launch_bounds__(256) dash_emit_kernel(DashArgs A) {
+  const int64_t R = A.off[A.n_links];
+  const int64_t tot_r = A.rib_pos[R], tot_d = A.dash_pos[R];
+  const int64_t tid0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool over = tot_r > A.rib_cap || tot_d > A.dash_cap;
+  if (tid0 == 0) {
+    A.st->dash_ribs = (unsigned long long)tot_r;
+    A.st->dash_count = (unsigned long long)tot_d;
+    if (over) atomicOr(&A.st->flags, (unsigned)PS_STATUS_DASH_OVERFLOW);
+  }
+  if (over) return;
+  for (int64_t r = tid0; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+    const int p = rib_path(A, r);
+    int64_t o = A.rib_pos[r];
+    int64_t dn = A.dash_pos[r];   // next dash index to open; dn-1 is the one running
+    const float s1 = A.vs[2 * r];
+    const double u1 = (double)s1 + A.phase;
+    auto put = [&](float nx, float ny, float px, float py, float s) {
+      A.dx[2 * o] = nx; A.dy[2 * o] = ny; A.dx[2 * o + 1] = px; A.dy[2 * o + 1] = py;
+      A.ds[2 * o] = s; A.ds[2 * o + 1] = s;
+      ++o;
+    };
+    bool on;
+    if (r == path_first_rib(A, p)) {
+      on = dash_on(A, u1);
+      if (on) { A.range[2 * dn] = o; ++dn; put(A.vx[2 * r], A.vy[2 * r], A.vx[2 * r + 1], A.vy[2 * r + 1], s1); }
+    } else {
+      const double u0 = (double)A.vs[2 * (r - 1)] + A.phase;
+      on = dash_on(A, u0);
+      const double nx0 = A.vx[2 * (r - 1)], ny0 = A.vy[2 * (r - 1)];
+      const double px0 = A.vx[2 * (r - 1) + 1], py0 = A.vy[2 * (r - 1) + 1];
+      const double nx1 = A.vx[2 * r], ny1 = A.vy[2 * r], px1 = A.vx[2 * r + 1], py1 = A.vy[2 * r + 1];
+      dash_boundaries(A, u0, u1, [&](double ub) {
+        const double lam = (ub - u0) / (u1 - u0);
+        const float bnx = (float)(nx0 + lam * (nx1 - nx0)), bny = (float)(ny0 + lam * (ny1 - ny0));
+        const float bpx = (float)(px0 + lam * (px1 - px0)), bpy = (float)(py0 + lam * (py1 - py0));
+        const float sb = (float)(ub - A.phase);
+        if (on) {
+          put(bnx, bny, bpx, bpy, sb);
+          A.range[2 * (dn - 1) + 1] = o;   // the running dash ends here
+          on = false;
+        } else {
+          A.range[2 * dn] = o;             // a new dash starts here
+          ++dn;
+          put(bnx, bny, bpx, bpy, sb);
+          on = true;
+        }
+      });
+      if (on) put(A.vx[2 * r], A.vy[2 * r], A.vx[2 * r + 1], A.vy[2 * r + 1], s1);
+    }
+    // a dash still on at the last rib of its path ends there
+    const int64_t path_end = A.off[2 * (int64_t)A.seg_begin[p + 1] + p + 1];
+    if (on && r + 1 == path_end) A.range[2 * (dn - 1) + 1] = o;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define PS_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(PS_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+struct EmitConfig {
+  int K = 8;
+  int waves = 4;
+};
+EmitConfig g_cfg;
+std::mutex g_mu;
+
+int64_t n_links_of(const ps_batch* b) { return 2 * (int64_t)b->n_segs + b->n_paths; }
+
+int check_batch(const ps_batch* b) {
+  if (!b) return fail(PS_E_ARG, "batch is NULL");
+  if (b->n_paths < 0 || b->n_segs < 0) return fail(PS_E_ARG, "negative path or segment count");
+  if (n_links_of(b) >= (int64_t)INT32_MAX)
+    return fail(PS_E_ARG, "too many links (2*n_segs + n_paths must be < 2^31)");
+  if (!b->seg_begin) return fail(PS_E_ARG, "seg_begin is NULL");
+  if (b->n_segs > 0 && b->n_paths == 0) return fail(PS_E_ARG, "segments without paths");
+  if (b->n_segs > 0 && (!b->kind || !b->cx || !b->cy || !b->conic_w))
+    return fail(PS_E_ARG, "segment arrays must not be NULL");
+  if (b->n_paths > 0 && (!b->width || !b->join || !b->cap))
+    return fail(PS_E_ARG, "path arrays must not be NULL");
+  return PS_OK;
+}
+
+int check_params(const ps_params* p) {
+  if (!p) return fail(PS_E_ARG, "params is NULL");
+  if (!(p->q >= 1e-4 && p->q <= M_PI)) return fail(PS_E_ARG, "q must be in [1e-4, pi] (got %g)", p->q);
+  if (p->precision < PS_PREC_FP32 || p->precision > PS_PREC_FP64)
+    return fail(PS_E_ARG, "unknown precision mode %d", p->precision);
+  if (p->n_dash != 0) {
+    if (p->n_dash < 2 || (p->n_dash & 1) || p->n_dash > kMaxDash)
+      return fail(PS_E_ARG, "dash pattern needs an even count in [2, %d]", kMaxDash);
+    if (!p->dash) return fail(PS_E_ARG, "dash pattern is NULL");
+    double sum = 0;
+    for (int i = 0; i < p->n_dash; ++i) {
+      if (!(p->dash[i] >= 0) || !std::isfinite(p->dash[i]))
+        return fail(PS_E_ARG, "dash entries must be finite and >= 0");
+      sum += p->dash[i];
+    }
+    if (!(sum > 0)) return fail(PS_E_ARG, "dash pattern sums to zero");
+    if (!(p->dash_phase >= 0) || !std::isfinite(p->dash_phase))
+      return fail(PS_E_ARG, "dash phase must be finite and >= 0");
+  }
+  return PS_OK;
+}
+
+int check_ws(const void* ws, size_t have, size_t need) {
+  if (!ws) return fail(PS_E_ARG, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PS_E_ARG, "workspace must be 256-byte aligned");
+  if (have < need) return fail(PS_E_WORKSPACE, "workspace has %zu bytes, needs %zu", have, need);
+  return PS_OK;
+}
+
+struct WsView {
+  DevStatus* st;
+  LinkRec* rec;
+  long long* scan;
+  int32_t* tile_link;
+  unsigned long long* desc;
+  int32_t* dash_r;
+  int32_t* dash_d;
+  int64_t* dash_rpos;
+  int64_t* dash_dpos;
+  long long* dash_scan;
+};
+
+WsView ws_view(void* ws, const WsLayout& w) {
+  char* b = (char*)ws;
+  WsView v;
+  v.st = (DevStatus*)(b + w.status);
+  v.rec = (LinkRec*)(b + w.rec);
+  v.scan = (long long*)(b + w.scan);
+  v.tile_link = (int32_t*)(b + w.tile_link);
+  v.desc = (unsigned long long*)(b + w.desc);
+  v.dash_r = (int32_t*)(b + w.dash_r);
+  v.dash_d = (int32_t*)(b + w.dash_d);
+  v.dash_rpos = (int64_t*)(b + w.dash_rpos);
+  v.dash_dpos = (int64_t*)(b + w.dash_dpos);
+  v.dash_scan = (long long*)(b + w.dash_scan);
+  return v;
+}
+
+int grid_for(int64_t n, int threads) {
+  const int64_t g = (n + threads - 1) / threads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
+}
+
+int num_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+      cus = p.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+int do_scan_i32(const int32_t* in, int64_t n_max, const int64_t* n_dev, int64_t* out,
+                long long* scratch, unsigned long long* total, hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(1, (n_max + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(scan_reduce_kernel<int32_t>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
+                     n_max, n_dev, scratch);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, scratch, nb);
+  hipLaunchKernelGGL(scan_apply_kernel<int32_t>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
+                     n_max, n_dev, (const long long*)scratch, out, nb, total);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
+template <int K, int PREC, bool WXY, bool WS>
+void emit_launcher(EmitArgs a, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL((emit_kernel<K, PREC, WXY, WS>), dim3(grid), dim3(block), 0, s, a);
+}
+
+using EmitLaunch = void (*)(EmitArgs, int, int, hipStream_t);
+
+template <int PREC, bool WXY, bool WS>
+EmitLaunch pick_k(int K) {
+  switch (K) {
+    case 2: return emit_launcher<2, PREC, WXY, WS>;
+    case 4: return emit_launcher<4, PREC, WXY, WS>;
+    case 8: return emit_launcher<8, PREC, WXY, WS>;
+    case 16: return emit_launcher<16, PREC, WXY, WS>;
+    default: return nullptr;
+  }
+}
+
+template <bool WXY, bool WS>
+EmitLaunch pick_prec(int prec, int K) {
+  switch (prec) {
+    case PS_PREC_FP32: return pick_k<PS_PREC_FP32, WXY, WS>(K);
+    case PS_PREC_FP32_FIXUP: return pick_k<PS_PREC_FP32_FIXUP, WXY, WS>(K);
+    default: return pick_k<PS_PREC_FP64, WXY, WS>(K);
+  }
+}
+
+EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws) {
+  if (wxy && ws) return pick_prec<true, true>(prec, K);
+  if (wxy) return pick_prec<true, false>(prec, K);
+  return pick_prec<false, true>(prec, K);
+}
+
+bool valid_k(int K) { return K == 2 || K == 4 || K == 8 || K == 16; }
+
+int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, const WsView& v,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, v.st);
+  const int64_t n = (int64_t)b->n_segs + b->n_paths;
+  if (n > 0) {
+    CountArgs a{*b, p->q, link_ribs, v.rec, v.st};
+    hipLaunchKernelGGL(count_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, a);
+  }
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
+int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float* vx, float* vy,
+                float* vs, int64_t cap, const WsView& v, const WsLayout& w, int K, int waves,
+                hipStream_t s) {
+  const int64_t L = n_links_of(b);
+  const int TS = 64 * K - 1;
+  EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr);
+  if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", K);
+  hipLaunchKernelGGL(emit_prepare_kernel, dim3(256), dim3(256), 0, s, off, L, TS, v.tile_link,
+                     v.desc, v.st, cap, w.max_tiles);
+  EmitArgs a;
+  a.B = *b; a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
+  a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
+  a.max_tiles = w.max_tiles;
+  const int block = 64 * waves;
+  const int grid = num_cus() * std::max(1, 16 / waves);
+  fn(a, grid, block, s);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
+int launch_dash(const ps_batch* b, const ps_params* p, const int64_t* off, const float* vx,
+                const float* vy, const float* vs, float* dx, float* dy, float* ds, int64_t* range,
+                int64_t rib_cap, int64_t dash_cap, const WsView& v, const WsLayout& w,
+                hipStream_t s) {
+  DashArgs a;
+  a.off = off; a.n_links = n_links_of(b); a.seg_begin = b->seg_begin; a.n_paths = b->n_paths;
+  a.vx = vx; a.vy = vy; a.vs = vs; a.cnt_r = v.dash_r; a.cnt_d = v.dash_d;
+  a.rib_pos = v.dash_rpos; a.dash_pos = v.dash_dpos;
+  a.dx = dx; a.dy = dy; a.ds = ds; a.range = range; a.rib_cap = rib_cap; a.dash_cap = dash_cap;
+  a.st = v.st; a.phase = p->dash_phase; a.n_pat = p->n_dash;
+  a.cum[0] = 0;
+  for (int i = 0; i < p->n_dash; ++i) a.cum[i + 1] = a.cum[i] + p->dash[i];
+  for (int i = p->n_dash + 1; i <= kMaxDash; ++i) a.cum[i] = 0;
+  const int grid = num_cus() * 8;
+  const int64_t* R_dev = off + a.n_links;
+  hipLaunchKernelGGL(dash_count_kernel, dim3(grid), dim3(256), 0, s, a);
+  int rc;
+  if ((rc = do_scan_i32(v.dash_r, w.max_ribs, R_dev, v.dash_rpos, v.dash_scan, nullptr, s))) return rc;
+  if ((rc = do_scan_i32(v.dash_d, w.max_ribs, R_dev, v.dash_dpos, v.dash_scan, nullptr, s))) return rc;
+  hipLaunchKernelGGL(dash_emit_kernel, dim3(grid), dim3(256), 0, s, a);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
+EmitConfig current_cfg() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_cfg;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Plan: autotuned emit mapping + one hipGraph for the whole chain
+// ===========================================================================
+struct ps_plan {
+  ps_batch b;
+  ps_params p;
+  std::vector<double> dash;
+  int32_t* link_ribs;
+  int64_t* off;
+  float *vx, *vy, *vs;
+  int64_t cap;
+  float *dx, *dy, *ds;
+  int64_t* range;
+  int64_t dash_rib_cap, dash_cap;
+  void* ws;
+  WsLayout w;
+  int K, waves;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace {
+
+int enqueue_chain(ps_plan* P, hipStream_t s) {
+  const WsView v = ws_view(P->ws, P->w);
+  int rc;
+  if ((rc = launch_count(&P->b, &P->p, P->link_ribs, v, s))) return rc;
+  if ((rc = do_scan_i32(P->link_ribs, n_links_of(&P->b), nullptr, P->off, v.scan, &v.st->total_ribs, s)))
+    return rc;
+  if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->K, P->waves, s)))
+    return rc;
+  if (P->p.n_dash > 0) {
+    if ((rc = launch_dash(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->dx, P->dy, P->ds, P->range,
+                          P->dash_rib_cap, P->dash_cap, v, P->w, s)))
+      return rc;
+  }
+  return PS_OK;
+}
+
+int time_emit(ps_plan* P, int K, int waves, hipStream_t s, float* ms) {
+  const WsView v = ws_view(P->ws, P->w);
+  hipEvent_t e0, e1;
+  PS_HIP(hipEventCreate(&e0));
+  PS_HIP(hipEventCreate(&e1));
+  int rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, s);
+  float best = 1e30f;
+  for (int rep = 0; rep < 3 && rc == PS_OK; ++rep) {
+    (void)hipEventRecord(e0, s);
+    rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, s);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float t = 0;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    best = std::min(best, t);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = best;
+  return rc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Public C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ps_version(void) { return PS_VERSION; }
+
+const char* ps_last_error(void) { return g_err.c_str(); }
+
+int64_t ps_num_links(const ps_batch* b) {
+  if (check_batch(b) != PS_OK) return -1;
+  return n_links_of(b);
+}
+
+size_t ps_workspace_bytes(const ps_batch* b, const ps_params* p, int64_t vertex_capacity) {
+  if (check_batch(b) != PS_OK) return 0;
+  const int nd = p ? p->n_dash : 0;
+  return ws_layout(n_links_of(b), std::max<int64_t>(0, vertex_capacity), nd).total;
+}
+
+int ps_set_emit_config(int32_t K, int32_t waves) {
+  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 2, 4, 8 or 16");
+  if (waves < 0 || waves > 16) return fail(PS_E_ARG, "waves_per_group must be in [1,16]");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (K) g_cfg.K = K;
+  if (waves) g_cfg.waves = waves;
+  return PS_OK;
+}
+
+int ps_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, void* ws, size_t ws_bytes,
+             void* stream) {
+  int rc;
+  if ((rc = check_batch(b)) || (rc = check_params(p))) return rc;
+  if (!link_ribs && n_links_of(b) > 0) return fail(PS_E_ARG, "link_ribs is NULL");
+  const WsLayout w = ws_layout(n_links_of(b), 0, 0);
+  if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+  return launch_count(b, p, link_ribs, ws_view(ws, w), (hipStream_t)stream);
+}
+
+int ps_scan(const int32_t* link_ribs, int64_t n_links, int64_t* offsets, void* ws, size_t ws_bytes,
+            void* stream) {
+  if (n_links < 0 || n_links >= (int64_t)INT32_MAX) return fail(PS_E_ARG, "bad n_links");
+  if (!offsets || (n_links > 0 && !link_ribs)) return fail(PS_E_ARG, "NULL array");
+  const WsLayout w = ws_layout(n_links, 0, 0);
+  int rc;
+  if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+  const WsView v = ws_view(ws, w);
+  return do_scan_i32(link_ribs, n_links, nullptr, offsets, v.scan, &v.st->total_ribs, (hipStream_t)stream);
+}
+
+int ps_emit(const ps_batch* b, const ps_params* p, const int64_t* offsets, float* vx, float* vy,
+            float* vs, int64_t cap, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_batch(b)) || (rc = check_params(p))) return rc;
+  if (!offsets || !vx || !vy) return fail(PS_E_ARG, "NULL array");
+  if (cap < 0) return fail(PS_E_ARG, "negative capacity");
+  const WsLayout w = ws_layout(n_links_of(b), cap, 0);
+  if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+  const EmitConfig c = current_cfg();
+  return launch_emit(b, p, offsets, vx, vy, vs, cap, ws_view(ws, w), w, c.K, c.waves, (hipStream_t)stream);
+}
+
+int ps_arclen(const ps_batch* b, const ps_params* p, const int64_t* offsets, float* vs, int64_t cap,
+              void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_batch(b)) || (rc = check_params(p))) return rc;
+  if (!offsets || !vs) return fail(PS_E_ARG, "NULL array");
+  if (cap < 0) return fail(PS_E_ARG, "negative capacity");
+  const WsLayout w = ws_layout(n_links_of(b), cap, 0);
+  if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+  const EmitConfig c = current_cfg();
+  return launch_emit(b, p, offsets, nullptr, nullptr, vs, cap, ws_view(ws, w), w, c.K, c.waves,
+                     (hipStream_t)stream);
+}
+
+int ps_dash(const ps_batch* b, const ps_params* p, const int64_t* offsets, const float* vx,
+            const float* vy, const float* vs, int64_t vcap, float* dx, float* dy, float* ds,
+            int64_t* range, int64_t rib_cap, int64_t dash_cap, void* ws, size_t ws_bytes,
+            void* stream) {
+  int rc;
+  if ((rc = check_batch(b)) || (rc = check_params(p))) return rc;
+  if (p->n_dash == 0) return fail(PS_E_ARG, "ps_dash needs a dash pattern");
+  if (!offsets || !vx || !vy || !vs || !dx || !dy || !ds || !range) return fail(PS_E_ARG, "NULL array");
+  if (vcap < 0 || rib_cap < 0 || dash_cap < 0) return fail(PS_E_ARG, "negative capacity");
+  const WsLayout w = ws_layout(n_links_of(b), vcap, p->n_dash);
+  if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+  return launch_dash(b, p, offsets, vx, vy, vs, dx, dy, ds, range, rib_cap, dash_cap, ws_view(ws, w), w,
+                     (hipStream_t)stream);
+}
+
+int ps_read_status(const void* ws, ps_status* out, void* stream) {
+  if (!ws || !out) return fail(PS_E_ARG, "NULL argument");
+  DevStatus d;
+  PS_HIP(hipMemcpyAsync(&d, ws, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  PS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  out->flags = d.flags;
+  out->reserved = 0;
+  out->total_ribs = (int64_t)d.total_ribs;
+  out->fixups = (int64_t)d.fixups;
+  out->dash_ribs = (int64_t)d.dash_ribs;
+  out->dash_count = (int64_t)d.dash_count;
+  return PS_OK;
+}
+
+int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, int64_t* offsets,
+                   float* vx, float* vy, float* vs, int64_t cap, float* dx, float* dy, float* ds,
+                   int64_t* range, int64_t dash_rib_cap, int64_t dash_cap, void* ws,
+                   size_t ws_bytes, void* stream, ps_plan** out) {
+  int rc;
+  if (!out) return fail(PS_E_ARG, "out is NULL");
+  *out = nullptr;
+  if ((rc = check_batch(b)) || (rc = check_params(p))) return rc;
+  if (!link_ribs || !offsets || !vx || !vy || !vs) return fail(PS_E_ARG, "NULL array");
+  if (p->n_dash > 0 && (!dx || !dy || !ds || !range)) return fail(PS_E_ARG, "NULL dash array");
+  const WsLayout w = ws_layout(n_links_of(b), cap, p->n_dash);
+  if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+  ps_plan* P = new (std::nothrow) ps_plan();
+  if (!P) return fail(PS_E_NOMEM, "plan allocation failed");
+  P->b = *b;
+  P->p = *p;
+  P->dash.assign(p->dash, p->dash + p->n_dash);
+  P->p.dash = P->dash.empty() ? nullptr : P->dash.data();
+  P->link_ribs = link_ribs; P->off = offsets; P->vx = vx; P->vy = vy; P->vs = vs; P->cap = cap;
+  P->dx = dx; P->dy = dy; P->ds = ds; P->range = range;
+  P->dash_rib_cap = dash_rib_cap; P->dash_cap = dash_cap;
+  P->ws = ws; P->w = w;
+  P->graph = nullptr; P->exec = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  // autotune the emit mapping on this batch
+  const EmitConfig c0 = current_cfg();
+  P->K = c0.K; P->waves = c0.waves;
+  const WsView v = ws_view(ws, w);
+  if ((rc = launch_count(b, &P->p, link_ribs, v, s)) ||
+      (rc = do_scan_i32(link_ribs, n_links_of(b), nullptr, offsets, v.scan, &v.st->total_ribs, s))) {
+    delete P;
+    return rc;
+  }
+  float best = 1e30f;
+  const int Ks[4] = {2, 4, 8, 16};
+  const int Ws[3] = {2, 4, 8};
+  for (int ki = 0; ki < 4; ++ki)
+    for (int wi = 0; wi < 3; ++wi) {
+      float ms = 0;
+      if ((rc = time_emit(P, Ks[ki], Ws[wi], s, &ms))) { delete P; return rc; }
+      if (ms < best) { best = ms; P->K = Ks[ki]; P->waves = Ws[wi]; }
+    }
+  // capture the chain into one graph
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete P; return fail(PS_E_HIP, "stream"); }
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cs); delete P; return fail(PS_E_HIP, "begin capture failed");
+  }
+  rc = enqueue_chain(P, cs);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (rc) { if (g) (void)hipGraphDestroy(g); delete P; return rc; }
+  if (e != hipSuccess || !g) { delete P; return fail(PS_E_HIP, "end capture: %s", hipGetErrorString(e)); }
+  P->graph = g;
+  e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) { (void)hipGraphDestroy(g); delete P; return fail(PS_E_HIP, "instantiate: %s", hipGetErrorString(e)); }
+  *out = P;
+  return PS_OK;
+}
+
+int ps_plan_launch(ps_plan* P, void* stream) {
+  if (!P || !P->exec) return fail(PS_E_ARG, "invalid plan");
+  PS_HIP(hipGraphLaunch(P->exec, (hipStream_t)stream));
+  return PS_OK;
+}
+
+int ps_plan_destroy(ps_plan* P) {
+  if (!P) return PS_OK;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  delete P;
+  return PS_OK;
+}
+
+int ps_plan_config(const ps_plan* P, int32_t* K, int32_t* waves) {
+  if (!P) return fail(PS_E_ARG, "invalid plan");
+  if (K) *K = P->K;
+  if (waves) *waves = P->waves;
+  return PS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/ps.h declares, and host-side validation rejects bad arguments before
+anything is queued (no compute call is made here)."""
+import ctypes
+import math
+
+import pytest
+
+import paper_2007_00308_amd as ps
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ps.load()
+    names = ps.declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert ps.ps_version()
+
+
+def _batch(n_paths=1, n_segs=1):
+    fake = 0x1000   # never dereferenced: validation fails first or no call is made
+    return ps.ps_batch(n_paths, n_segs, fake, fake, fake, fake, fake, fake, fake, fake)
+
+
+def test_num_links_and_workspace_are_host_only():
+    lib = ps.load()
+    b = _batch(3, 10)
+    assert lib.ps_num_links(ctypes.byref(b)) == 23
+    p = ps.make_params(math.pi / 64)
+    w0 = lib.ps_workspace_bytes(ctypes.byref(b), ctypes.byref(p), 0)
+    w1 = lib.ps_workspace_bytes(ctypes.byref(b), ctypes.byref(p), 1 << 20)
+    assert 0 < w0 < w1
+    pd = ps.make_params(math.pi / 64, dash=(10.0, 5.0))
+    assert lib.ps_workspace_bytes(ctypes.byref(b), ctypes.byref(pd), 1 << 20) > w1
+
+
+@pytest.mark.parametrize("q", [0.0, -1.0, 1e-6, 4.0, float("nan")])
+def test_bad_q_rejected(q):
+    lib = ps.load()
+    b = _batch()
+    p = ps.make_params(q)
+    rc = lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None)
+    assert rc == ps.PS_E_ARG
+    assert "q must be" in lib.ps_last_error().decode()
+
+
+def test_null_and_negative_arguments_rejected():
+    lib = ps.load()
+    p = ps.make_params(0.1)
+    assert lib.ps_count(None, ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    b = _batch(-1, 0)
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    b = ps.ps_batch(1, 1, 0, 0, 0, 0, 0, 0, 0, 0)
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    b = _batch(0, 3)   # segments without any path
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    assert lib.ps_scan(None, 5, 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    assert lib.ps_scan(0x1000, -1, 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+
+
+def test_workspace_checks():
+    lib = ps.load()
+    b = _batch(2, 4)
+    p = ps.make_params(0.1)
+    need = lib.ps_workspace_bytes(ctypes.byref(b), ctypes.byref(p), 0)
+    # too small
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, need - 1, None) == ps.PS_E_WORKSPACE
+    # misaligned
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1008, need, None) == ps.PS_E_ARG
+    assert "aligned" in lib.ps_last_error().decode()
+
+
+@pytest.mark.parametrize("dash", [(1.0,), (1.0, 2.0, 3.0), (0.0, 0.0), (-1.0, 2.0), (float("inf"), 1.0)])
+def test_bad_dash_rejected(dash):
+    lib = ps.load()
+    b = _batch()
+    p = ps.make_params(0.1, dash=dash)
+    rc = lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None)
+    assert rc == ps.PS_E_ARG
+
+
+def test_bad_precision_and_emit_config_rejected():
+    lib = ps.load()
+    b = _batch()
+    p = ps.make_params(0.1, precision=7)
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    assert lib.ps_set_emit_config(3, 4) == ps.PS_E_ARG
+    assert lib.ps_set_emit_config(8, 99) == ps.PS_E_ARG
+    assert lib.ps_set_emit_config(0, 0) == ps.PS_OK
+
+
+def test_plan_rejects_null_buffers():
+    lib = ps.load()
+    b = _batch()
+    p = ps.make_params(0.1)
+    h = ctypes.c_void_p()
+    rc = lib.ps_plan_create(ctypes.byref(b), ctypes.byref(p), None, None, None, None, None, 0,
+                            None, None, None, None, 0, 0, 0x1000, 1 << 30, None, ctypes.byref(h))
+    assert rc == ps.PS_E_ARG and not h.value
+    assert lib.ps_plan_launch(None, None) == ps.PS_E_ARG
+    assert lib.ps_plan_destroy(None) == ps.PS_OK

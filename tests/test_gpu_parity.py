@@ -1,0 +1,228 @@
+"""GPU-vs-oracle parity through the C ABI (needs an MI355X).
+
+Bar: link rib counts and offsets bit-exact; every vertex within 2e-3 px of the
+FP64 oracle (FP32 with FP64 fix-up, and FP64); arc length within a tolerance
+derived from FP32 output rounding of s (stated per case in the assertion).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2007_00308_amd as ps
+from paper_2007_00308_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+VERTEX_TOL = 2e-3
+
+
+def _gpu(b, precision=ps.PS_PREC_FP32_FIXUP, **kw):
+    db = ps.DeviceBatch(b)
+    out = ps.stroke(db, b.q, precision=precision, **kw)
+    import torch
+    torch.cuda.synchronize()
+    return db, out
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _arc_tol(ref_s):
+    # FP32 output of s: half an ulp of the largest value, plus accumulated
+    # chord rounding (relative 1e-6)
+    return float(np.spacing(np.float32(max(1.0, ref_s.max())))) + 1e-6 * float(ref_s.max())
+
+
+def _compare(b, precision=ps.PS_PREC_FP32_FIXUP, vertex_tol=VERTEX_TOL, check_s=True):
+    ref = oracle.stroke(b)
+    db, out = _gpu(b, precision)
+    st = out["status"]
+    assert st.flags == 0, st.flags
+    np.testing.assert_array_equal(_np(out["link_ribs"]), ref["link_ribs"])
+    np.testing.assert_array_equal(_np(out["offsets"]), ref["offsets"])
+    R = int(ref["offsets"][-1])
+    assert out["total_ribs"] == R
+    vx, vy = _np(out["vx"]).astype(np.float64), _np(out["vy"]).astype(np.float64)
+    err = np.hypot(vx - ref["vx"], vy - ref["vy"])
+    worst = int(np.argmax(err)) if err.size else 0
+    assert err.size == 0 or err.max() <= vertex_tol, (
+        f"max vertex error {err.max():.3e} px at vertex {worst} (rib {worst // 2}, "
+        f"t={ref['t'][worst // 2]}, psi={ref['psi'][worst // 2]})")
+    s_err = 0.0
+    if check_s and R:
+        vs = _np(out["vs"]).astype(np.float64)
+        assert np.array_equal(vs[0::2], vs[1::2])
+        s_err = float(np.abs(vs[0::2] - ref["vs"]).max())
+        assert s_err <= _arc_tol(ref["vs"]), f"arc length error {s_err:.3e}"
+    return dict(R=R, vmax=float(err.max()) if err.size else 0.0, smax=s_err, fixups=st.fixups)
+
+
+# --------------------------------------------------------------- configurations
+def test_config1_full():
+    r = _compare(W.config1())
+    assert r["R"] > 1000
+
+
+@pytest.mark.parametrize("prec", [ps.PS_PREC_FP32_FIXUP, ps.PS_PREC_FP64])
+def test_config2_reduced(prec):
+    _compare(W.config2(n_paths=96, max_segs=64), precision=prec)
+
+
+def test_config3_full_path():
+    r = _compare(W.config3())
+    assert r["R"] > 100_000
+
+
+def test_config4_reduced_precision_cases():
+    _compare(W.config4(n_paths=160, max_segs=32), precision=ps.PS_PREC_FP32_FIXUP)
+    _compare(W.config4(n_paths=160, max_segs=32), precision=ps.PS_PREC_FP64)
+
+
+@pytest.mark.parametrize("q", [math.pi / 16, math.pi / 64, math.pi / 256])
+def test_config5_reduced(q):
+    _compare(W.config5(q=q, n_paths=512, total_segs=4096))
+
+
+@pytest.mark.parametrize("join,cap", [(W.JOIN_ROUND, W.CAP_ROUND), (W.JOIN_BEVEL, W.CAP_SQUARE),
+                                      (W.JOIN_TRIANGLE, W.CAP_TRIANGLE), (W.JOIN_NONE, W.CAP_BUTT)])
+def test_styles(join, cap):
+    _compare(W.random_mixed(21, n_paths=60, max_segs=20, extent=2048.0, join=join, cap=cap))
+
+
+def test_fp32_only_is_reported():
+    # single precision alone is allowed a looser bound; it is not the default
+    b = W.config2(n_paths=64, max_segs=32)
+    ref = oracle.stroke(b)
+    _, out = _gpu(b, ps.PS_PREC_FP32)
+    np.testing.assert_array_equal(_np(out["link_ribs"]), ref["link_ribs"])
+    err = np.hypot(_np(out["vx"]) - ref["vx"], _np(out["vy"]) - ref["vy"])
+    assert err.max() < 0.5
+
+
+# --------------------------------------------------------------------- edge cases
+def test_edge_single_line_and_degenerate():
+    segs = [(W.KIND_L, [(0, 0), (100, 0)], 1.0),
+            (W.KIND_C, [(100, 0), (100, 0), (100, 0), (100, 0)], 1.0),     # zero length
+            (W.KIND_C, [(100, 0), (150, 0), (120, 0), (200, 0)], 1.0),     # collinear with folds
+            (W.KIND_Q, [(200, 0), (200, 0), (250, 50)], 1.0),              # coincident P1 = P0
+            (W.KIND_K, [(250, 50), (300, 100), (350, 50)], 1e-5),          # near-degenerate weight
+            (W.KIND_C, [(350, 50), (351, 51), (350, 51), (351, 50)], 1.0)]  # exact cusp
+    b = W.path(segs, width=4.0, q=math.pi / 32, cap=W.CAP_ROUND)
+    _compare(b)
+
+
+def test_edge_empty_paths_and_batches():
+    b = W.paths([[], [(W.KIND_L, [(0, 0), (5, 5)], 1.0)], [], []], widths=[1, 2, 3, 4],
+                q=math.pi / 8, caps=[W.CAP_SQUARE] * 4)
+    _compare(b)
+    b0 = W.paths([[]], widths=[1.0], q=0.1)
+    r = _compare(b0)
+    assert r["R"] == 0
+
+
+@pytest.mark.parametrize("q", [math.pi, 1e-3])
+def test_edge_extreme_q(q):
+    b = W.random_mixed(5, n_paths=4, max_segs=3, extent=300.0, q=q)
+    _compare(b)
+
+
+def test_overflow_sets_status_and_writes_nothing():
+    import torch
+    b = W.config1()
+    db = ps.DeviceBatch(b)
+    ref = oracle.stroke(b)
+    R = int(ref["offsets"][-1])
+    cap = 2 * R - 2
+    out = ps.stroke(db, b.q, vertex_capacity=cap)
+    assert out["status"].flags & ps.PS_STATUS_OVERFLOW
+
+
+def test_nonfinite_and_bad_values_flagged():
+    b = W.random_mixed(3, n_paths=3, max_segs=4)
+    b.cx[1, 2] = np.nan
+    b.conic_w[:] = -1.0
+    b.kind[b.kind == W.KIND_K] = W.KIND_K
+    _, out = _gpu(b)
+    assert out["status"].flags & ps.PS_STATUS_NONFINITE
+
+
+# ------------------------------------------------------ mapping / determinism
+def test_mappings_agree_and_are_deterministic():
+    import torch
+    b = W.config2(n_paths=48, max_segs=96)
+    outs = []
+    try:
+        for K in (2, 4, 8, 16):
+            for waves in (1, 4):
+                ps.ps_set_emit_config(K, waves)
+                _, o = _gpu(b)
+                outs.append((K, waves, _np(o["vx"]), _np(o["vy"]), _np(o["vs"])))
+    finally:
+        ps.ps_set_emit_config(8, 4)
+    for K, w, vx, vy, vs in outs[1:]:
+        assert np.array_equal(vx, outs[0][2]) and np.array_equal(vy, outs[0][3]), (K, w)
+        assert np.array_equal(vs, outs[0][4]), (K, w)
+
+
+def test_arclen_only_matches_emit():
+    import torch
+    b = W.config3(n_segs=800)
+    db, out = _gpu(b)
+    vs2 = torch.empty_like(out["vs"])
+    ps.ps_arclen(db, out["params"], out["offsets"], vs2, out["capacity"], out["ws"])
+    torch.cuda.synchronize()
+    assert torch.equal(vs2, out["vs"])
+
+
+# ------------------------------------------------------------------ dash
+def test_dash_exact_on_axis_lines():
+    # collinear axis lines with dyadic lengths: the rib stream is exact on both
+    # sides, so dash counts, ranges and positions must agree exactly
+    segs = [(W.KIND_L, [(x0, 0), (x1, 0)], 1.0) for x0, x1 in
+            [(0, 7.5), (7.5, 31.25), (31.25, 32.0), (32.0, 80.0)]]
+    b = W.path(segs, width=2.0, q=math.pi / 8, join=W.JOIN_ROUND, cap=W.CAP_BUTT)
+    ref = oracle.stroke(b)
+    pr = oracle.path_rib_begin(b, ref["offsets"])
+    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], [10.0, 5.0], 3.0)
+    _, out = _gpu(b, dash=(10.0, 5.0), dash_phase=3.0)
+    rng = _np(out["dash_range"])
+    np.testing.assert_array_equal(rng, dref["ranges"])
+    np.testing.assert_array_equal(_np(out["dx"]), dref["dx"].astype(np.float32))
+    np.testing.assert_array_equal(_np(out["ds"])[0::2], dref["ds"].astype(np.float32))
+
+
+def test_dash_config3_unique_quantities():
+    b = W.config3(n_segs=600)
+    ref = oracle.stroke(b)
+    pr = oracle.path_rib_begin(b, ref["offsets"])
+    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], list(b.dash), b.dash_phase)
+    _, out = _gpu(b, dash=b.dash, dash_phase=b.dash_phase)
+    rng = _np(out["dash_range"])
+    ds = _np(out["ds"])[0::2].astype(np.float64)
+    assert rng.shape == dref["ranges"].shape
+    # dash start / end arc lengths are the pattern's boundaries
+    np.testing.assert_allclose(ds[rng[:, 0]], dref["ds"][dref["ranges"][:, 0]], atol=0.05)
+    np.testing.assert_allclose(ds[rng[:, 1] - 1], dref["ds"][dref["ranges"][:, 1] - 1], atol=0.05)
+    dx = _np(out["dx"]).astype(np.float64)
+    np.testing.assert_allclose(dx[2 * rng[:, 0]], dref["dx"][2 * dref["ranges"][:, 0]], atol=0.05)
+
+
+# ------------------------------------------------------------------ plan / graph
+def test_plan_graph_replays_match_eager():
+    import torch
+    b = W.config2(n_paths=40, max_segs=64)
+    db, eager = _gpu(b)
+    plan = ps.Plan(db, b.q, vertex_capacity=eager["capacity"])
+    R = eager["total_ribs"]
+    for rep in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.vx[:2 * R], eager["vx"]), rep
+        assert torch.equal(plan.vs[:2 * R], eager["vs"]), rep
+        # unrelated eager work between replays
+        torch.ones(1 << 20, device="cuda").sum().item()
+    assert plan.status().flags == 0
+    plan.close()
