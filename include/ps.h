@@ -220,7 +220,7 @@ int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_p
 
 /*
  * Emit tuning for the unplanned calls: K consecutive 64-rib iterations per
- * wave tile (1..32) and waves per workgroup (1..16).  0 keeps the default.
+ * wave tile (2, 4, 8 or 16) and waves per workgroup (1..4).  0 keeps the default.
  */
 int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group);
 

@@ -733,16 +733,16 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
     }
     if (WS) {
       // decoupled look-back over tile sums in fixed point: integer additions
-      // are associative, so every run gives the same bits
+      // are associative, so every run gives the same bits.  A tile holding a
+      // path start publishes its inclusive sum at once; it still needs the
+      // prefix if its first ribs continue a path from earlier tiles.
       const unsigned long long agg = (unsigned long long)llrint(run * kFix) & kValMask;
+      const bool any_need = __ballot(need_prefix != 0) != 0ull;
       unsigned long long prefix = 0;
       if (lane == 0) {
-        if (seen_start) {
-          __hip_atomic_store(&A.desc[tile], (2ull << 62) | agg, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          __hip_atomic_store(&A.desc[tile], (1ull << 62) | agg, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (any_need) {
           int64_t T = tile - 1;
           while (T >= 0) {
             const unsigned long long w =
@@ -750,12 +750,13 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
             const unsigned stt = (unsigned)(w >> 62);
             if (stt == 0) { __builtin_amdgcn_s_sleep(2); continue; }
             prefix += w & kValMask;
-            if (stt == 2 || ((w >> 61) & 1ull)) break;
+            if (stt == 2) break;
             --T;
           }
+        }
+        if (!seen_start)
           __hip_atomic_store(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask),
                              __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
       }
       const unsigned int plo = __shfl((unsigned int)(prefix & 0xffffffffu), 0, 64);
       const unsigned int phi = __shfl((unsigned int)(prefix >> 32), 0, 64);
@@ -1126,8 +1127,9 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
   a.B = *b; a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
   a.max_tiles = w.max_tiles;
-  const int block = 64 * waves;
-  const int grid = num_cus() * std::max(1, 16 / waves);
+  if (waves < 1 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
+  const int block = 64 * waves;   // never above the kernel's launch bound of 256
+  const int grid = num_cus() * (16 / waves);
   fn(a, grid, block, s);
   PS_HIP(hipGetLastError());
   return PS_OK;
@@ -1249,7 +1251,7 @@ size_t ps_workspace_bytes(const ps_batch* b, const ps_params* p, int64_t vertex_
 
 int ps_set_emit_config(int32_t K, int32_t waves) {
   if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 2, 4, 8 or 16");
-  if (waves < 0 || waves > 16) return fail(PS_E_ARG, "waves_per_group must be in [1,16]");
+  if (waves < 0 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   std::lock_guard<std::mutex> lk(g_mu);
   if (K) g_cfg.K = K;
   if (waves) g_cfg.waves = waves;
@@ -1366,7 +1368,7 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   }
   float best = 1e30f;
   const int Ks[4] = {2, 4, 8, 16};
-  const int Ws[3] = {2, 4, 8};
+  const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
   for (int ki = 0; ki < 4; ++ki)
     for (int wi = 0; wi < 3; ++wi) {
       float ms = 0;

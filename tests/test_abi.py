@@ -87,6 +87,7 @@ def test_bad_precision_and_emit_config_rejected():
     assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
     assert lib.ps_set_emit_config(3, 4) == ps.PS_E_ARG
     assert lib.ps_set_emit_config(8, 99) == ps.PS_E_ARG
+    assert lib.ps_set_emit_config(8, 5) == ps.PS_E_ARG   # above the 256-thread launch bound
     assert lib.ps_set_emit_config(0, 0) == ps.PS_OK
 
 
