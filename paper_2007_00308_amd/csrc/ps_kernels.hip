@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -35,8 +36,9 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;                        // items per thread
 constexpr int kScanTile = kScanThreads * kScanItems;  // 4096 items per block
 constexpr int kMinTileRibs = 64 * 1 - 1;              // smallest emit tile (K = 1)
-constexpr double kFix = 16777216.0;                   // arc-length fixed point: 2^-24 px
-constexpr unsigned long long kValMask = (1ull << 61) - 1;
+constexpr double kFix = 4294967296.0;                 // arc length in fixed point: 2^-32 px
+constexpr unsigned long long kValMask = (1ull << 62) - 1;
+constexpr int kTileGroup = 4;                         // tiles claimed per ticket
 constexpr int kMaxDash = 64;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -489,6 +491,7 @@ struct EmitArgs {
   unsigned long long* desc;
   DevStatus* st;
   int64_t max_tiles;
+  float fix_tol;   // FP32 roots whose estimated position error exceeds this (px) are re-solved in FP64
 };
 
 __device__ __forceinline__ int link_of(const int64_t* off, int lo, int hi, int64_t r) {
@@ -605,7 +608,7 @@ __device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r,
             }
             const float dt = (hn + sum_e) * 2.4e-7f / fmaxf(so.dh, 1e-30f) + 6e-8f;
             const float est = fk * hn * dt;
-            need64 = !so.found || !(est < 4e-4f);
+            need64 = !so.found || !(est < A.fix_tol);
           }
         }
         if (need64) {
@@ -665,7 +668,13 @@ __device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r,
 
 // Persistent emit.  Tile T covers ribs [T*TS, (T+1)*TS), TS = 64*K - 1; lane
 // slot (k, lane) handles rib T*TS - 1 + 64k + lane, so slot (0,0) re-reads the
-// previous tile's last rib for the first chord and stores nothing.
+// previous tile's last rib for the first chord and stores nothing.  Waves
+// claim kTileGroup consecutive tiles per ticket, always in increasing order,
+// so every tile a wave waits on belongs to a wave that is already running.
+//
+// Arc length is accumulated in 64-bit fixed point (2^-32 px per unit): each
+// chord is rounded once and every sum after that is an integer sum, so s does
+// not depend on the tiling, the mapping or the order tiles finish in.
 template <int K, int PREC, bool WXY, bool WS>
 __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
   const int lane = threadIdx.x & 63;
@@ -678,95 +687,102 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
   for (;;) {
     unsigned int tk = 0;
     if (lane == 0) tk = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
-    const int64_t tile = (int64_t)__shfl(tk, 0, 64);
-    if (tile >= n_tiles) break;
-    const int64_t r0 = tile * TS;
-    const int lhi = A.tile_link[tile + 1];
-    int l = A.tile_link[tile];
-    double run = 0.0;           // chord sum since the tile start or its last path start
-    bool seen_start = false;
-    double cgx = 0, cgy = 0, ct = 0;   // the previous iteration's last rib
-    double srel[K];
-    unsigned int need_prefix = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t r = r0 - 1 + 64 * k + lane;
-      const bool valid = (r >= 0) && (r < R);
-      const bool mine = valid && (r >= r0);
-      RibOut o;
-      o.gx = o.gy = o.t = 0; o.chord_ok = false; o.path_start = false; o.fixed = false;
-      if (valid) {
-        l = link_of(A.off, l, lhi, r);
-        compute_rib<PREC>(A, l, r, o);
-        if (WXY && mine) {
-          *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
-          *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
-        }
-        fixups += o.fixed ? 1 : 0;
-      }
-      // chord from the previous rib; zero when t decreases
-      double pgx = __shfl_up(o.gx, 1, 64), pgy = __shfl_up(o.gy, 1, 64), pt = __shfl_up(o.t, 1, 64);
-      if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
-      double c = 0.0;
-      if (mine && o.chord_ok && o.t >= pt) {
-        const double dx = o.gx - pgx, dy = o.gy - pgy;
-        c = sqrt(dx * dx + dy * dy);
-      }
-      int f = (mine && o.path_start) ? 1 : 0;
-      // segmented inclusive scan across the wave: a path start resets the sum
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const double cu = __shfl_up(c, d, 64);
-        const int fu = __shfl_up(f, d, 64);
-        if (lane >= d) {
-          c = f ? c : c + cu;
-          f = f | fu;
-        }
-      }
-      srel[k] = f ? c : run + c;
-      if (!(f || seen_start)) need_prefix |= (1u << k);
-      const double c63 = __shfl(c, 63, 64);
-      const int f63 = __shfl(f, 63, 64);
-      run = f63 ? c63 : run + c63;
-      seen_start = seen_start || (f63 != 0);
-      cgx = __shfl(o.gx, 63, 64); cgy = __shfl(o.gy, 63, 64); ct = __shfl(o.t, 63, 64);
-    }
-    if (WS) {
-      // decoupled look-back over tile sums in fixed point: integer additions
-      // are associative, so every run gives the same bits.  A tile holding a
-      // path start publishes its inclusive sum at once; it still needs the
-      // prefix if its first ribs continue a path from earlier tiles.
-      const unsigned long long agg = (unsigned long long)llrint(run * kFix) & kValMask;
-      const bool any_need = __ballot(need_prefix != 0) != 0ull;
-      unsigned long long prefix = 0;
-      if (lane == 0) {
-        __hip_atomic_store(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        if (any_need) {
-          int64_t T = tile - 1;
-          while (T >= 0) {
-            const unsigned long long w =
-                __hip_atomic_load(&A.desc[T], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned stt = (unsigned)(w >> 62);
-            if (stt == 0) { __builtin_amdgcn_s_sleep(2); continue; }
-            prefix += w & kValMask;
-            if (stt == 2) break;
-            --T;
-          }
-        }
-        if (!seen_start)
-          __hip_atomic_store(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask),
-                             __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      const unsigned int plo = __shfl((unsigned int)(prefix & 0xffffffffu), 0, 64);
-      const unsigned int phi = __shfl((unsigned int)(prefix >> 32), 0, 64);
-      const double pre = (double)(((unsigned long long)phi << 32) | plo) * (1.0 / kFix);
+    const int64_t first_tile = (int64_t)__shfl(tk, 0, 64) * kTileGroup;
+    if (first_tile >= n_tiles) break;
+    for (int64_t tile = first_tile; tile < first_tile + kTileGroup && tile < n_tiles; ++tile) {
+      const int64_t r0 = tile * TS;
+      const int lhi = A.tile_link[tile + 1];
+      int l = A.tile_link[tile];
+      long long run = 0;          // chord sum since the tile start or its last path start
+      bool seen_start = false;
+      double cgx = 0, cgy = 0, ct = 0;   // the previous iteration's last rib
+      long long srel[K];
+      unsigned int need_prefix = 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int64_t r = r0 - 1 + 64 * k + lane;
-        if (r >= r0 && r < R) {
-          const float s = (float)(((need_prefix >> k) & 1u) ? pre + srel[k] : srel[k]);
-          *reinterpret_cast<float2*>(A.vs + 2 * r) = make_float2(s, s);
+        const bool valid = (r >= 0) && (r < R);
+        const bool mine = valid && (r >= r0);
+        RibOut o;
+        o.gx = o.gy = o.t = 0; o.chord_ok = false; o.path_start = false; o.fixed = false;
+        if (valid) {
+          l = link_of(A.off, l, lhi, r);
+          compute_rib<PREC>(A, l, r, o);
+          if (WXY && mine) {
+            *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
+            *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
+          }
+          fixups += o.fixed ? 1 : 0;
+        }
+        if (WS) {
+          // chord from the previous rib; zero when t decreases
+          double pgx = __shfl_up(o.gx, 1, 64), pgy = __shfl_up(o.gy, 1, 64), pt = __shfl_up(o.t, 1, 64);
+          if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
+          long long c = 0;
+          if (mine && o.chord_ok && o.t >= pt) {
+            const double dx = o.gx - pgx, dy = o.gy - pgy;
+            c = llrint(sqrt(dx * dx + dy * dy) * kFix);
+          }
+          int f = (mine && o.path_start) ? 1 : 0;
+          // segmented inclusive scan across the wave: a path start resets the sum
+#pragma unroll
+          for (int d = 1; d < 64; d <<= 1) {
+            const long long cu = __shfl_up(c, d, 64);
+            const int fu = __shfl_up(f, d, 64);
+            if (lane >= d) {
+              c = f ? c : c + cu;
+              f = f | fu;
+            }
+          }
+          srel[k] = f ? c : run + c;
+          if (!(f || seen_start)) need_prefix |= (1u << k);
+          const long long c63 = __shfl(c, 63, 64);
+          const int f63 = __shfl(f, 63, 64);
+          run = f63 ? c63 : run + c63;
+          seen_start = seen_start || (f63 != 0);
+          cgx = __shfl(o.gx, 63, 64); cgy = __shfl(o.gy, 63, 64); ct = __shfl(o.t, 63, 64);
+        }
+      }
+      if (WS) {
+        // Decoupled look-back on one 64-bit word per tile (2 state bits, 62
+        // value bits).  The word carries everything a reader needs, so
+        // relaxed device-scope atomics suffice: no cache write-back or
+        // invalidation is needed around them.  A tile holding a path start
+        // publishes its inclusive sum at once, and still looks back when
+        // its first ribs continue a path from earlier tiles.
+        const unsigned long long agg = (unsigned long long)run & kValMask;
+        const bool any_need = __ballot(need_prefix != 0) != 0ull;
+        unsigned long long prefix = 0;
+        if (lane == 0) {
+          __hip_atomic_store(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (any_need) {
+            int64_t T = tile - 1;
+            while (T >= 0) {
+              const unsigned long long w =
+                  __hip_atomic_load(&A.desc[T], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              const unsigned stt = (unsigned)(w >> 62);
+              if (stt == 0) { __builtin_amdgcn_s_sleep(1); continue; }
+              prefix += w & kValMask;
+              if (stt == 2) break;
+              --T;
+            }
+          }
+          if (!seen_start)
+            __hip_atomic_store(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const unsigned int plo = __shfl((unsigned int)(prefix & 0xffffffffu), 0, 64);
+        const unsigned int phi = __shfl((unsigned int)(prefix >> 32), 0, 64);
+        const long long pre = (long long)(((unsigned long long)phi << 32) | plo);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int64_t r = r0 - 1 + 64 * k + lane;
+          if (r >= r0 && r < R) {
+            const long long sf = ((need_prefix >> k) & 1u) ? pre + srel[k] : srel[k];
+            const float s = (float)((double)sf * (1.0 / kFix));
+            *reinterpret_cast<float2*>(A.vs + 2 * r) = make_float2(s, s);
+          }
         }
       }
     }
@@ -1102,6 +1118,17 @@ EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws) {
 
 bool valid_k(int K) { return K == 2 || K == 4 || K == 8 || K == 16; }
 
+// Estimated FP32 position error (px) above which a rib is re-solved in FP64.
+// PS_FIXUP_TOL overrides it, for precision studies.
+float fixup_tolerance() {
+  static float tol = [] {
+    const char* e = getenv("PS_FIXUP_TOL");
+    const float v = e ? (float)atof(e) : 0.0f;
+    return v > 0 ? v : 4e-4f;
+  }();
+  return tol;
+}
+
 int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, const WsView& v,
                  hipStream_t s) {
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, v.st);
@@ -1127,6 +1154,7 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
   a.B = *b; a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
   a.max_tiles = w.max_tiles;
+  a.fix_tol = fixup_tolerance();
   if (waves < 1 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   const int block = 64 * waves;   // never above the kernel's launch bound of 256
   const int grid = num_cus() * (16 / waves);

@@ -247,20 +247,21 @@ def config4(seed: int = 1004, n_paths: int = 1024, max_segs: int = 64) -> Batch:
                 cx[s, i], cy[s, i] = pt
             n["near_collinear"] += 1
         elif c == 1 and kind[i] == KIND_C:
-            # cusp at t_c within 1e-6 of an end: choose b, c and solve g'(t_c) = 0 for a
+            # cusp at t_c within 1e-6 of an end: g'(t_c) = (1-t)^2 a + 2(1-t)t b + t^2 c = 0,
+            # solved for the handle next to that end (the well-conditioned unknown)
             tc = rng.uniform(1e-8, 1e-6)
-            if rng.uniform() < 0.5:
-                tc = 1.0 - tc
-            u = 1.0 - tc
-            p2 = np.array([cx[2, i], cy[2, i]])
             p1 = np.array([cx[1, i], cy[1, i]])
-            b = p2 - p1
-            cc = pe - p2
-            a = -(2 * u * tc * b + tc * tc * cc) / (u * u)
-            p1n = p0 + a
-            # keep b = P2 - P1 by moving P2 along with P1
-            cx[1, i], cy[1, i] = p1n
-            cx[2, i], cy[2, i] = p1n + b
+            p2 = np.array([cx[2, i], cy[2, i]])
+            if rng.uniform() < 0.5:
+                u, t = 1.0 - tc, tc          # near t = 0: unknown a, keep P0, P2, P3
+                cc = pe - p2
+                a = -(2 * u * t * (p2 - p0) + t * t * cc) / (u * u - 2 * u * t)
+                cx[1, i], cy[1, i] = p0 + a
+            else:
+                u, t = tc, 1.0 - tc          # near t = 1: unknown c, keep P0, P1, P3
+                a = p1 - p0
+                cc = -(u * u * a + 2 * u * t * (pe - p1)) / (t * t - 2 * u * t)
+                cx[2, i], cy[2, i] = pe - cc
             n["cusp_near_end"] += 1
         elif c == 2 and kind[i] == KIND_C:
             # exact cusp (P2 = P0 + P1 - P3), then nudge P2 by a few ulps
@@ -274,6 +275,7 @@ def config4(seed: int = 1004, n_paths: int = 1024, max_segs: int = 64) -> Batch:
             cw[i] = 10.0 ** (rng.uniform(-6, -2) if rng.uniform() < 0.5 else rng.uniform(2.5, 3))
             n["extreme_weight"] += 1
     meta.update(n)
+    assert np.abs(cx).max() < 1024 and np.abs(cy).max() < 1024
     width = np.exp(rng.uniform(math.log(0.5), math.log(16.0), size=n_paths))
     return _finish(sb, kind, cx, cy, cw, width, np.full(n_paths, JOIN_ROUND),
                    np.full(n_paths, CAP_BUTT), q=math.pi / 64,
