@@ -49,6 +49,9 @@ def main() -> int:
     ap.add_argument("--profile", action="store_true", help="few steps, no oracle (for rocprofv3)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--study", choices=["precision", "c3", "c5"], default=None,
+                    help="secondary measurements: the near-degenerate precision study, the long "
+                         "dashed path, or the stress configuration at q in {pi/16, pi/64, pi/256}")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
@@ -64,6 +67,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.study:
+        return STUDIES[args.study](args, torch, ps, W, dev)
     prec = {"fp32": ps.PS_PREC_FP32, "fp32_fixup": ps.PS_PREC_FP32_FIXUP, "fp64": ps.PS_PREC_FP64}[args.precision]
 
     t0 = time.time()
@@ -81,8 +86,8 @@ def main() -> int:
     torch.cuda.synchronize()
 
     plan = ps.Plan(db, b.q, vertex_capacity=cap, precision=prec)
-    K, waves = plan.config()
-    log(f"plan: autotuned emit mapping K={K} waves/group={waves}")
+    K, waves, stage = plan.config()
+    log(f"plan: autotuned emit mapping K={K} waves/group={waves} lds-staged={stage}")
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -104,7 +109,7 @@ def main() -> int:
 
     # the emit kernel alone, timed with HIP events on the stream it runs on
     reps = max(5, args.steps)
-    ps.ps_set_emit_config(K, waves)
+    ps.ps_set_emit_config(K, waves, stage)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for _ in range(2):
         ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, cap, plan.ws)
@@ -214,7 +219,8 @@ def main() -> int:
         "config": {"workload": "batched: 4096 paths, log-uniform [1,512] segments, 60/25/15% C/Q/K, "
                                "q=pi/64, round joins, butt caps",
                    "paths": b.n_paths, "segments": b.n_segs, "ribs": R, "vertices": V,
-                   "precision": args.precision, "emit_K": K, "emit_waves_per_group": waves},
+                   "precision": args.precision, "emit_K": K, "emit_waves_per_group": waves,
+                   "emit_lds_staged": stage},
         "gb_per_s": B_alg / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": emit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": emit_gbs / HBM_PEAK_GBS, "traffic": None,
@@ -227,6 +233,119 @@ def main() -> int:
     plan.close()
     print(json.dumps(result), flush=True)
     return 0
+
+
+def _time_plan(torch, plan, steps, warmup):
+    for _ in range(warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t) / steps
+
+
+def study_precision(args, torch, ps, W, dev):
+    """Near-degenerate shapes: count mismatches and worst vertex / arc-length
+    error against the FP64 oracle for FP32 only, FP32 + FP64 polish, FP64."""
+    import oracle
+    b = W.config4()
+    ref = oracle.stroke(b)
+    db = ps.DeviceBatch(b, device=dev)
+    rows = {}
+    for name, prec in (("fp32", ps.PS_PREC_FP32), ("fp32_fixup", ps.PS_PREC_FP32_FIXUP),
+                       ("fp64", ps.PS_PREC_FP64)):
+        out = ps.stroke(db, b.q, precision=prec)
+        R = out["total_ribs"]
+        mism = int(np.sum(out["link_ribs"].cpu().numpy() != ref["link_ribs"]))
+        row = {"count_mismatches": mism, "total_ribs": R, "fixups": int(out["status"].fixups)}
+        if R == int(ref["offsets"][-1]):
+            verr = np.hypot(out["vx"].cpu().numpy() - ref["vx"], out["vy"].cpu().numpy() - ref["vy"])
+            serr = np.abs(out["vs"].cpu().numpy()[0::2] - ref["vs"])
+            row.update(max_vertex_err_px=float(verr.max()), p999_vertex_err_px=float(np.quantile(verr, 0.999)),
+                       max_arclen_err_px=float(serr.max()))
+        rows[name] = row
+        log(f"{name}: {row}")
+    print(json.dumps({"study": "precision", "workload": b.name, "segments": b.n_segs,
+                      "meta": b.meta, "modes": rows}), flush=True)
+    return 0
+
+
+def study_c3(args, torch, ps, W, dev):
+    """One 5,000-cubic random-walk path: stroke with arc length, then dashing."""
+    import oracle
+    b = W.config3()
+    db = ps.DeviceBatch(b, device=dev)
+    first = ps.stroke(db, b.q)
+    R = first["total_ribs"]
+    rcap, dcap = 4 * R, R
+    plan = ps.Plan(db, b.q, vertex_capacity=2 * R, dash=b.dash, dash_phase=b.dash_phase,
+                   dash_rib_capacity=rcap, dash_capacity=dcap)
+    ms = _time_plan(torch, plan, args.steps, args.warmup)
+    st = plan.status()
+    plain = ps.Plan(db, b.q, vertex_capacity=2 * R)
+    ms_plain = _time_plan(torch, plain, args.steps, args.warmup)
+    ref = oracle.stroke(b)
+    serr = np.abs(plan.vs[:2 * R].cpu().numpy()[0::2] - ref["vs"])
+    verr = np.hypot(plan.vx[:2 * R].cpu().numpy() - ref["vx"], plan.vy[:2 * R].cpu().numpy() - ref["vy"])
+    pr = oracle.path_rib_begin(b, ref["offsets"])
+    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], list(b.dash), b.dash_phase)
+    res = {"study": "c3", "workload": b.name, "ribs": R, "vertices": 2 * R,
+           "ms_stroke": ms_plain, "ms_stroke_and_dash": ms, "ms_dash": ms - ms_plain,
+           "dash_ribs": int(st.dash_ribs), "dashes": int(st.dash_count),
+           "oracle_dashes": int(dref["ranges"].shape[0]), "path_length_px": float(ref["vs"][-1]),
+           "max_vertex_err_px": float(verr.max()), "max_arclen_err_px": float(serr.max()),
+           "dash_bytes": 12 * 2 * int(st.dash_ribs) + 12 * 2 * R}
+    log(str(res))
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def study_c5(args, torch, ps, W, dev):
+    """2^20 segments over 65,536 Zipf(1.2) paths at three q; autotuned vs fixed mapping."""
+    rows = []
+    for qn in (16, 64, 256):
+        q = math.pi / qn
+        b = W.config5(q=q)
+        db = ps.DeviceBatch(b, device=dev)
+        first = ps.stroke(db, q)
+        R = first["total_ribs"]
+        del first
+        plan = ps.Plan(db, q, vertex_capacity=2 * R)
+        K, waves, stage = plan.config()
+        ms = _time_plan(torch, plan, args.steps, args.warmup)
+        # the emit call alone: the autotuned mapping vs a fixed one (K=8, 4 waves, staged)
+        stream = torch.cuda.current_stream()
+        emit_ms = {}
+        for name, cfg in (("autotuned", (K, waves, stage)), ("fixed", (8, 4, 1))):
+            ps.ps_set_emit_config(*cfg)
+            for _ in range(2):
+                ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            emit_ms[name] = e0.elapsed_time(e1) / args.steps
+        ps.ps_set_emit_config(8, 4, 1)
+        plan.close()
+        V = 2 * R
+        row = {"q": f"pi/{qn}", "ribs": R, "vertices": V, "ms_per_step": ms,
+               "vertices_per_s": V / (ms * 1e-3),
+               "gb_per_s": algorithmic_bytes(V, b.n_segs, b.n_paths) / (ms * 1e-3) / 1e9,
+               "autotuned": {"K": K, "waves": waves, "lds_staged": stage},
+               "emit_ms_autotuned": emit_ms["autotuned"], "emit_ms_fixed_K8_w4_staged": emit_ms["fixed"]}
+        rows.append(row)
+        log(str(row))
+        del db
+        torch.cuda.empty_cache()
+    print(json.dumps({"study": "c5", "rows": rows}), flush=True)
+    return 0
+
+
+STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5}
 
 
 if __name__ == "__main__":

@@ -215,14 +215,18 @@ int ps_plan_create(const ps_batch* batch, const ps_params* params, int32_t* link
                    ps_plan** out);
 int ps_plan_launch(ps_plan* plan, void* stream);
 int ps_plan_destroy(ps_plan* plan);
-/* The emit mapping a plan chose: ribs per lane K and waves per workgroup. */
-int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_per_group);
+/* The emit mapping a plan chose: K, waves per workgroup, LDS staging (0/1). */
+int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_per_group,
+                   int32_t* stage);
 
 /*
- * Emit tuning for the unplanned calls: K consecutive 64-rib iterations per
- * wave tile (2, 4, 8 or 16) and waves per workgroup (1..4).  0 keeps the default.
+ * Emit mapping for the unplanned calls: each wavefront tile is K iterations of
+ * 64 consecutive ribs (K = 4, 8 or 16), workgroups hold 1..4 wavefronts, and
+ * stage = 1 stages the tile's link records in LDS (0 reads them from global
+ * memory per rib; -1 keeps the current choice).  0 for K or waves keeps the
+ * current value.  Output bits do not depend on the mapping.
  */
-int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group);
+int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group, int32_t stage);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* ps_last_error(void);

@@ -81,8 +81,8 @@ def load(path: str = LIB_PATH):
                                           ctypes.c_int64, _vp, ctypes.c_size_t, _vp, P(_vp)]),
         "ps_plan_launch": (ctypes.c_int, [_vp, _vp]),
         "ps_plan_destroy": (ctypes.c_int, [_vp]),
-        "ps_plan_config": (ctypes.c_int, [_vp, P(ctypes.c_int32), P(ctypes.c_int32)]),
-        "ps_set_emit_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+        "ps_plan_config": (ctypes.c_int, [_vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
+        "ps_set_emit_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "ps_last_error": (ctypes.c_char_p, []),
         "ps_version": (ctypes.c_char_p, []),
     }
@@ -198,8 +198,9 @@ def ps_read_status(ws, stream=None) -> ps_status:
     return st
 
 
-def ps_set_emit_config(ribs_per_lane: int = 0, waves_per_group: int = 0):
-    _check(load().ps_set_emit_config(int(ribs_per_lane), int(waves_per_group)), "ps_set_emit_config")
+def ps_set_emit_config(ribs_per_lane: int = 0, waves_per_group: int = 0, stage: int = -1):
+    _check(load().ps_set_emit_config(int(ribs_per_lane), int(waves_per_group), int(stage)),
+           "ps_set_emit_config")
 
 
 def ps_version() -> str:
@@ -297,9 +298,10 @@ class Plan:
         _check(load().ps_plan_launch(self.handle, _stream(stream)), "ps_plan_launch")
 
     def config(self):
-        k, w = ctypes.c_int32(), ctypes.c_int32()
-        _check(load().ps_plan_config(self.handle, ctypes.byref(k), ctypes.byref(w)), "ps_plan_config")
-        return int(k.value), int(w.value)
+        k, w, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().ps_plan_config(self.handle, ctypes.byref(k), ctypes.byref(w), ctypes.byref(s)),
+               "ps_plan_config")
+        return int(k.value), int(w.value), int(s.value)
 
     def status(self, stream=None) -> ps_status:
         return ps_read_status(self.ws, stream)

@@ -27,22 +27,23 @@ constexpr int kMaxIv = 5;              // intervals per segment (collinear: 3 fl
 
 enum Role : uint8_t { ROLE_SEG = 0, ROLE_JOIN = 1, ROLE_SCAP = 2, ROLE_ECAP = 3, ROLE_EMPTY = 255 };
 
-// Per-link setup record, written by the count kernel and read by emit.
-// 128 bytes, one per link slot.
+// Per-link record, written by the count kernel and read by emit: everything
+// a rib of the link needs, so the emit kernel stages it in LDS with one load.
 struct alignas(16) LinkRec {
-  uint8_t role;      // Role
-  uint8_t n_iv;      // intervals (segments); 1 for pivots
-  uint8_t kind;      // segment form (segments)
-  uint8_t cap;       // cap style (caps), for square-cap corner radii
-  int32_t path;
-  int32_t seg;       // segment the link belongs to (segments)
+  uint8_t role;           // Role
+  uint8_t n_iv;           // intervals (segments); 1 for pivots
+  uint8_t kind;           // segment form (segments)
+  uint8_t flags;          // bit 0: first link with ribs of its path; bits 4..7: cap style
+  float r;                // half the stroke width
   int32_t dsum[kMaxIv];   // cumulative steps Delta_Sigma(1..n_iv); pivots: dsum[0] = J
+  float w;                // conic weight (conics)
+  float x[4], y[4];       // control points (segments); x[0], y[0]: pivot (joins, caps)
   double p[kMaxIv - 1];   // interior interval boundaries p_1..p_{n_iv-1}
   double psi[kMaxIv + 1]; // unwrapped Psi_0..Psi_{n_iv}; pivots psi[0], psi[1] = psi[0] + delta
-  float px, py;           // pivot point (joins and caps)
-  float pad[2];
 };
-static_assert(sizeof(LinkRec) == 128, "LinkRec must stay 128 bytes");
+static_assert(sizeof(LinkRec) == 144, "LinkRec must stay 144 bytes");
+
+constexpr uint8_t kFirstInPath = 1;
 
 // Device status word kept at the start of the workspace.
 struct DevStatus {

@@ -265,23 +265,25 @@ __device__ inline double seg_end_angle(const ps_batch& B, int i) {
 #pragma clang fp contract(on)
 
 __device__ inline void clear_rec(LinkRec& r) {
-  r.role = ROLE_EMPTY; r.n_iv = 0; r.kind = 0; r.cap = 0; r.path = 0; r.seg = 0;
+  r.role = ROLE_EMPTY; r.n_iv = 0; r.kind = 0; r.flags = 0; r.r = 0; r.w = 1;
   for (int k = 0; k < kMaxIv; ++k) r.dsum[k] = 0;
+  for (int k = 0; k < 4; ++k) { r.x[k] = 0; r.y[k] = 0; }
   for (int k = 0; k < kMaxIv - 1; ++k) r.p[k] = 0;
   for (int k = 0; k <= kMaxIv; ++k) r.psi[k] = 0;
-  r.px = r.py = 0; r.pad[0] = r.pad[1] = 0;
 }
 
 // A pivot link (join or cap) with J steps from psi0 through psi0 + delta.
 __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slot, uint8_t role,
-                                   int path, int seg, double psi0, double delta, int J, float px,
-                                   float py, uint8_t cap) {
+                                   double psi0, double delta, int J, float px, float py,
+                                   uint8_t cap, float half_w, bool first) {
   LinkRec r;
   clear_rec(r);
   r.role = J > 0 ? role : (uint8_t)ROLE_EMPTY;
-  r.n_iv = 1; r.cap = cap; r.path = path; r.seg = seg;
+  r.n_iv = 1;
+  r.flags = (uint8_t)((cap << 4) | ((first && J > 0) ? kFirstInPath : 0));
+  r.r = half_w;
   r.dsum[0] = J; r.psi[0] = psi0; r.psi[1] = psi0 + delta;
-  r.px = px; r.py = py;
+  r.x[0] = px; r.y[0] = py;
   rec[slot] = r;
   link_ribs[slot] = J > 0 ? J + 1 : 0;
 }
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
   if (tid < S) {
     const int i = (int)tid;
     const int p = path_of_seg(B.seg_begin, P, i);
-    const int e = B.seg_begin[p + 1];
+    const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
     const int64_t slot = 2 * (int64_t)i + p + 1;
     const float wd = B.width[p];
     const bool wok = isfinite(wd) && wd > 0;
@@ -301,20 +303,37 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     if (!isfinite(wd)) set_flag(A.st, PS_STATUS_NONFINITE);
     else if (!wok || !sok) set_flag(A.st, PS_STATUS_BAD_VALUE);
     const bool usable = wok && sok && seg_usable(B, i, A.st, true);
+    const float half_w = 0.5f * wd;
     LinkRec r;
     clear_rec(r);
-    r.kind = B.kind[i]; r.path = p; r.seg = i;
+    r.kind = B.kind[i];
+    r.r = half_w;
     int ribs = 0;
     if (usable) {
       const int N = segment_setup(B, i, A.q, r, A.st);
-      if (N > 0) { ribs = N + 1; r.role = ROLE_SEG; }
+      if (N > 0) {
+        ribs = N + 1;
+        r.role = ROLE_SEG;
+        const int npts = npts_of(r.kind);
+        for (int k = 0; k < 4; ++k) {
+          const int kk = k < npts ? k : npts - 1;
+          r.x[k] = B.cx[(int64_t)kk * S + i];
+          r.y[k] = B.cy[(int64_t)kk * S + i];
+        }
+        r.w = (r.kind == PS_KIND_CONIC) ? B.conic_w[i] : 1.0f;
+        // the first link with ribs of the path: no start cap ribs and no
+        // usable segment before this one
+        bool first = cap_steps(B.cap[p], A.q) == 0;
+        for (int k = i - 1; first && k >= b; --k) first = !seg_usable(B, k, A.st, false);
+        if (first) r.flags |= kFirstInPath;
+      }
     }
     A.rec[slot] = r;
     A.link_ribs[slot] = ribs;
     // the join after this segment, or the end cap
     const int64_t jslot = slot + 1;
     if (!usable) {
-      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, p, i, 0, 0, 0, 0, 0, 0);
+      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, 0, 0, 0, 0, 0, 0, half_w, false);
       return;
     }
     const int n = npts_of(B.kind[i]);
@@ -325,11 +344,11 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
       double d = adiff(seg_start_angle(B, k), psi_e);
       if (d == -kPi) d = kPi;   // antiparallel: turn +pi
       const int J = join_steps(B.join[p], d, A.q);
-      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, p, i, psi_e, d, J, ex, ey, 0);
+      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, psi_e, d, J, ex, ey, 0, half_w, false);
       return;
     }
     const int J = cap_steps(B.cap[p], A.q);
-    write_pivot(A.rec, A.link_ribs, jslot, ROLE_ECAP, p, i, psi_e, -kPi, J, ex, ey, B.cap[p]);
+    write_pivot(A.rec, A.link_ribs, jslot, ROLE_ECAP, psi_e, -kPi, J, ex, ey, B.cap[p], half_w, false);
     return;
   }
   if (tid < (int64_t)S + P) {
@@ -345,12 +364,12 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
         const double psi_s = seg_start_angle(B, k);
         const int J = cap_steps(B.cap[p], A.q);
         // start cap: from the reversed start tangent, +pi round to it
-        write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, p, k, psi_s - kPi, kPi, J, B.cx[k], B.cy[k],
-                    B.cap[p]);
+        write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, psi_s - kPi, kPi, J, B.cx[k], B.cy[k],
+                    B.cap[p], 0.5f * wd, true);
         return;
       }
     }
-    write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, p, b, 0, 0, 0, 0, 0, 0);
+    write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, 0, 0, 0, 0, 0, 0, 0.5f * wd, false);
   }
 }
 
@@ -491,7 +510,8 @@ struct EmitArgs {
   unsigned long long* desc;
   DevStatus* st;
   int64_t max_tiles;
-  float fix_tol;   // FP32 roots whose estimated position error exceeds this (px) are re-solved in FP64
+  float fix_tol;   // largest FP64 Newton step accepted on an FP32 root; beyond it the rib is re-solved in FP64
+  unsigned long long zero;   // always 0: the operand of the look-back's read-modify-write reads
 };
 
 __device__ __forceinline__ int link_of(const int64_t* off, int lo, int hi, int64_t r) {
@@ -541,40 +561,31 @@ struct RibOut {
   bool fixed;
 };
 
-// One rib: Eq. func_t / func_N for segments (t from the tangent-angle solve),
-// a pivot for joins and caps, then Eqs. RibVertices-N/P.
-template <int PREC>
-__device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r, RibOut& o) {
-  const LinkRec* rp = A.rec + l;
-  const int j = (int)(r - A.off[l]);
-  const uint8_t role = rp->role;
-  const int path = rp->path;
-  const double rad = 0.5 * (double)A.B.width[path];
-  o.path_start = (r == A.off[2 * (int64_t)A.B.seg_begin[path] + path]);
+// One rib j of a link: Eqs. func_t / func_N for segments (t from the
+// tangent-angle solve), a pivot for joins and caps, then Eqs.
+// RibVertices-N/P.  The record may live in LDS or in global memory.
+template <int PREC, typename Rec>
+__device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol, RibOut& o) {
+  const uint8_t role = rp.role;
+  const double rad = (double)rp.r;
+  o.path_start = (rp.flags & kFirstInPath) && j == 0;
   o.fixed = false;
   double nx = 0, ny = 1;   // n(psi) = (-sin psi, cos psi)
   double rN = rad, rP = rad;
   if (role == ROLE_SEG) {
-    const int seg = rp->seg;
-    const int kind = rp->kind;
-    const int n_iv = rp->n_iv;
-    const int64_t S = A.B.n_segs;
-    const int npts = npts_of(kind);
+    const int kind = rp.kind;
+    const int n_iv = rp.n_iv;
     float X[4], Y[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int kk = k < npts ? k : npts - 1;
-      X[k] = A.B.cx[kk * S + seg];
-      Y[k] = A.B.cy[kk * S + seg];
-    }
-    const float wf = (kind == PS_KIND_CONIC) ? A.B.conic_w[seg] : 1.0f;
+    for (int k = 0; k < 4; ++k) { X[k] = rp.x[k]; Y[k] = rp.y[k]; }
+    const float wf = rp.w;
     // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]
     int k = 1, d0 = 0;
-    while (k < n_iv && j > rp->dsum[k - 1]) { d0 = rp->dsum[k - 1]; ++k; }
-    const int d1 = rp->dsum[k - 1];
-    const double lo = (k == 1) ? 0.0 : rp->p[k - 2];
-    const double hi = (k == n_iv) ? 1.0 : rp->p[k - 1];
-    const double psa = rp->psi[k - 1], psb = rp->psi[k];
+    while (k < n_iv && j > rp.dsum[k - 1]) { d0 = rp.dsum[k - 1]; ++k; }
+    const int d1 = rp.dsum[k - 1];
+    const double lo = (k == 1) ? 0.0 : rp.p[k - 2];
+    const double hi = (k == n_iv) ? 1.0 : rp.p[k - 1];
+    const double psa = rp.psi[k - 1], psb = rp.psi[k];
     double t, psi;
     bool have_n = false;
     if (j == d0) { t = lo; psi = psa; }
@@ -584,7 +595,8 @@ __device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r,
       t = lo;
       if (lo != hi) {
         bool need64 = (PREC == PS_PREC_FP64);
-        if (PREC != PS_PREC_FP64) {
+        if (PREC == PS_PREC_FP32) {
+          // single precision throughout (precision studies only)
           float sn, cs;
           sincosf(reduce_angle<float>(psi), &sn, &cs);
           const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
@@ -592,23 +604,33 @@ __device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r,
           t = (double)so.t;
           nx = -(double)sn; ny = (double)cs;
           have_n = true;
-          if (PREC == PS_PREC_FP32_FIXUP) {
-            // position error of the FP32 root: |g'| dt, with dt from the
-            // rounding of the angle and coefficients over the slope of g'.N
-            const float hn = sqrtf(so.hx * so.hx + so.hy * so.hy);
-            const float sum_e = fabsf(h.e0x) + fabsf(h.e0y) + 2.0f * (fabsf(h.e1x) + fabsf(h.e1y)) +
-                                fabsf(h.e2x) + fabsf(h.e2y);
-            float fk = 3.0f;
-            if (kind == PS_KIND_QUAD) fk = 2.0f;
-            else if (kind == PS_KIND_LINE) fk = 1.0f;
-            else if (kind == PS_KIND_CONIC) {
-              const float u = 1.0f - so.t;
-              const float den = u * u + 2.0f * u * so.t * wf + so.t * so.t;
-              fk = 2.0f / (den * den);
-            }
-            const float dt = (hn + sum_e) * 2.4e-7f / fmaxf(so.dh, 1e-30f) + 6e-8f;
-            const float est = fk * hn * dt;
-            need64 = !so.found || !(est < A.fix_tol);
+        } else if (PREC == PS_PREC_FP32_FIXUP) {
+          // FP64 direction; the FP32 quadratic isolates and selects the root,
+          // one FP64 Newton step on g'(t).N polishes it.  No FP32 root, a
+          // large step or a step out of the interval (a root close to a cusp
+          // or to another root) sends the rib to the FP64 solve.
+          double sn, cs;
+          sincos(psi, &sn, &cs);
+          nx = -sn; ny = cs;
+          have_n = true;
+          const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
+          const SolveOut<float> so =
+              solve_t<float>(h, -(float)sn, (float)cs, (float)cs, (float)sn, (float)lo, (float)hi);
+          if (so.found) {
+            const Hodo<double> hd = hodo_of<double>(kind, X, Y, (double)wf);
+            const double al = hd.e0x * nx + hd.e0y * ny;
+            const double be = hd.e1x * nx + hd.e1y * ny;
+            const double ga = hd.e2x * nx + hd.e2y * ny;
+            const double Aq = al - 2.0 * be + ga, Bq = 2.0 * (be - al);
+            const double t0 = (double)so.t;
+            const double hv = (Aq * t0 + Bq) * t0 + al;
+            const double dv = 2.0 * Aq * t0 + Bq;
+            const double step = (dv != 0.0) ? hv / dv : 0.0;
+            const double t1 = t0 - step;
+            if (fabs(step) <= (double)fix_tol && t1 >= lo && t1 <= hi) t = t1;
+            else need64 = true;
+          } else {
+            need64 = true;
           }
         }
         if (need64) {
@@ -640,8 +662,8 @@ __device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r,
   } else {
     // join or cap: a pivot at a fixed point (Sec. "Tessellation Approach for
     // Caps and Joins"); only the side away from the turn keeps its radius
-    const int J = rp->dsum[0];
-    const double psa = rp->psi[0], psb = rp->psi[1];
+    const int J = rp.dsum[0];
+    const double psa = rp.psi[0], psb = rp.psi[1];
     const double psi = psa + (psb - psa) * (double)j / (double)J;
     if (PREC == PS_PREC_FP64) {
       double sn, cs;
@@ -653,17 +675,39 @@ __device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r,
       nx = -(double)s32; ny = (double)c32;
     }
     double rout = rad;
-    if ((role == ROLE_SCAP || role == ROLE_ECAP) && rp->cap == PS_CAP_SQUARE && (j == 1 || j == 3))
+    if ((role == ROLE_SCAP || role == ROLE_ECAP) && (rp.flags >> 4) == PS_CAP_SQUARE && (j == 1 || j == 3))
       rout = rad * 1.41421356237309504880;
     const bool left_turn = (psb - psa) > 0;
     rN = left_turn ? rout : 0.0;
     rP = left_turn ? 0.0 : rout;
-    o.gx = (double)rp->px; o.gy = (double)rp->py;
+    o.gx = (double)rp.x[0]; o.gy = (double)rp.y[0];
     o.t = 0.0;
     o.chord_ok = false;
   }
   o.Nx = (float)(o.gx - rN * nx); o.Ny = (float)(o.gy - rN * ny);
   o.Px = (float)(o.gx + rP * nx); o.Py = (float)(o.gy + rP * ny);
+}
+
+// Link window staged in LDS, one per wave: kWin consecutive link slots
+// starting at `base`, their offsets and (for links with ribs) their records.
+constexpr int kWin = 64;
+struct WinLDS {
+  long long off[kWin + 1];
+  LinkRec rec[kWin];
+};
+
+// Descriptor words of the look-back are read and written with device-scope
+// read-modify-write atomics: they are performed at the coherence point of
+// the device, so a word published on one XCD is seen on every other XCD
+// without write-backs or invalidations of the per-XCD L2 caches.
+__device__ __forceinline__ void desc_publish(unsigned long long* p, unsigned long long w) {
+  (void)__hip_atomic_exchange(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// `zero` is 0 at run time but opaque to the compiler, which would otherwise
+// turn an idempotent read-modify-write into a plain (non-coherent) load.
+__device__ __forceinline__ unsigned long long desc_read(unsigned long long* p,
+                                                        unsigned long long zero) {
+  return __hip_atomic_fetch_add(p, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Persistent emit.  Tile T covers ribs [T*TS, (T+1)*TS), TS = 64*K - 1; lane
@@ -672,11 +716,16 @@ __device__ __forceinline__ void compute_rib(const EmitArgs& A, int l, int64_t r,
 // claim kTileGroup consecutive tiles per ticket, always in increasing order,
 // so every tile a wave waits on belongs to a wave that is already running.
 //
+// STAGE: link records are staged per wave in LDS (one cooperative load per
+// window of kWin links) instead of being read from global memory per rib.
+//
 // Arc length is accumulated in 64-bit fixed point (2^-32 px per unit): each
 // chord is rounded once and every sum after that is an integer sum, so s does
 // not depend on the tiling, the mapping or the order tiles finish in.
-template <int K, int PREC, bool WXY, bool WS>
+template <int K, int PREC, bool WXY, bool WS, bool STAGE>
 __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
+  extern __shared__ unsigned char smem_raw[];
+  WinLDS& win = reinterpret_cast<WinLDS*>(smem_raw)[STAGE ? (threadIdx.x >> 6) : 0];
   const int lane = threadIdx.x & 63;
   const int64_t L = A.n_links;
   const int64_t R = A.off[L];
@@ -693,6 +742,8 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
       const int64_t r0 = tile * TS;
       const int lhi = A.tile_link[tile + 1];
       int l = A.tile_link[tile];
+      int base = -1;              // first link slot of the staged window (STAGE)
+      long long wend = -1;        // first rib past the staged window
       long long run = 0;          // chord sum since the tile start or its last path start
       bool seen_start = false;
       double cgx = 0, cgy = 0, ct = 0;   // the previous iteration's last rib
@@ -705,9 +756,36 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
         const bool mine = valid && (r >= r0);
         RibOut o;
         o.gx = o.gy = o.t = 0; o.chord_ok = false; o.path_start = false; o.fixed = false;
+        bool staged = false;
+        if (STAGE) {
+          const int64_t rf = (r0 - 1 + 64 * k) < 0 ? 0 : (r0 - 1 + 64 * k);
+          const int64_t rl = (r0 - 1 + 64 * k + 63) < R ? (r0 - 1 + 64 * k + 63) : R - 1;
+          if (rf <= rl && (base < 0 || rl >= wend)) {
+            // (re)stage the window starting at the link of the first rib
+            base = (base < 0) ? l : link_of(A.off, base, lhi, rf);
+            const int64_t idx = (int64_t)base + lane;
+            const long long o_i = idx <= L ? A.off[idx] : LLONG_MAX;
+            const long long o_n = idx + 1 <= L ? A.off[idx + 1] : LLONG_MAX;
+            win.off[lane] = o_i;
+            if (lane == 63) win.off[kWin] = o_n;
+            if (idx < L && o_i < o_n) win.rec[lane] = A.rec[idx];
+            wend = __shfl(o_n, 63, 64);
+          }
+          staged = (rf <= rl) && (rl < wend);
+        }
         if (valid) {
-          l = link_of(A.off, l, lhi, r);
-          compute_rib<PREC>(A, l, r, o);
+          if (staged) {
+            // largest i with off[base + i] <= r, searched in LDS
+            int a = 0, b = kWin - 1;
+            while (a < b) {
+              const int m = (a + b + 1) >> 1;
+              if (win.off[m] <= r) a = m; else b = m - 1;
+            }
+            compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, o);
+          } else {
+            l = link_of(A.off, l, lhi, r);
+            compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, o);
+          }
           if (WXY && mine) {
             *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
             *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
@@ -745,22 +823,18 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
       }
       if (WS) {
         // Decoupled look-back on one 64-bit word per tile (2 state bits, 62
-        // value bits).  The word carries everything a reader needs, so
-        // relaxed device-scope atomics suffice: no cache write-back or
-        // invalidation is needed around them.  A tile holding a path start
-        // publishes its inclusive sum at once, and still looks back when
-        // its first ribs continue a path from earlier tiles.
+        // value bits).  A tile holding a path start publishes its inclusive
+        // sum at once, and still looks back when its first ribs continue a
+        // path from earlier tiles.
         const unsigned long long agg = (unsigned long long)run & kValMask;
         const bool any_need = __ballot(need_prefix != 0) != 0ull;
         unsigned long long prefix = 0;
         if (lane == 0) {
-          __hip_atomic_store(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg,
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          desc_publish(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg);
           if (any_need) {
             int64_t T = tile - 1;
             while (T >= 0) {
-              const unsigned long long w =
-                  __hip_atomic_load(&A.desc[T], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              const unsigned long long w = desc_read(&A.desc[T], A.zero);
               const unsigned stt = (unsigned)(w >> 62);
               if (stt == 0) { __builtin_amdgcn_s_sleep(1); continue; }
               prefix += w & kValMask;
@@ -768,9 +842,7 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
               --T;
             }
           }
-          if (!seen_start)
-            __hip_atomic_store(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (!seen_start) desc_publish(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask));
         }
         const unsigned int plo = __shfl((unsigned int)(prefix & 0xffffffffu), 0, 64);
         const unsigned int phi = __shfl((unsigned int)(prefix >> 32), 0, 64);
@@ -976,6 +1048,7 @@ int fail(int code, const char* fmt, ...) {
 struct EmitConfig {
   int K = 8;
   int waves = 4;
+  int stage = 1;   // 1: link records staged in LDS per wave; 0: read from global memory
 };
 EmitConfig g_cfg;
 std::mutex g_mu;
@@ -1083,48 +1156,54 @@ int do_scan_i32(const int32_t* in, int64_t n_max, const int64_t* n_dev, int64_t*
   return PS_OK;
 }
 
-template <int K, int PREC, bool WXY, bool WS>
+template <int K, int PREC, bool WXY, bool WS, bool STAGE>
 void emit_launcher(EmitArgs a, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL((emit_kernel<K, PREC, WXY, WS>), dim3(grid), dim3(block), 0, s, a);
+  const size_t lds = STAGE ? (size_t)(block / 64) * sizeof(WinLDS) : 0;
+  hipLaunchKernelGGL((emit_kernel<K, PREC, WXY, WS, STAGE>), dim3(grid), dim3(block), lds, s, a);
 }
 
 using EmitLaunch = void (*)(EmitArgs, int, int, hipStream_t);
 
-template <int PREC, bool WXY, bool WS>
+template <int PREC, bool WXY, bool WS, bool STAGE>
 EmitLaunch pick_k(int K) {
   switch (K) {
-    case 2: return emit_launcher<2, PREC, WXY, WS>;
-    case 4: return emit_launcher<4, PREC, WXY, WS>;
-    case 8: return emit_launcher<8, PREC, WXY, WS>;
-    case 16: return emit_launcher<16, PREC, WXY, WS>;
+    case 4: return emit_launcher<4, PREC, WXY, WS, STAGE>;
+    case 8: return emit_launcher<8, PREC, WXY, WS, STAGE>;
+    case 16: return emit_launcher<16, PREC, WXY, WS, STAGE>;
     default: return nullptr;
   }
 }
 
-template <bool WXY, bool WS>
+template <bool WXY, bool WS, bool STAGE>
 EmitLaunch pick_prec(int prec, int K) {
   switch (prec) {
-    case PS_PREC_FP32: return pick_k<PS_PREC_FP32, WXY, WS>(K);
-    case PS_PREC_FP32_FIXUP: return pick_k<PS_PREC_FP32_FIXUP, WXY, WS>(K);
-    default: return pick_k<PS_PREC_FP64, WXY, WS>(K);
+    case PS_PREC_FP32: return pick_k<PS_PREC_FP32, WXY, WS, STAGE>(K);
+    case PS_PREC_FP32_FIXUP: return pick_k<PS_PREC_FP32_FIXUP, WXY, WS, STAGE>(K);
+    default: return pick_k<PS_PREC_FP64, WXY, WS, STAGE>(K);
   }
 }
 
-EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws) {
-  if (wxy && ws) return pick_prec<true, true>(prec, K);
-  if (wxy) return pick_prec<true, false>(prec, K);
-  return pick_prec<false, true>(prec, K);
+template <bool STAGE>
+EmitLaunch pick_mode(int prec, int K, bool wxy, bool ws) {
+  if (wxy && ws) return pick_prec<true, true, STAGE>(prec, K);
+  if (wxy) return pick_prec<true, false, STAGE>(prec, K);
+  return pick_prec<false, true, STAGE>(prec, K);
 }
 
-bool valid_k(int K) { return K == 2 || K == 4 || K == 8 || K == 16; }
+EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws, bool stage) {
+  return stage ? pick_mode<true>(prec, K, wxy, ws) : pick_mode<false>(prec, K, wxy, ws);
+}
 
-// Estimated FP32 position error (px) above which a rib is re-solved in FP64.
-// PS_FIXUP_TOL overrides it, for precision studies.
+bool valid_k(int K) { return K == 4 || K == 8 || K == 16; }
+
+// Largest Newton step (in t) accepted when polishing an FP32 root in FP64;
+// a larger step means the FP32 root was ill-conditioned and the rib is
+// re-solved in FP64.  PS_FIXUP_TOL overrides it, for precision studies.
 float fixup_tolerance() {
   static float tol = [] {
     const char* e = getenv("PS_FIXUP_TOL");
     const float v = e ? (float)atof(e) : 0.0f;
-    return v > 0 ? v : 4e-4f;
+    return v > 0 ? v : 1e-4f;
   }();
   return tol;
 }
@@ -1143,10 +1222,10 @@ int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, cons
 
 int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float* vx, float* vy,
                 float* vs, int64_t cap, const WsView& v, const WsLayout& w, int K, int waves,
-                hipStream_t s) {
+                int stage, hipStream_t s) {
   const int64_t L = n_links_of(b);
   const int TS = 64 * K - 1;
-  EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr);
+  EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr, stage != 0);
   if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", K);
   hipLaunchKernelGGL(emit_prepare_kernel, dim3(256), dim3(256), 0, s, off, L, TS, v.tile_link,
                      v.desc, v.st, cap, w.max_tiles);
@@ -1155,6 +1234,7 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
   a.max_tiles = w.max_tiles;
   a.fix_tol = fixup_tolerance();
+  a.zero = 0ull;
   if (waves < 1 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   const int block = 64 * waves;   // never above the kernel's launch bound of 256
   const int grid = num_cus() * (16 / waves);
@@ -1210,7 +1290,7 @@ struct ps_plan {
   int64_t dash_rib_cap, dash_cap;
   void* ws;
   WsLayout w;
-  int K, waves;
+  int K, waves, stage;
   hipGraph_t graph;
   hipGraphExec_t exec;
 };
@@ -1223,7 +1303,8 @@ int enqueue_chain(ps_plan* P, hipStream_t s) {
   if ((rc = launch_count(&P->b, &P->p, P->link_ribs, v, s))) return rc;
   if ((rc = do_scan_i32(P->link_ribs, n_links_of(&P->b), nullptr, P->off, v.scan, &v.st->total_ribs, s)))
     return rc;
-  if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->K, P->waves, s)))
+  if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->K, P->waves,
+                        P->stage, s)))
     return rc;
   if (P->p.n_dash > 0) {
     if ((rc = launch_dash(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->dx, P->dy, P->ds, P->range,
@@ -1233,16 +1314,16 @@ int enqueue_chain(ps_plan* P, hipStream_t s) {
   return PS_OK;
 }
 
-int time_emit(ps_plan* P, int K, int waves, hipStream_t s, float* ms) {
+int time_emit(ps_plan* P, int K, int waves, int stage, hipStream_t s, float* ms) {
   const WsView v = ws_view(P->ws, P->w);
   hipEvent_t e0, e1;
   PS_HIP(hipEventCreate(&e0));
   PS_HIP(hipEventCreate(&e1));
-  int rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, s);
+  int rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, stage, s);
   float best = 1e30f;
   for (int rep = 0; rep < 3 && rc == PS_OK; ++rep) {
     (void)hipEventRecord(e0, s);
-    rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, s);
+    rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, stage, s);
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float t = 0;
@@ -1277,12 +1358,14 @@ size_t ps_workspace_bytes(const ps_batch* b, const ps_params* p, int64_t vertex_
   return ws_layout(n_links_of(b), std::max<int64_t>(0, vertex_capacity), nd).total;
 }
 
-int ps_set_emit_config(int32_t K, int32_t waves) {
-  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 2, 4, 8 or 16");
+int ps_set_emit_config(int32_t K, int32_t waves, int32_t stage) {
+  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 4, 8 or 16");
   if (waves < 0 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
+  if (stage < -1 || stage > 1) return fail(PS_E_ARG, "stage must be -1 (keep), 0 or 1");
   std::lock_guard<std::mutex> lk(g_mu);
   if (K) g_cfg.K = K;
   if (waves) g_cfg.waves = waves;
+  if (stage >= 0) g_cfg.stage = stage;
   return PS_OK;
 }
 
@@ -1316,7 +1399,8 @@ int ps_emit(const ps_batch* b, const ps_params* p, const int64_t* offsets, float
   const WsLayout w = ws_layout(n_links_of(b), cap, 0);
   if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
   const EmitConfig c = current_cfg();
-  return launch_emit(b, p, offsets, vx, vy, vs, cap, ws_view(ws, w), w, c.K, c.waves, (hipStream_t)stream);
+  return launch_emit(b, p, offsets, vx, vy, vs, cap, ws_view(ws, w), w, c.K, c.waves, c.stage,
+                     (hipStream_t)stream);
 }
 
 int ps_arclen(const ps_batch* b, const ps_params* p, const int64_t* offsets, float* vs, int64_t cap,
@@ -1329,7 +1413,7 @@ int ps_arclen(const ps_batch* b, const ps_params* p, const int64_t* offsets, flo
   if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
   const EmitConfig c = current_cfg();
   return launch_emit(b, p, offsets, nullptr, nullptr, vs, cap, ws_view(ws, w), w, c.K, c.waves,
-                     (hipStream_t)stream);
+                     c.stage, (hipStream_t)stream);
 }
 
 int ps_dash(const ps_batch* b, const ps_params* p, const int64_t* offsets, const float* vx,
@@ -1385,9 +1469,10 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   P->ws = ws; P->w = w;
   P->graph = nullptr; P->exec = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  // autotune the emit mapping on this batch
+  // autotune the emit mapping on this batch: ribs per lane K, waves per
+  // workgroup, and whether link records are staged in LDS
   const EmitConfig c0 = current_cfg();
-  P->K = c0.K; P->waves = c0.waves;
+  P->K = c0.K; P->waves = c0.waves; P->stage = c0.stage;
   const WsView v = ws_view(ws, w);
   if ((rc = launch_count(b, &P->p, link_ribs, v, s)) ||
       (rc = do_scan_i32(link_ribs, n_links_of(b), nullptr, offsets, v.scan, &v.st->total_ribs, s))) {
@@ -1395,14 +1480,15 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
     return rc;
   }
   float best = 1e30f;
-  const int Ks[4] = {2, 4, 8, 16};
+  const int Ks[3] = {4, 8, 16};
   const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
-  for (int ki = 0; ki < 4; ++ki)
-    for (int wi = 0; wi < 3; ++wi) {
-      float ms = 0;
-      if ((rc = time_emit(P, Ks[ki], Ws[wi], s, &ms))) { delete P; return rc; }
-      if (ms < best) { best = ms; P->K = Ks[ki]; P->waves = Ws[wi]; }
-    }
+  for (int st = 1; st >= 0; --st)
+    for (int ki = 0; ki < 3; ++ki)
+      for (int wi = 0; wi < 3; ++wi) {
+        float ms = 0;
+        if ((rc = time_emit(P, Ks[ki], Ws[wi], st, s, &ms))) { delete P; return rc; }
+        if (ms < best) { best = ms; P->K = Ks[ki]; P->waves = Ws[wi]; P->stage = st; }
+      }
   // capture the chain into one graph
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete P; return fail(PS_E_HIP, "stream"); }
@@ -1437,10 +1523,11 @@ int ps_plan_destroy(ps_plan* P) {
   return PS_OK;
 }
 
-int ps_plan_config(const ps_plan* P, int32_t* K, int32_t* waves) {
+int ps_plan_config(const ps_plan* P, int32_t* K, int32_t* waves, int32_t* stage) {
   if (!P) return fail(PS_E_ARG, "invalid plan");
   if (K) *K = P->K;
   if (waves) *waves = P->waves;
+  if (stage) *stage = P->stage;
   return PS_OK;
 }
 

@@ -85,10 +85,11 @@ def test_bad_precision_and_emit_config_rejected():
     b = _batch()
     p = ps.make_params(0.1, precision=7)
     assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(3, 4) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(8, 99) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(8, 5) == ps.PS_E_ARG   # above the 256-thread launch bound
-    assert lib.ps_set_emit_config(0, 0) == ps.PS_OK
+    assert lib.ps_set_emit_config(3, 4, -1) == ps.PS_E_ARG
+    assert lib.ps_set_emit_config(8, 99, -1) == ps.PS_E_ARG
+    assert lib.ps_set_emit_config(8, 5, -1) == ps.PS_E_ARG   # above the 256-thread launch bound
+    assert lib.ps_set_emit_config(8, 4, 2) == ps.PS_E_ARG
+    assert lib.ps_set_emit_config(0, 0, -1) == ps.PS_OK
 
 
 def test_plan_rejects_null_buffers():

@@ -155,16 +155,17 @@ def test_mappings_agree_and_are_deterministic():
     b = W.config2(n_paths=48, max_segs=96)
     outs = []
     try:
-        for K in (2, 4, 8, 16):
-            for waves in (1, 4):
-                ps.ps_set_emit_config(K, waves)
-                _, o = _gpu(b)
-                outs.append((K, waves, _np(o["vx"]), _np(o["vy"]), _np(o["vs"])))
+        for stage in (1, 0):
+            for K in (4, 8, 16):
+                for waves in (1, 4):
+                    ps.ps_set_emit_config(K, waves, stage)
+                    _, o = _gpu(b)
+                    outs.append(((K, waves, stage), _np(o["vx"]), _np(o["vy"]), _np(o["vs"])))
     finally:
-        ps.ps_set_emit_config(8, 4)
-    for K, w, vx, vy, vs in outs[1:]:
-        assert np.array_equal(vx, outs[0][2]) and np.array_equal(vy, outs[0][3]), (K, w)
-        assert np.array_equal(vs, outs[0][4]), (K, w)
+        ps.ps_set_emit_config(8, 4, 1)
+    for cfg, vx, vy, vs in outs[1:]:
+        assert np.array_equal(vx, outs[0][1]) and np.array_equal(vy, outs[0][2]), cfg
+        assert np.array_equal(vs, outs[0][3]), cfg
 
 
 def test_arclen_only_matches_emit():
@@ -211,6 +212,16 @@ def test_dash_config3_unique_quantities():
 
 
 # ------------------------------------------------------------------ plan / graph
+def test_small_links_overflow_the_lds_window():
+    # single-segment paths with butt caps and many zero-length segments: a
+    # 64-rib iteration then spans more than 64 link slots, so the emit falls
+    # back from the LDS window to global reads for it
+    segs = [[(W.KIND_L, [(0, 0), (0, 0)], 1.0)] * 40 + [(W.KIND_L, [(0, 0), (3, 1)], 1.0)]
+            + [(W.KIND_L, [(3, 1), (3, 1)], 1.0)] * 40 for _ in range(30)]
+    b = W.paths(segs, widths=[1.0] * 30, q=math.pi / 4, caps=[W.CAP_BUTT] * 30)
+    _compare(b)
+
+
 def test_plan_graph_replays_match_eager():
     import torch
     b = W.config2(n_paths=40, max_segs=64)
