@@ -215,7 +215,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32" if prec == ps.PS_PREC_FP32 else ("f64" if prec == ps.PS_PREC_FP64 else "f32+f64"),
         "data": "synthetic",
-        "fixup_tolerance_px": float(os.environ.get("PS_FIXUP_TOL", "4e-4")),
+        "fixup_newton_step_tol": float(os.environ.get("PS_FIXUP_TOL", "1e-4")),
         "config": {"workload": "batched: 4096 paths, log-uniform [1,512] segments, 60/25/15% C/Q/K, "
                                "q=pi/64, round joins, butt caps",
                    "paths": b.n_paths, "segments": b.n_segs, "ribs": R, "vertices": V,

@@ -195,6 +195,40 @@ __device__ __forceinline__ double cubic_curv(double X, double Y, double Z, doubl
 
 #pragma clang fp contract(on)
 
+// sin and cos of an unwrapped tangent angle in FP64 (|x| < 2^20; the angles
+// here stay within a few turns).  x = k pi/2 + y with pi/2 split in three
+// parts, the first two of 33 significant bits so that k P1 and k P2 are exact,
+// then the Taylor series of sin (to y^17) and cos (to y^16) on |y| <= pi/4,
+// whose truncation errors there are below 3e-18.
+__device__ __forceinline__ void sincos_rd(double x, double* s, double* c) {
+  const double P1 = 1.5707963267341256, P2 = 6.077100506303966e-11, P3 = 2.0222662487959506e-21;
+  const double k = rint(x * 0.6366197723675814);
+  const double y = ((x - k * P1) - k * P2) - k * P3;
+  const double z = y * y;
+  double ps = 2.8114572543455206e-15;       //  1/17!
+  ps = ps * z - 7.647163731819816e-13;      // -1/15!
+  ps = ps * z + 1.6059043836821613e-10;     //  1/13!
+  ps = ps * z - 2.505210838544172e-08;      // -1/11!
+  ps = ps * z + 2.7557319223985893e-06;     //  1/9!
+  ps = ps * z - 1.984126984126984e-04;      // -1/7!
+  ps = ps * z + 8.333333333333333e-03;      //  1/5!
+  ps = ps * z - 1.6666666666666666e-01;     // -1/3!
+  const double sn = y + y * z * ps;
+  double pc = 4.779477332387385e-14;        //  1/16!
+  pc = pc * z - 1.1470745597729725e-11;     // -1/14!
+  pc = pc * z + 2.08767569878681e-09;       //  1/12!
+  pc = pc * z - 2.755731922398589e-07;      // -1/10!
+  pc = pc * z + 2.48015873015873e-05;       //  1/8!
+  pc = pc * z - 1.388888888888889e-03;      // -1/6!
+  pc = pc * z + 4.1666666666666664e-02;     //  1/4!
+  pc = pc * z - 0.5;                        // -1/2!
+  const double cs = 1.0 + z * pc;
+  const int q = (int)k & 3;
+  const double s0 = (q & 1) ? cs : sn, c0 = (q & 1) ? sn : cs;
+  *s = (q & 2) ? -s0 : s0;
+  *c = ((q + 1) & 2) ? -c0 : c0;
+}
+
 // ===========================================================================
 // Hodograph and the tangent-angle solve (Eq. angle2t), FP32 or FP64
 // ===========================================================================

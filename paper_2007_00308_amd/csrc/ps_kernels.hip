@@ -38,7 +38,6 @@ constexpr int kScanTile = kScanThreads * kScanItems;  // 4096 items per block
 constexpr int kMinTileRibs = 64 * 1 - 1;              // smallest emit tile (K = 1)
 constexpr double kFix = 4294967296.0;                 // arc length in fixed point: 2^-32 px
 constexpr unsigned long long kValMask = (1ull << 62) - 1;
-constexpr int kTileGroup = 4;                         // tiles claimed per ticket
 constexpr int kMaxDash = 64;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -610,7 +609,7 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
           // large step or a step out of the interval (a root close to a cusp
           // or to another root) sends the rib to the FP64 solve.
           double sn, cs;
-          sincos(psi, &sn, &cs);
+          sincos_rd(psi, &sn, &cs);
           nx = -sn; ny = cs;
           have_n = true;
           const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
@@ -635,7 +634,7 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
         }
         if (need64) {
           double sn, cs;
-          sincos(psi, &sn, &cs);
+          sincos_rd(psi, &sn, &cs);
           const Hodo<double> h = hodo_of<double>(kind, X, Y, (double)wf);
           const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, lo, hi);
           t = so.t;
@@ -648,7 +647,7 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
     if (!have_n) {
       if (PREC == PS_PREC_FP64) {
         double sn, cs;
-        sincos(psi, &sn, &cs);
+        sincos_rd(psi, &sn, &cs);
         nx = -sn; ny = cs;
       } else {
         float s32, c32;
@@ -667,7 +666,7 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
     const double psi = psa + (psb - psa) * (double)j / (double)J;
     if (PREC == PS_PREC_FP64) {
       double sn, cs;
-      sincos(psi, &sn, &cs);
+      sincos_rd(psi, &sn, &cs);
       nx = -sn; ny = cs;
     } else {
       float s32, c32;
@@ -713,8 +712,11 @@ __device__ __forceinline__ unsigned long long desc_read(unsigned long long* p,
 // Persistent emit.  Tile T covers ribs [T*TS, (T+1)*TS), TS = 64*K - 1; lane
 // slot (k, lane) handles rib T*TS - 1 + 64k + lane, so slot (0,0) re-reads the
 // previous tile's last rib for the first chord and stores nothing.  Waves
-// claim kTileGroup consecutive tiles per ticket, always in increasing order,
-// so every tile a wave waits on belongs to a wave that is already running.
+// claim one tile per ticket, in increasing order, so every tile a wave waits
+// on belongs to a wave that is already running.  A ticket is a single tile on
+// purpose: a wave holding several consecutive tiles would publish the last of
+// them only after the look-backs of the others, and the next wave's first tile
+// waits on exactly that one, which chains all waves into one sequence.
 //
 // STAGE: link records are staged per wave in LDS (one cooperative load per
 // window of kWin links) instead of being read from global memory per rib.
@@ -722,10 +724,18 @@ __device__ __forceinline__ unsigned long long desc_read(unsigned long long* p,
 // Arc length is accumulated in 64-bit fixed point (2^-32 px per unit): each
 // chord is rounded once and every sum after that is an integer sum, so s does
 // not depend on the tiling, the mapping or the order tiles finish in.
+// Dynamic LDS per wave: the link window (STAGE) and the in-tile arc-length
+// sums of its K x 64 rib slots (WS), kept until the tile's prefix is known.
+__host__ __device__ constexpr size_t emit_lds_per_wave(int K, bool ws, bool stage) {
+  return (stage ? sizeof(WinLDS) : 0) + (ws ? (size_t)K * 64 * sizeof(long long) : 0);
+}
+
 template <int K, int PREC, bool WXY, bool WS, bool STAGE>
 __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
   extern __shared__ unsigned char smem_raw[];
-  WinLDS& win = reinterpret_cast<WinLDS*>(smem_raw)[STAGE ? (threadIdx.x >> 6) : 0];
+  unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_lds_per_wave(K, WS, STAGE);
+  WinLDS& win = *reinterpret_cast<WinLDS*>(wave_lds);
+  long long* srel = reinterpret_cast<long long*>(wave_lds + (STAGE ? sizeof(WinLDS) : 0));
   const int lane = threadIdx.x & 63;
   const int64_t L = A.n_links;
   const int64_t R = A.off[L];
@@ -736,9 +746,9 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
   for (;;) {
     unsigned int tk = 0;
     if (lane == 0) tk = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
-    const int64_t first_tile = (int64_t)__shfl(tk, 0, 64) * kTileGroup;
-    if (first_tile >= n_tiles) break;
-    for (int64_t tile = first_tile; tile < first_tile + kTileGroup && tile < n_tiles; ++tile) {
+    const int64_t tile = (int64_t)__shfl(tk, 0, 64);
+    if (tile >= n_tiles) break;
+    {
       const int64_t r0 = tile * TS;
       const int lhi = A.tile_link[tile + 1];
       int l = A.tile_link[tile];
@@ -747,9 +757,8 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
       long long run = 0;          // chord sum since the tile start or its last path start
       bool seen_start = false;
       double cgx = 0, cgy = 0, ct = 0;   // the previous iteration's last rib
-      long long srel[K];
       unsigned int need_prefix = 0;
-#pragma unroll
+#pragma unroll 1
       for (int k = 0; k < K; ++k) {
         const int64_t r = r0 - 1 + 64 * k + lane;
         const bool valid = (r >= 0) && (r < R);
@@ -774,6 +783,8 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
           staged = (rf <= rl) && (rl < wend);
         }
         if (valid) {
+          const LinkRec* rp;
+          int j;
           if (staged) {
             // largest i with off[base + i] <= r, searched in LDS
             int a = 0, b = kWin - 1;
@@ -781,11 +792,14 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
               const int m = (a + b + 1) >> 1;
               if (win.off[m] <= r) a = m; else b = m - 1;
             }
-            compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, o);
+            rp = &win.rec[a];
+            j = (int)(r - win.off[a]);
           } else {
             l = link_of(A.off, l, lhi, r);
-            compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, o);
+            rp = &A.rec[l];
+            j = (int)(r - A.off[l]);
           }
+          compute_rib<PREC>(*rp, j, A.fix_tol, o);
           if (WXY && mine) {
             *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
             *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
@@ -812,7 +826,7 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
               f = f | fu;
             }
           }
-          srel[k] = f ? c : run + c;
+          srel[k * 64 + lane] = f ? c : run + c;
           if (!(f || seen_start)) need_prefix |= (1u << k);
           const long long c63 = __shfl(c, 63, 64);
           const int f63 = __shfl(f, 63, 64);
@@ -822,36 +836,43 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
         }
       }
       if (WS) {
-        // Decoupled look-back on one 64-bit word per tile (2 state bits, 62
-        // value bits).  A tile holding a path start publishes its inclusive
-        // sum at once, and still looks back when its first ribs continue a
-        // path from earlier tiles.
+        // Decoupled look-back on one 64-bit word per tile (2 state bits: 1 =
+        // tile sum, 2 = sum since the last path start up to the tile's end; 62
+        // value bits).  A tile holding a path start publishes its inclusive sum
+        // at once, and still looks back when its first ribs continue a path
+        // from earlier tiles.  The whole wave looks back: lane i reads tile
+        // base - i, 64 predecessors per round trip.
         const unsigned long long agg = (unsigned long long)run & kValMask;
         const bool any_need = __ballot(need_prefix != 0) != 0ull;
+        if (lane == 0) desc_publish(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg);
         unsigned long long prefix = 0;
-        if (lane == 0) {
-          desc_publish(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg);
-          if (any_need) {
-            int64_t T = tile - 1;
-            while (T >= 0) {
-              const unsigned long long w = desc_read(&A.desc[T], A.zero);
-              const unsigned stt = (unsigned)(w >> 62);
-              if (stt == 0) { __builtin_amdgcn_s_sleep(1); continue; }
-              prefix += w & kValMask;
-              if (stt == 2) break;
-              --T;
-            }
-          }
-          if (!seen_start) desc_publish(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask));
-        }
-        const unsigned int plo = __shfl((unsigned int)(prefix & 0xffffffffu), 0, 64);
-        const unsigned int phi = __shfl((unsigned int)(prefix >> 32), 0, 64);
-        const long long pre = (long long)(((unsigned long long)phi << 32) | plo);
+        if (any_need) {
+          int64_t base = tile - 1;
+          for (;;) {
+            const int64_t Ti = base - lane;
+            // before tile 0 every path has started: an inclusive zero
+            const unsigned long long w = Ti >= 0 ? desc_read(&A.desc[Ti], A.zero) : (2ull << 62);
+            const unsigned stt = (unsigned)(w >> 62);
+            const unsigned long long incl = __ballot(stt == 2);
+            const int stop = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive word
+            const unsigned long long upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
+            if (__ballot(stt == 0) & upto) { __builtin_amdgcn_s_sleep(1); continue; }
+            unsigned long long v = lane <= stop ? (w & kValMask) : 0ull;
 #pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+            prefix += v;
+            if (stop < 64) break;
+            base -= 64;
+          }
+          if (lane == 0 && !seen_start)
+            desc_publish(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask));
+        }
+        const long long pre = (long long)prefix;
         for (int k = 0; k < K; ++k) {
           const int64_t r = r0 - 1 + 64 * k + lane;
           if (r >= r0 && r < R) {
-            const long long sf = ((need_prefix >> k) & 1u) ? pre + srel[k] : srel[k];
+            const long long sr = srel[k * 64 + lane];
+            const long long sf = ((need_prefix >> k) & 1u) ? pre + sr : sr;
             const float s = (float)((double)sf * (1.0 / kFix));
             *reinterpret_cast<float2*>(A.vs + 2 * r) = make_float2(s, s);
           }
@@ -1158,7 +1179,13 @@ int do_scan_i32(const int32_t* in, int64_t n_max, const int64_t* n_dev, int64_t*
 
 template <int K, int PREC, bool WXY, bool WS, bool STAGE>
 void emit_launcher(EmitArgs a, int grid, int block, hipStream_t s) {
-  const size_t lds = STAGE ? (size_t)(block / 64) * sizeof(WinLDS) : 0;
+  const size_t lds = (size_t)(block / 64) * emit_lds_per_wave(K, WS, STAGE);
+  // above 64 KiB of dynamic LDS the kernel has to be allowed it once (every
+  // configuration is first launched eagerly, before any graph capture)
+  static const hipError_t allowed = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&emit_kernel<K, PREC, WXY, WS, STAGE>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * emit_lds_per_wave(K, WS, STAGE)));
+  (void)allowed;
   hipLaunchKernelGGL((emit_kernel<K, PREC, WXY, WS, STAGE>), dim3(grid), dim3(block), lds, s, a);
 }
 
