@@ -43,10 +43,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32_fixup", choices=["fp32", "fp32_fixup", "fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp32_fixup", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-per-path", action="store_true", help="skip the per-path form")
     ap.add_argument("--profile", action="store_true", help="few steps, no oracle (for rocprofv3)")
+    ap.add_argument("--emit-config", default=None, metavar="K,W,S",
+                    help="fixed emit mapping (ribs per lane, waves per group, LDS staging) "
+                         "instead of the plan's autotuning, e.g. for profiles of one mapping")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--study", choices=["precision", "c3", "c5"], default=None,
@@ -85,7 +88,12 @@ def main() -> int:
     del first
     torch.cuda.synchronize()
 
+    if args.emit_config:
+        k_, w_, s_ = (int(x) for x in args.emit_config.split(","))
+        ps.ps_set_emit_config(k_, w_, s_)
+        ps.ps_set_plan_autotune(False)
     plan = ps.Plan(db, b.q, vertex_capacity=cap, precision=prec)
+    ps.ps_set_plan_autotune(True)
     K, waves, stage = plan.config()
     log(f"plan: autotuned emit mapping K={K} waves/group={waves} lds-staged={stage}")
     stream = torch.cuda.current_stream()

@@ -46,11 +46,15 @@ enum { PS_KIND_LINE = 0, PS_KIND_QUAD = 1, PS_KIND_CONIC = 2, PS_KIND_CUBIC = 3 
 enum { PS_JOIN_NONE = 0, PS_JOIN_BEVEL = 1, PS_JOIN_ROUND = 2, PS_JOIN_TRIANGLE = 3 };
 /* Cap styles (Secs. "Easy Caps", "Harder Caps"): J = 0, ceil(pi/q), 4, 2. */
 enum { PS_CAP_BUTT = 0, PS_CAP_ROUND = 1, PS_CAP_SQUARE = 2, PS_CAP_TRIANGLE = 3 };
-/* Arithmetic of the per-rib tangent-angle solve (Eq. angle2t):
- *   FP32        single precision only;
- *   FP32_FIXUP  single precision, re-solved in double where the FP32 answer
- *               is ill-conditioned (default);
- *   FP64        double precision for every rib. */
+/* Arithmetic of the per-rib direction and tangent-angle solve (Eq. angle2t);
+ * the setup (ps_count), the point evaluation and the arc length are FP64 in
+ * every mode:
+ *   FP32        single precision direction and solve (studies only);
+ *   FP32_FIXUP  FP64 direction, FP32 root isolation polished by one FP64
+ *               Newton step, re-solved in FP64 where that is ill-conditioned;
+ *   FP64        double precision for every rib (recommended: on gfx950 the
+ *               FP64 vector rate equals the unpacked FP32 rate, and it is the
+ *               shortest instruction path). */
 enum { PS_PREC_FP32 = 0, PS_PREC_FP32_FIXUP = 1, PS_PREC_FP64 = 2 };
 
 enum {
@@ -227,6 +231,14 @@ int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_p
  * current value.  Output bits do not depend on the mapping.
  */
 int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group, int32_t stage);
+
+/*
+ * Whether ps_plan_create times the emit mappings (on = 1, the default) or
+ * takes the current ps_set_emit_config mapping as is (0), e.g. so that a
+ * profile of the plan holds only the launches of one mapping.  Other values
+ * are rejected with PS_E_ARG.
+ */
+int ps_set_plan_autotune(int32_t on);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* ps_last_error(void);

@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
         "ps_plan_destroy": (ctypes.c_int, [_vp]),
         "ps_plan_config": (ctypes.c_int, [_vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
         "ps_set_emit_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+        "ps_set_plan_autotune": (ctypes.c_int, [ctypes.c_int32]),
         "ps_last_error": (ctypes.c_char_p, []),
         "ps_version": (ctypes.c_char_p, []),
     }
@@ -142,7 +143,7 @@ class DeviceBatch:
                                _ptr(self.join), _ptr(self.cap))
 
 
-def make_params(q: float, precision: int = PS_PREC_FP32_FIXUP, dash=(), dash_phase: float = 0.0):
+def make_params(q: float, precision: int = PS_PREC_FP64, dash=(), dash_phase: float = 0.0):
     arr = (ctypes.c_double * max(1, len(dash)))(*dash) if len(dash) else None
     p = ps_params(float(q), int(precision), len(dash), ctypes.cast(arr, _vp) if arr else None,
                   float(dash_phase))
@@ -203,6 +204,10 @@ def ps_set_emit_config(ribs_per_lane: int = 0, waves_per_group: int = 0, stage: 
            "ps_set_emit_config")
 
 
+def ps_set_plan_autotune(on: bool):
+    _check(load().ps_set_plan_autotune(1 if on else 0), "ps_set_plan_autotune")
+
+
 def ps_version() -> str:
     return load().ps_version().decode()
 
@@ -218,7 +223,7 @@ def alloc_workspace(nbytes: int, device="cuda"):
 # ----------------------------------------------------------------------------
 # Convenience: the whole chain, with the rib total read back once
 # ----------------------------------------------------------------------------
-def stroke(db: DeviceBatch, q: float, precision: int = PS_PREC_FP32_FIXUP, vertex_capacity=None,
+def stroke(db: DeviceBatch, q: float, precision: int = PS_PREC_FP64, vertex_capacity=None,
            with_arclen: bool = True, dash=(), dash_phase: float = 0.0, stream=None) -> dict:
     """count -> scan -> (read total) -> emit [-> dash]; returns device tensors."""
     import torch
@@ -264,7 +269,7 @@ class Plan:
     """ps_plan_create / ps_plan_launch / ps_plan_destroy around owned buffers."""
 
     def __init__(self, db: DeviceBatch, q: float, vertex_capacity: int,
-                 precision: int = PS_PREC_FP32_FIXUP, dash=(), dash_phase: float = 0.0,
+                 precision: int = PS_PREC_FP64, dash=(), dash_phase: float = 0.0,
                  dash_rib_capacity: int = 0, dash_capacity: int = 0, stream=None):
         import torch
         dev = db.seg_begin.device

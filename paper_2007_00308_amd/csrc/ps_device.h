@@ -77,29 +77,29 @@ __device__ inline Seg load_seg(const ps_batch& B, int i) {
   s.kind = B.kind[i];
   s.npts = npts_of(s.kind);
   const int64_t S = B.n_segs;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (k < s.npts) {
-      s.x[k] = (double)B.cx[k * S + i];
-      s.y[k] = (double)B.cy[k * S + i];
-    } else {
-      s.x[k] = s.x[s.npts - 1];
-      s.y[k] = s.y[s.npts - 1];
-    }
-  }
+  // points past the last one repeat it (constant indices only)
+  s.x[0] = (double)B.cx[i];         s.y[0] = (double)B.cy[i];
+  s.x[1] = (double)B.cx[S + i];     s.y[1] = (double)B.cy[S + i];
+  s.x[2] = s.npts > 2 ? (double)B.cx[2 * S + i] : s.x[1];
+  s.y[2] = s.npts > 2 ? (double)B.cy[2 * S + i] : s.y[1];
+  s.x[3] = s.npts > 3 ? (double)B.cx[3 * S + i] : s.x[2];
+  s.y[3] = s.npts > 3 ? (double)B.cy[3 * S + i] : s.y[2];
   s.w = (s.kind == PS_KIND_CONIC) ? (double)B.conic_w[i] : 1.0;
   return s;
 }
 
+// (the padded points repeat the last one, so all four can be tested)
 __device__ __forceinline__ bool seg_is_point(const Seg& s) {
   bool same = true;
-  for (int k = 1; k < s.npts; ++k) same = same && s.x[k] == s.x[0] && s.y[k] == s.y[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k) same = same && s.x[k] == s.x[0] && s.y[k] == s.y[0];
   return same;
 }
 
 __device__ __forceinline__ bool seg_finite(const Seg& s) {
   bool ok = isfinite(s.w);
-  for (int k = 0; k < s.npts; ++k) ok = ok && isfinite(s.x[k]) && isfinite(s.y[k]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ok = ok && isfinite(s.x[k]) && isfinite(s.y[k]);
   return ok;
 }
 
@@ -129,9 +129,10 @@ __device__ inline void start_dir(const Seg& s, double& dx, double& dy) {
 }
 
 __device__ inline void end_dir(const Seg& s, double& dx, double& dy) {
-  const int e = s.npts - 1;
   if (s.kind == PS_KIND_LINE) { dx = s.x[1] - s.x[0]; dy = s.y[1] - s.y[0]; return; }
-  dx = s.x[e] - s.x[e - 1]; dy = s.y[e] - s.y[e - 1];
+  // last point minus the one before it (x[3] repeats the last point)
+  const bool cub = s.kind == PS_KIND_CUBIC;
+  dx = s.x[3] - (cub ? s.x[2] : s.x[1]); dy = s.y[3] - (cub ? s.y[2] : s.y[1]);
   if (s.kind == PS_KIND_CUBIC) {
     if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[1]; dy = s.y[3] - s.y[1]; }
     if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[0]; dy = s.y[3] - s.y[0]; }
@@ -177,14 +178,26 @@ __device__ inline int simple_roots01(double A, double B1, double C, double r[2])
       n = 2;
     }
   }
-  int m = 0;
-  if (n >= 1 && t0 > 0 && t0 < 1) r[m++] = t0;
-  if (n >= 2 && t1 > 0 && t1 < 1) r[m++] = t1;
-  if (m == 2) {
-    if (r[0] > r[1]) { double tmp = r[0]; r[0] = r[1]; r[1] = tmp; }
-    else if (r[0] == r[1]) m = 1;
+  // the roots inside (0,1), ascending, a repeated one once (selections only,
+  // with constant indices, so the array stays in registers)
+  const bool ok0 = n >= 1 && t0 > 0 && t0 < 1;
+  const bool ok1 = n >= 2 && t1 > 0 && t1 < 1;
+  if (ok0 && ok1) {
+    r[0] = t0 < t1 ? t0 : t1;
+    r[1] = t0 < t1 ? t1 : t0;
+    return t0 == t1 ? 1 : 2;
   }
-  return m;
+  r[0] = ok0 ? t0 : t1;
+  return (ok0 || ok1) ? 1 : 0;
+}
+
+// a[n] = v for a run-time n, as a chain of selections over constant indices
+// (a dynamically indexed private array would live in scratch memory)
+template <int NMAX, typename T>
+__device__ __forceinline__ void put_at(T (&a)[NMAX], int n, T v) {
+#pragma unroll
+  for (int m = 0; m < NMAX; ++m)
+    if (m == n) a[m] = v;
 }
 
 // Cubic curvature sign: g' x g'' ~ (1-t)^2 X + (1-t) t Y + t^2 Z.
@@ -194,6 +207,32 @@ __device__ __forceinline__ double cubic_curv(double X, double Y, double Z, doubl
 }
 
 #pragma clang fp contract(on)
+
+// 1/x in FP64 for normal, finite x: the hardware estimate refined by two
+// Newton steps (each squares the relative error), so within an ulp or two.
+__device__ __forceinline__ double rcp64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// sqrt(x) in FP64 for x >= 0: from the hardware 1/sqrt estimate, one coupled
+// Newton step on (sqrt x, 1/(2 sqrt x)) and two residual corrections
+// x - g^2.  x below 2^-960 (and 0) goes to the library routine.
+__device__ __forceinline__ double sqrt64(double x) {
+  if (!(x >= 0x1p-960)) return sqrt(x);
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
 
 // sin and cos of an unwrapped tangent angle in FP64 (|x| < 2^20; the angles
 // here stay within a few turns).  x = k pi/2 + y with pi/2 split in three
@@ -287,10 +326,24 @@ __device__ __forceinline__ SolveOut<F> solve_t(const Hodo<F>& h, F nx, F ny, F t
   if (A != (F)0) {
     const F disc = B1 * B1 - (F)4 * A * C;
     if (disc >= (F)0) {
-      const F sq = sqrt(disc);
-      const F qq = (F)-0.5 * (B1 + (B1 >= (F)0 ? sq : -sq));
-      r0 = qq / A;
-      r1 = (qq != (F)0) ? C / qq : r0;
+      if constexpr (sizeof(F) == 8) {
+        // one reciprocal for both roots: qq/A = qq^2/(A qq), C/qq = C A/(A qq)
+        const F sq = sqrt64(disc);
+        const F qq = (F)-0.5 * (B1 + (B1 >= (F)0 ? sq : -sq));
+        const F aq = A * qq;
+        if (aq != (F)0) {
+          const F inv = rcp64(aq);
+          r0 = qq * qq * inv;
+          r1 = C * A * inv;
+        } else {
+          r0 = r1 = (F)0;   // qq = 0 only when B1 = C = 0: the double root t = 0
+        }
+      } else {
+        const F sq = sqrt(disc);
+        const F qq = (F)-0.5 * (B1 + (B1 >= (F)0 ? sq : -sq));
+        r0 = qq / A;
+        r1 = (qq != (F)0) ? C / qq : r0;
+      }
     }
   } else if (B1 != (F)0) {
     r0 = r1 = -C / B1;
@@ -337,9 +390,9 @@ __device__ __forceinline__ void eval_point(int kind, const float* X, const float
   } else {
     const double ww = (kind == PS_KIND_CONIC) ? w : 1.0;
     const double b0 = u * u, b1 = 2.0 * u * t * ww, b2 = t * t;
-    const double den = b0 + b1 + b2;
-    gx = (b0 * X[0] + b1 * X[1] + b2 * X[2]) / den;
-    gy = (b0 * Y[0] + b1 * Y[1] + b2 * Y[2]) / den;
+    const double inv = rcp64(b0 + b1 + b2);   // > 0 for t in [0,1], w > 0
+    gx = (b0 * X[0] + b1 * X[1] + b2 * X[2]) * inv;
+    gy = (b0 * Y[0] + b1 * Y[1] + b2 * Y[2]) * inv;
   }
 }
 

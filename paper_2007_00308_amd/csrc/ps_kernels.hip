@@ -142,6 +142,9 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, D
     collinear = crs(ax, ay, bx, by) == 0;
   }
 
+  // interval n gets dsum[n], its end parameter p[n] and end angle psi[n+1];
+  // loops run to their constant maxima so every private array keeps constant
+  // indices (and stays in registers)
   int n = 0, N = 0;
   double psi_run = psi0;
   rec.psi[0] = psi0;
@@ -161,48 +164,58 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, D
       const double al = ax * dx + ay * dy, be = bx * dx + by * dy, w = s.w;
       A = w * al - (al + be) + w * be; B1 = (al + be) - 2 * w * al; C = w * al;
     }
-    double f[2];
+    double f[2] = {0, 0};
     const int nf = (s.kind == PS_KIND_LINE) ? 0 : simple_roots01(A, B1, C, f);
     const int flat = steps_of(0.0, q), fold = steps_of(kPi, q);
-    for (int k = 0; k < nf; ++k) {
-      N += flat; rec.dsum[n] = N; rec.p[n] = f[k]; rec.psi[n + 1] = psi_run; ++n;
-      N += fold; rec.dsum[n] = N; rec.p[n] = f[k];
-      psi_run = psi_run + kPi; rec.psi[n + 1] = psi_run; ++n;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k < nf) {
+        N += flat; put_at(rec.dsum, n, N); put_at(rec.p, n, f[k]); put_at(rec.psi, n + 1, psi_run); ++n;
+        N += fold; put_at(rec.dsum, n, N); put_at(rec.p, n, f[k]);
+        psi_run = psi_run + kPi; put_at(rec.psi, n + 1, psi_run); ++n;
+      }
     }
-    N += flat; rec.dsum[n] = N; rec.psi[n + 1] = psi_run; ++n;
+    N += flat; put_at(rec.dsum, n, N); put_at(rec.psi, n + 1, psi_run); ++n;
     rec.n_iv = (uint8_t)n;
     return N;
   }
 
-  // reversal parameters: simple roots of the cubic curvature sign
-  double pr[4];
+  // reversal parameters: simple roots of the cubic curvature sign;
+  // pr[0..M] = 0, the roots, 1 (M <= 3)
+  double pr[4] = {0.0, 1.0, 1.0, 1.0};
   int M = 1;
-  pr[0] = 0.0;
   if (s.kind == PS_KIND_CUBIC) {
-    double r[2];
+    double r[2] = {0, 0};
     const int nr = simple_roots01(X3 - Y3 + Z3, Y3 - 2 * X3, X3, r);
-    for (int k = 0; k < nr; ++k) pr[M++] = r[k];
+    M = 1 + nr;
+    pr[1] = nr >= 1 ? r[0] : 1.0;
+    pr[2] = nr >= 2 ? r[1] : 1.0;
   }
-  pr[M] = 1.0;
   double Psi[4];
   Psi[0] = psi0;
-  for (int k = 1; k < M; ++k) {
+#pragma unroll
+  for (int k = 1; k < 3; ++k) {
     const double t = pr[k], u = 1 - t;
     const double gx = u * u * ax + 2 * u * t * bx + t * t * cx;
     const double gy = u * u * ay + 2 * u * t * by + t * t * cy;
-    Psi[k] = atan2(gy, gx);
+    Psi[k] = (k < M) ? atan2(gy, gx) : 0.0;
   }
   double ex, ey;
   end_dir(s, ex, ey);
-  Psi[M] = unit_angle(ex, ey);
+  put_at(Psi, M, unit_angle(ex, ey));
   const double crsQ = crs(ax, ay, bx, by);
-  for (int k = 1; k <= M; ++k) {
+#pragma unroll
+  for (int k = 1; k <= 3; ++k) {
+    if (k > M) break;
     double d = adiff(Psi[k], Psi[k - 1]);   // the short way round
     double sigma = 0;                       // rotation sense of the interval
     if (s.kind == PS_KIND_CUBIC) {
-      const double fr[3] = {0.5, 0.25, 0.75};
-      for (int m = 0; m < 3 && sigma == 0; ++m)
-        sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + fr[m] * (pr[k] - pr[k - 1])));
+      // the middle of the interval, then its quarter points (an exact cusp
+      // makes the curvature vanish at a single point)
+      const double w = pr[k] - pr[k - 1];
+      sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.5 * w));
+      if (sigma == 0) sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.25 * w));
+      if (sigma == 0) sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.75 * w));
     } else {
       sigma = sgn_d(crsQ);
     }
@@ -216,13 +229,13 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, D
       sincos(psi_s, &sn, &cs);
       const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, pr[k - 1], pr[k]);
       const int half = steps_of(fabs(0.5 * d), q);
-      N += half; rec.dsum[n] = N; rec.p[n] = so.t; rec.psi[n + 1] = psi_s; ++n;
-      N += half; rec.dsum[n] = N; if (k < M) rec.p[n] = pr[k];
-      psi_run = psi_s + 0.5 * d; rec.psi[n + 1] = psi_run; ++n;
+      N += half; put_at(rec.dsum, n, N); put_at(rec.p, n, so.t); put_at(rec.psi, n + 1, psi_s); ++n;
+      N += half; put_at(rec.dsum, n, N); if (k < M) put_at(rec.p, n, pr[k]);
+      psi_run = psi_s + 0.5 * d; put_at(rec.psi, n + 1, psi_run); ++n;
     } else {
       if (n + 1 > kMaxIv) { set_flag(st, PS_STATUS_INTERVALS); rec.n_iv = 0; return -1; }
-      N += steps_of(fabs(d), q); rec.dsum[n] = N; if (k < M) rec.p[n] = pr[k];
-      psi_run = psi_run + d; rec.psi[n + 1] = psi_run; ++n;
+      N += steps_of(fabs(d), q); put_at(rec.dsum, n, N); if (k < M) put_at(rec.p, n, pr[k]);
+      psi_run = psi_run + d; put_at(rec.psi, n + 1, psi_run); ++n;
     }
   }
   rec.n_iv = (uint8_t)n;
@@ -510,7 +523,6 @@ struct EmitArgs {
   DevStatus* st;
   int64_t max_tiles;
   float fix_tol;   // largest FP64 Newton step accepted on an FP32 root; beyond it the rib is re-solved in FP64
-  unsigned long long zero;   // always 0: the operand of the look-back's read-modify-write reads
 };
 
 __device__ __forceinline__ int link_of(const int64_t* off, int lo, int hi, int64_t r) {
@@ -562,59 +574,63 @@ struct RibOut {
 
 // One rib j of a link: Eqs. func_t / func_N for segments (t from the
 // tangent-angle solve), a pivot for joins and caps, then Eqs.
-// RibVertices-N/P.  The record may live in LDS or in global memory.
+// RibVertices-N/P.  A pivot is one interval [0, J] of its own, so the angle
+// and the direction are computed once for both roles (a wavefront usually
+// holds ribs of both) and only the t solve and the point differ.  The record
+// may live in LDS or in global memory.
 template <int PREC, typename Rec>
 __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol, RibOut& o) {
   const uint8_t role = rp.role;
+  const bool seg = role == ROLE_SEG;
   const double rad = (double)rp.r;
   o.path_start = (rp.flags & kFirstInPath) && j == 0;
   o.fixed = false;
-  double nx = 0, ny = 1;   // n(psi) = (-sin psi, cos psi)
+  // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]; pivots have one
+  const int n_iv = rp.n_iv;
+  int k = 1, d0 = 0;
+  while (k < n_iv && j > rp.dsum[k - 1]) { d0 = rp.dsum[k - 1]; ++k; }
+  const int d1 = rp.dsum[k - 1];
+  const double psa = rp.psi[k - 1], psb = rp.psi[k];
+  const bool at0 = j == d0, at1 = j == d1;
+  const double psi =
+      at0 ? psa : (at1 ? psb : psa + (psb - psa) * ((double)(j - d0) * rcp64((double)(d1 - d0))));
+  double nx, ny;   // n(psi) = (-sin psi, cos psi)
+  if (PREC == PS_PREC_FP32) {
+    float s32, c32;
+    sincosf(reduce_angle<float>(psi), &s32, &c32);
+    nx = -(double)s32; ny = (double)c32;
+  } else {
+    double sn, cs;
+    sincos_rd(psi, &sn, &cs);
+    nx = -sn; ny = cs;
+  }
   double rN = rad, rP = rad;
-  if (role == ROLE_SEG) {
+  if (seg) {
     const int kind = rp.kind;
-    const int n_iv = rp.n_iv;
     float X[4], Y[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { X[k] = rp.x[k]; Y[k] = rp.y[k]; }
+    for (int i = 0; i < 4; ++i) { X[i] = rp.x[i]; Y[i] = rp.y[i]; }
     const float wf = rp.w;
-    // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]
-    int k = 1, d0 = 0;
-    while (k < n_iv && j > rp.dsum[k - 1]) { d0 = rp.dsum[k - 1]; ++k; }
-    const int d1 = rp.dsum[k - 1];
     const double lo = (k == 1) ? 0.0 : rp.p[k - 2];
     const double hi = (k == n_iv) ? 1.0 : rp.p[k - 1];
-    const double psa = rp.psi[k - 1], psb = rp.psi[k];
-    double t, psi;
-    bool have_n = false;
-    if (j == d0) { t = lo; psi = psa; }
-    else if (j == d1) { t = hi; psi = psb; }
-    else {
-      psi = psa + (psb - psa) * (double)(j - d0) / (double)(d1 - d0);
-      t = lo;
-      if (lo != hi) {
+    double t = at1 ? hi : lo;
+    if (!at0 && !at1 && lo != hi) {
+      if (PREC == PS_PREC_FP32) {
+        // single precision throughout (precision studies only)
+        const float sn = (float)-nx, cs = (float)ny;
+        const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
+        t = (double)solve_t<float>(h, -sn, cs, cs, sn, (float)lo, (float)hi).t;
+      } else {
         bool need64 = (PREC == PS_PREC_FP64);
-        if (PREC == PS_PREC_FP32) {
-          // single precision throughout (precision studies only)
-          float sn, cs;
-          sincosf(reduce_angle<float>(psi), &sn, &cs);
+        if (PREC == PS_PREC_FP32_FIXUP) {
+          // the FP32 quadratic isolates and selects the root, one FP64 Newton
+          // step on g'(t).N polishes it.  No FP32 root, a large step or a step
+          // out of the interval (a root close to a cusp or to another root)
+          // sends the rib to the FP64 solve.
           const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
-          const SolveOut<float> so = solve_t<float>(h, -sn, cs, cs, sn, (float)lo, (float)hi);
-          t = (double)so.t;
-          nx = -(double)sn; ny = (double)cs;
-          have_n = true;
-        } else if (PREC == PS_PREC_FP32_FIXUP) {
-          // FP64 direction; the FP32 quadratic isolates and selects the root,
-          // one FP64 Newton step on g'(t).N polishes it.  No FP32 root, a
-          // large step or a step out of the interval (a root close to a cusp
-          // or to another root) sends the rib to the FP64 solve.
-          double sn, cs;
-          sincos_rd(psi, &sn, &cs);
-          nx = -sn; ny = cs;
-          have_n = true;
-          const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
-          const SolveOut<float> so =
-              solve_t<float>(h, -(float)sn, (float)cs, (float)cs, (float)sn, (float)lo, (float)hi);
+          const SolveOut<float> so = solve_t<float>(h, (float)nx, (float)ny, (float)ny,
+                                                    (float)-nx, (float)lo, (float)hi);
+          need64 = true;
           if (so.found) {
             const Hodo<double> hd = hodo_of<double>(kind, X, Y, (double)wf);
             const double al = hd.e0x * nx + hd.e0y * ny;
@@ -624,35 +640,16 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
             const double t0 = (double)so.t;
             const double hv = (Aq * t0 + Bq) * t0 + al;
             const double dv = 2.0 * Aq * t0 + Bq;
-            const double step = (dv != 0.0) ? hv / dv : 0.0;
+            const double step = (dv != 0.0) ? hv * rcp64(dv) : 0.0;
             const double t1 = t0 - step;
-            if (fabs(step) <= (double)fix_tol && t1 >= lo && t1 <= hi) t = t1;
-            else need64 = true;
-          } else {
-            need64 = true;
+            if (fabs(step) <= (double)fix_tol && t1 >= lo && t1 <= hi) { t = t1; need64 = false; }
           }
+          o.fixed = need64;
         }
         if (need64) {
-          double sn, cs;
-          sincos_rd(psi, &sn, &cs);
           const Hodo<double> h = hodo_of<double>(kind, X, Y, (double)wf);
-          const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, lo, hi);
-          t = so.t;
-          nx = -sn; ny = cs;
-          have_n = true;
-          o.fixed = (PREC == PS_PREC_FP32_FIXUP);
+          t = solve_t<double>(h, nx, ny, ny, -nx, lo, hi).t;
         }
-      }
-    }
-    if (!have_n) {
-      if (PREC == PS_PREC_FP64) {
-        double sn, cs;
-        sincos_rd(psi, &sn, &cs);
-        nx = -sn; ny = cs;
-      } else {
-        float s32, c32;
-        sincosf(reduce_angle<float>(psi), &s32, &c32);
-        nx = -(double)s32; ny = (double)c32;
       }
     }
     eval_point(kind, X, Y, (double)wf, t, o.gx, o.gy);
@@ -661,18 +658,6 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
   } else {
     // join or cap: a pivot at a fixed point (Sec. "Tessellation Approach for
     // Caps and Joins"); only the side away from the turn keeps its radius
-    const int J = rp.dsum[0];
-    const double psa = rp.psi[0], psb = rp.psi[1];
-    const double psi = psa + (psb - psa) * (double)j / (double)J;
-    if (PREC == PS_PREC_FP64) {
-      double sn, cs;
-      sincos_rd(psi, &sn, &cs);
-      nx = -sn; ny = cs;
-    } else {
-      float s32, c32;
-      sincosf(reduce_angle<float>(psi), &s32, &c32);
-      nx = -(double)s32; ny = (double)c32;
-    }
     double rout = rad;
     if ((role == ROLE_SCAP || role == ROLE_ECAP) && (rp.flags >> 4) == PS_CAP_SQUARE && (j == 1 || j == 3))
       rout = rad * 1.41421356237309504880;
@@ -688,25 +673,24 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
 }
 
 // Link window staged in LDS, one per wave: kWin consecutive link slots
-// starting at `base`, their offsets and (for links with ribs) their records.
-constexpr int kWin = 64;
+// starting at `base`, their offsets and their records.
+constexpr int kWin = 32;
 struct WinLDS {
   long long off[kWin + 1];
   LinkRec rec[kWin];
 };
 
-// Descriptor words of the look-back are read and written with device-scope
-// read-modify-write atomics: they are performed at the coherence point of
-// the device, so a word published on one XCD is seen on every other XCD
-// without write-backs or invalidations of the per-XCD L2 caches.
+// Look-back words are published with a device-scope atomic swap and read
+// with device-scope relaxed atomic loads.  At device scope both reach the
+// point where the XCDs' L2 caches are coherent, so a word published on one
+// XCD is seen on every other one without whole-cache write-backs or
+// invalidations (which release/acquire ordering would add per tile); the
+// vertex data needs no ordering with the words.
 __device__ __forceinline__ void desc_publish(unsigned long long* p, unsigned long long w) {
   (void)__hip_atomic_exchange(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// `zero` is 0 at run time but opaque to the compiler, which would otherwise
-// turn an idempotent read-modify-write into a plain (non-coherent) load.
-__device__ __forceinline__ unsigned long long desc_read(unsigned long long* p,
-                                                        unsigned long long zero) {
-  return __hip_atomic_fetch_add(p, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned long long desc_read(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Persistent emit.  Tile T covers ribs [T*TS, (T+1)*TS), TS = 64*K - 1; lane
@@ -773,12 +757,14 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
             // (re)stage the window starting at the link of the first rib
             base = (base < 0) ? l : link_of(A.off, base, lhi, rf);
             const int64_t idx = (int64_t)base + lane;
-            const long long o_i = idx <= L ? A.off[idx] : LLONG_MAX;
-            const long long o_n = idx + 1 <= L ? A.off[idx + 1] : LLONG_MAX;
-            win.off[lane] = o_i;
-            if (lane == 63) win.off[kWin] = o_n;
-            if (idx < L && o_i < o_n) win.rec[lane] = A.rec[idx];
-            wend = __shfl(o_n, 63, 64);
+            const long long o_i = (lane <= kWin && idx <= L) ? A.off[idx] : LLONG_MAX;
+            if (lane <= kWin) win.off[lane] = o_i;
+            wend = __shfl(o_i, kWin, 64);
+            // the window's records, copied in coalesced 16-byte pieces
+            const int n_rec = (int)(L - base < kWin ? L - base : kWin);
+            const int4* src = reinterpret_cast<const int4*>(A.rec + base);
+            int4* dst = reinterpret_cast<int4*>(win.rec);
+            for (int c = lane; c < n_rec * (int)(sizeof(LinkRec) / 16); c += 64) dst[c] = src[c];
           }
           staged = (rf <= rl) && (rl < wend);
         }
@@ -813,7 +799,7 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
           long long c = 0;
           if (mine && o.chord_ok && o.t >= pt) {
             const double dx = o.gx - pgx, dy = o.gy - pgy;
-            c = llrint(sqrt(dx * dx + dy * dy) * kFix);
+            c = llrint(sqrt64(dx * dx + dy * dy) * kFix);
           }
           int f = (mine && o.path_start) ? 1 : 0;
           // segmented inclusive scan across the wave: a path start resets the sum
@@ -851,7 +837,7 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
           for (;;) {
             const int64_t Ti = base - lane;
             // before tile 0 every path has started: an inclusive zero
-            const unsigned long long w = Ti >= 0 ? desc_read(&A.desc[Ti], A.zero) : (2ull << 62);
+            const unsigned long long w = Ti >= 0 ? desc_read(&A.desc[Ti]) : (2ull << 62);
             const unsigned stt = (unsigned)(w >> 62);
             const unsigned long long incl = __ballot(stt == 2);
             const int stop = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive word
@@ -1072,6 +1058,7 @@ struct EmitConfig {
   int stage = 1;   // 1: link records staged in LDS per wave; 0: read from global memory
 };
 EmitConfig g_cfg;
+bool g_autotune = true;
 std::mutex g_mu;
 
 int64_t n_links_of(const ps_batch* b) { return 2 * (int64_t)b->n_segs + b->n_paths; }
@@ -1261,7 +1248,6 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
   a.max_tiles = w.max_tiles;
   a.fix_tol = fixup_tolerance();
-  a.zero = 0ull;
   if (waves < 1 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   const int block = 64 * waves;   // never above the kernel's launch bound of 256
   const int grid = num_cus() * (16 / waves);
@@ -1396,6 +1382,13 @@ int ps_set_emit_config(int32_t K, int32_t waves, int32_t stage) {
   return PS_OK;
 }
 
+int ps_set_plan_autotune(int32_t on) {
+  if (on != 0 && on != 1) return fail(PS_E_ARG, "autotune must be 0 or 1");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_autotune = on != 0;
+  return PS_OK;
+}
+
 int ps_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, void* ws, size_t ws_bytes,
              void* stream) {
   int rc;
@@ -1506,10 +1499,15 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
     delete P;
     return rc;
   }
+  bool tune;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    tune = g_autotune;
+  }
   float best = 1e30f;
   const int Ks[3] = {4, 8, 16};
   const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
-  for (int st = 1; st >= 0; --st)
+  for (int st = 1; tune && st >= 0; --st)
     for (int ki = 0; ki < 3; ++ki)
       for (int wi = 0; wi < 3; ++wi) {
         float ms = 0;

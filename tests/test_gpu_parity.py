@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 VERTEX_TOL = 2e-3
 
 
-def _gpu(b, precision=ps.PS_PREC_FP32_FIXUP, **kw):
+def _gpu(b, precision=ps.PS_PREC_FP64, **kw):
     db = ps.DeviceBatch(b)
     out = ps.stroke(db, b.q, precision=precision, **kw)
     import torch
@@ -36,7 +36,7 @@ def _arc_tol(ref_s):
     return float(np.spacing(np.float32(max(1.0, ref_s.max())))) + 1e-6 * float(ref_s.max())
 
 
-def _compare(b, precision=ps.PS_PREC_FP32_FIXUP, vertex_tol=VERTEX_TOL, check_s=True):
+def _compare(b, precision=ps.PS_PREC_FP64, vertex_tol=VERTEX_TOL, check_s=True):
     ref = oracle.stroke(b)
     db, out = _gpu(b, precision)
     st = out["status"]
