@@ -52,7 +52,7 @@ def main() -> int:
                          "instead of the plan's autotuning, e.g. for profiles of one mapping")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--study", choices=["precision", "c3", "c5"], default=None,
+    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit"], default=None,
                     help="secondary measurements: the near-degenerate precision study, the long "
                          "dashed path, or the stress configuration at q in {pi/16, pi/64, pi/256}")
     args = ap.parse_args()
@@ -353,7 +353,47 @@ def study_c5(args, torch, ps, W, dev):
     return 0
 
 
-STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5}
+def study_emit(args, torch, ps, W, dev):
+    """The emit stage of the benchmark batch by output mode and mapping: vertices
+    and arc length (ps_emit), vertices only (ps_emit without vs), arc length only
+    (ps_arclen), for every mapping K x waves (LDS-staged)."""
+    b = W.config2_fast()
+    db = ps.DeviceBatch(b, device=dev)
+    first = ps.stroke(db, b.q)
+    R = first["total_ribs"]
+    del first
+    plan = ps.Plan(db, b.q, vertex_capacity=2 * R)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=10):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    P, cap, ws = plan.params, 2 * R, plan.ws
+    rows = []
+    for K in (4, 8, 16):
+        for waves in (1, 2, 4):
+            ps.ps_set_emit_config(K, waves, 1)
+            row = {"K": K, "waves": waves,
+                   "ms_xy_s": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, plan.vs, cap, ws)),
+                   "ms_xy": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, None, cap, ws)),
+                   "ms_s": timed(lambda: ps.ps_arclen(db, P, plan.offsets, plan.vs, cap, ws))}
+            rows.append(row)
+            log(str(row))
+    ps.ps_set_emit_config(8, 4, 1)
+    plan.close()
+    print(json.dumps({"study": "emit", "ribs": R, "rows": rows}), flush=True)
+    return 0
+
+
+STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5, "emit": study_emit}
 
 
 if __name__ == "__main__":

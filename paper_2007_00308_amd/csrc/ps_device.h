@@ -276,8 +276,8 @@ struct Hodo {
   F e0x, e0y, e1x, e1y, e2x, e2y;
 };
 
-template <typename F>
-__device__ __forceinline__ Hodo<F> hodo_of(int kind, const float* X, const float* Y, F w) {
+template <typename F, typename P>
+__device__ __forceinline__ Hodo<F> hodo_of(int kind, const P* X, const P* Y, F w) {
   Hodo<F> h;
   const F ax = (F)X[1] - (F)X[0], ay = (F)Y[1] - (F)Y[0];
   if (kind == PS_KIND_CUBIC) {
@@ -377,7 +377,7 @@ __device__ __forceinline__ SolveOut<F> solve_t(const Hodo<F>& h, F nx, F ny, F t
 
 // g(t) in FP64: cubic Bernstein, or a rational quadratic (quadratic: w = 1,
 // line: middle point at the chord midpoint).
-__device__ __forceinline__ void eval_point(int kind, const float* X, const float* Y, double w,
+__device__ __forceinline__ void eval_point(int kind, const double* X, const double* Y, double w,
                                            double t, double& gx, double& gy) {
   const double u = 1.0 - t;
   if (kind == PS_KIND_CUBIC) {

@@ -114,9 +114,11 @@ __device__ inline bool seg_usable(const ps_batch& B, int i, DevStatus* st, bool 
 
 #pragma clang fp contract(off)
 
-// Intervals of one usable segment, written into rec.  Returns the step count N
-// (the segment has N+1 ribs), or -1 if it needs more than kMaxIv intervals.
-__device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, DevStatus* st) {
+// Intervals of one usable segment, written into rec, and the end tangent
+// angle (as the joins use it) into psi_end.  Returns the step count N (the
+// segment has N+1 ribs), or -1 if it needs more than kMaxIv intervals.
+__device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, double& psi_end,
+                             DevStatus* st) {
   const Seg s = load_seg(B, i);
   float X[4], Y[4];
   const int64_t S = B.n_segs;
@@ -148,6 +150,9 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, D
   int n = 0, N = 0;
   double psi_run = psi0;
   rec.psi[0] = psi0;
+  double ex, ey;
+  end_dir(s, ex, ey);
+  psi_end = unit_angle(ex, ey);
   if (collinear) {
     // flat pieces of one step, split by +pi pivots at the simple roots of
     // g'(t).d where the segment reverses along its line (a cusp)
@@ -200,9 +205,7 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, D
     const double gy = u * u * ay + 2 * u * t * by + t * t * cy;
     Psi[k] = (k < M) ? atan2(gy, gx) : 0.0;
   }
-  double ex, ey;
-  end_dir(s, ex, ey);
-  put_at(Psi, M, unit_angle(ex, ey));
+  put_at(Psi, M, psi_end);
   const double crsQ = crs(ax, ay, bx, by);
 #pragma unroll
   for (int k = 1; k <= 3; ++k) {
@@ -267,13 +270,6 @@ __device__ inline double seg_start_angle(const ps_batch& B, int i) {
   return unit_angle(dx, dy);
 }
 
-__device__ inline double seg_end_angle(const ps_batch& B, int i) {
-  const Seg s = load_seg(B, i);
-  double dx, dy;
-  end_dir(s, dx, dy);
-  return unit_angle(dx, dy);
-}
-
 #pragma clang fp contract(on)
 
 __device__ inline void clear_rec(LinkRec& r) {
@@ -321,8 +317,9 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     r.kind = B.kind[i];
     r.r = half_w;
     int ribs = 0;
+    double psi_e = 0;
     if (usable) {
-      const int N = segment_setup(B, i, A.q, r, A.st);
+      const int N = segment_setup(B, i, A.q, r, psi_e, A.st);
       if (N > 0) {
         ribs = N + 1;
         r.role = ROLE_SEG;
@@ -350,7 +347,6 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     }
     const int n = npts_of(B.kind[i]);
     const float ex = B.cx[(int64_t)(n - 1) * S + i], ey = B.cy[(int64_t)(n - 1) * S + i];
-    const double psi_e = seg_end_angle(B, i);
     for (int k = i + 1; k < e; ++k) {
       if (!seg_usable(B, k, A.st, false)) continue;
       double d = adiff(seg_start_angle(B, k), psi_e);
@@ -550,12 +546,22 @@ __global__ void __launch_bounds__(256) emit_prepare_kernel(const int64_t* off, i
     if (tid == 0) atomicOr(&st->flags, (unsigned)PS_STATUS_OVERFLOW);
     return;
   }
-  for (int64_t T = tid; T <= n_tiles; T += (int64_t)gridDim.x * blockDim.x) {
-    int64_t rib = T * TS - 1;
-    if (rib < 0) rib = 0;
-    if (rib > R - 1) rib = R - 1;
-    tile_link[T] = R > 0 ? link_of(off, 0, (int)n_links - 1, rib) : 0;
-    if (T < n_tiles) desc[T] = 0ull;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t T = tid; T < n_tiles; T += stride) desc[T] = 0ull;
+  if (R == 0) {
+    if (tid == 0) tile_link[0] = 0;
+    return;
+  }
+  // tile T (0 <= T <= n_tiles, the last one a sentinel) first reads rib
+  // f(T) = clamp(T*TS - 1, 0, R - 1); each link with ribs [a, b) writes the
+  // tiles whose f(T) it holds: T*TS in [a+1, b], plus T = 0 for the link
+  // holding rib 0 and the sentinel for the one holding rib R - 1
+  for (int64_t l = tid; l < n_links; l += stride) {
+    const int64_t a = off[l], b = off[l + 1];
+    if (a >= b) continue;
+    const int64_t t0 = (a == 0) ? 0 : (a + TS) / TS;
+    const int64_t t1 = (b == R) ? n_tiles : b / TS;
+    for (int64_t T = t0; T <= t1; ++T) tile_link[T] = (int32_t)l;
   }
 }
 
@@ -608,8 +614,12 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
   if (seg) {
     const int kind = rp.kind;
     float X[4], Y[4];
+    double Xd[4], Yd[4];   // the FP32 inputs, converted once (exactly)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { X[i] = rp.x[i]; Y[i] = rp.y[i]; }
+    for (int i = 0; i < 4; ++i) {
+      X[i] = rp.x[i]; Y[i] = rp.y[i];
+      Xd[i] = (double)X[i]; Yd[i] = (double)Y[i];
+    }
     const float wf = rp.w;
     const double lo = (k == 1) ? 0.0 : rp.p[k - 2];
     const double hi = (k == n_iv) ? 1.0 : rp.p[k - 1];
@@ -632,7 +642,7 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
                                                     (float)-nx, (float)lo, (float)hi);
           need64 = true;
           if (so.found) {
-            const Hodo<double> hd = hodo_of<double>(kind, X, Y, (double)wf);
+            const Hodo<double> hd = hodo_of<double>(kind, Xd, Yd, (double)wf);
             const double al = hd.e0x * nx + hd.e0y * ny;
             const double be = hd.e1x * nx + hd.e1y * ny;
             const double ga = hd.e2x * nx + hd.e2y * ny;
@@ -647,12 +657,12 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
           o.fixed = need64;
         }
         if (need64) {
-          const Hodo<double> h = hodo_of<double>(kind, X, Y, (double)wf);
+          const Hodo<double> h = hodo_of<double>(kind, Xd, Yd, (double)wf);
           t = solve_t<double>(h, nx, ny, ny, -nx, lo, hi).t;
         }
       }
     }
-    eval_point(kind, X, Y, (double)wf, t, o.gx, o.gy);
+    eval_point(kind, Xd, Yd, (double)wf, t, o.gx, o.gy);
     o.t = t;
     o.chord_ok = (j > 0);
   } else {
@@ -693,14 +703,50 @@ __device__ __forceinline__ unsigned long long desc_read(const unsigned long long
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Cross-lane moves on the VALU (DPP) rather than through the LDS crossbar.
+// A lane whose source lies outside its row, or that row_mask leaves out,
+// reads 0: the identity of the sums below.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_i64(long long v) {
+  const unsigned lo = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)(unsigned long long)v);
+  const unsigned hi = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+// the value of lane - 1 (wave_shr:1); lane 0 reads 0
+__device__ __forceinline__ double wave_shr1(double v) {
+  return __longlong_as_double(dpp_i64<0x138, 0xf>(__double_as_longlong(v)));
+}
+__device__ __forceinline__ long long readlane_i64(long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(unsigned long long)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)v >> 32), l);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __longlong_as_double(readlane_i64(__double_as_longlong(v), l));
+}
+// one step of the segmented scan: (c, f) <- (left) op (c, f), where op keeps
+// the right sum when it holds a path start
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_scan_step(long long& c, int& f) {
+  const long long cu = dpp_i64<CTRL, ROWS>(c);
+  const int fu = dpp_i32<CTRL, ROWS>(f);
+  c = f ? c : c + cu;
+  f |= fu;
+}
+
 // Persistent emit.  Tile T covers ribs [T*TS, (T+1)*TS), TS = 64*K - 1; lane
 // slot (k, lane) handles rib T*TS - 1 + 64k + lane, so slot (0,0) re-reads the
-// previous tile's last rib for the first chord and stores nothing.  Waves
-// claim one tile per ticket, in increasing order, so every tile a wave waits
-// on belongs to a wave that is already running.  A ticket is a single tile on
-// purpose: a wave holding several consecutive tiles would publish the last of
-// them only after the look-backs of the others, and the next wave's first tile
-// waits on exactly that one, which chains all waves into one sequence.
+// previous tile's last rib for the first chord and stores nothing.  A
+// workgroup of W waves claims W consecutive tiles per ticket, one per wave, in
+// increasing order, so every tile a wave waits on belongs to a wave that is
+// already running.  No wave holds more than one tile at a time on purpose: a
+// wave holding several consecutive tiles would publish the last of them only
+// after the look-backs of the others, and the next group's first tile waits on
+// exactly that one, which chains all waves into one sequence.
 //
 // STAGE: link records are staged per wave in LDS (one cooperative load per
 // window of kWin links) instead of being read from global memory per rib.
@@ -715,7 +761,8 @@ __host__ __device__ constexpr size_t emit_lds_per_wave(int K, bool ws, bool stag
 }
 
 template <int K, int PREC, bool WXY, bool WS, bool STAGE>
-__global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PS_PREC_FP32_FIXUP ? 3 : 4)))
+emit_kernel(EmitArgs A) {
   extern __shared__ unsigned char smem_raw[];
   unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_lds_per_wave(K, WS, STAGE);
   WinLDS& win = *reinterpret_cast<WinLDS*>(wave_lds);
@@ -727,12 +774,20 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
   const int64_t n_tiles = (R + TS - 1) / TS;
   if (2 * R > A.capacity || n_tiles > A.max_tiles) return;
   unsigned long long fixups = 0;
+  // one ticket per workgroup per round: wave w of the group takes tile
+  // ticket * waves + w (a single ticket counter serialises its atomics, so
+  // fewer tickets per rib matter more than their latency)
+  __shared__ unsigned int group_ticket;
+  const int n_waves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
   for (;;) {
-    unsigned int tk = 0;
-    if (lane == 0) tk = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
-    const int64_t tile = (int64_t)__shfl(tk, 0, 64);
-    if (tile >= n_tiles) break;
-    {
+    if (threadIdx.x == 0) group_ticket = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
+    __syncthreads();
+    const int64_t first = (int64_t)group_ticket * n_waves;
+    __syncthreads();   // every wave has read the ticket before the next round writes it
+    if (first >= n_tiles) break;
+    const int64_t tile = first + wave;
+    if (tile < n_tiles) {
       const int64_t r0 = tile * TS;
       const int lhi = A.tile_link[tile + 1];
       int l = A.tile_link[tile];
@@ -749,43 +804,49 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
         const bool mine = valid && (r >= r0);
         RibOut o;
         o.gx = o.gy = o.t = 0; o.chord_ok = false; o.path_start = false; o.fixed = false;
-        bool staged = false;
         if (STAGE) {
+          // every record comes from the LDS window; an iteration whose ribs
+          // span more link slots than the window holds (runs of links with
+          // few or no ribs) takes further passes, each restaging the window
+          // at the first rib still pending (lanes hold consecutive ribs)
           const int64_t rf = (r0 - 1 + 64 * k) < 0 ? 0 : (r0 - 1 + 64 * k);
           const int64_t rl = (r0 - 1 + 64 * k + 63) < R ? (r0 - 1 + 64 * k + 63) : R - 1;
-          if (rf <= rl && (base < 0 || rl >= wend)) {
-            // (re)stage the window starting at the link of the first rib
-            base = (base < 0) ? l : link_of(A.off, base, lhi, rf);
-            const int64_t idx = (int64_t)base + lane;
-            const long long o_i = (lane <= kWin && idx <= L) ? A.off[idx] : LLONG_MAX;
-            if (lane <= kWin) win.off[lane] = o_i;
-            wend = __shfl(o_i, kWin, 64);
-            // the window's records, copied in coalesced 16-byte pieces
-            const int n_rec = (int)(L - base < kWin ? L - base : kWin);
-            const int4* src = reinterpret_cast<const int4*>(A.rec + base);
-            int4* dst = reinterpret_cast<int4*>(win.rec);
-            for (int c = lane; c < n_rec * (int)(sizeof(LinkRec) / 16); c += 64) dst[c] = src[c];
+          bool pending = valid;
+          int64_t rs = rf;
+          bool restage = rf <= rl && (base < 0 || rl >= wend);
+          for (;;) {
+            if (restage) {
+              base = (base < 0) ? l : link_of(A.off, base, lhi, rs);
+              const int64_t idx = (int64_t)base + lane;
+              const long long o_i = (lane <= kWin && idx <= L) ? A.off[idx] : LLONG_MAX;
+              if (lane <= kWin) win.off[lane] = o_i;
+              wend = __shfl(o_i, kWin, 64);
+              // the window's records, copied in coalesced 16-byte pieces
+              const int n_rec = (int)(L - base < kWin ? L - base : kWin);
+              const int4* src = reinterpret_cast<const int4*>(A.rec + base);
+              int4* dst = reinterpret_cast<int4*>(win.rec);
+              for (int c = lane; c < n_rec * (int)(sizeof(LinkRec) / 16); c += 64) dst[c] = src[c];
+            }
+            if (pending && r < wend) {
+              // largest i with off[base + i] <= r, searched in LDS
+              int a = 0, b = kWin - 1;
+              while (a < b) {
+                const int m = (a + b + 1) >> 1;
+                if (win.off[m] <= r) a = m; else b = m - 1;
+              }
+              compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, o);
+              pending = false;
+            }
+            const unsigned long long pm = __ballot(pending);
+            if (pm == 0ull) break;
+            rs = r0 - 1 + 64 * k + __builtin_ctzll(pm);
+            restage = true;
           }
-          staged = (rf <= rl) && (rl < wend);
+        } else if (valid) {
+          l = link_of(A.off, l, lhi, r);
+          compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, o);
         }
         if (valid) {
-          const LinkRec* rp;
-          int j;
-          if (staged) {
-            // largest i with off[base + i] <= r, searched in LDS
-            int a = 0, b = kWin - 1;
-            while (a < b) {
-              const int m = (a + b + 1) >> 1;
-              if (win.off[m] <= r) a = m; else b = m - 1;
-            }
-            rp = &win.rec[a];
-            j = (int)(r - win.off[a]);
-          } else {
-            l = link_of(A.off, l, lhi, r);
-            rp = &A.rec[l];
-            j = (int)(r - A.off[l]);
-          }
-          compute_rib<PREC>(*rp, j, A.fix_tol, o);
           if (WXY && mine) {
             *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
             *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
@@ -794,7 +855,7 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
         }
         if (WS) {
           // chord from the previous rib; zero when t decreases
-          double pgx = __shfl_up(o.gx, 1, 64), pgy = __shfl_up(o.gy, 1, 64), pt = __shfl_up(o.t, 1, 64);
+          double pgx = wave_shr1(o.gx), pgy = wave_shr1(o.gy), pt = wave_shr1(o.t);
           if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
           long long c = 0;
           if (mine && o.chord_ok && o.t >= pt) {
@@ -802,23 +863,22 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs A) {
             c = llrint(sqrt64(dx * dx + dy * dy) * kFix);
           }
           int f = (mine && o.path_start) ? 1 : 0;
-          // segmented inclusive scan across the wave: a path start resets the sum
-#pragma unroll
-          for (int d = 1; d < 64; d <<= 1) {
-            const long long cu = __shfl_up(c, d, 64);
-            const int fu = __shfl_up(f, d, 64);
-            if (lane >= d) {
-              c = f ? c : c + cu;
-              f = f | fu;
-            }
-          }
+          // segmented inclusive scan across the wave (a path start resets
+          // the sum): Hillis-Steele inside each row of 16 lanes, then the
+          // row totals broadcast from lanes 15 and 31
+          seg_scan_step<0x111, 0xf>(c, f);   // row_shr:1
+          seg_scan_step<0x112, 0xf>(c, f);   // row_shr:2
+          seg_scan_step<0x114, 0xf>(c, f);   // row_shr:4
+          seg_scan_step<0x118, 0xf>(c, f);   // row_shr:8
+          seg_scan_step<0x142, 0xa>(c, f);   // row_bcast:15 into rows 1, 3
+          seg_scan_step<0x143, 0xc>(c, f);   // row_bcast:31 into rows 2, 3
           srel[k * 64 + lane] = f ? c : run + c;
           if (!(f || seen_start)) need_prefix |= (1u << k);
-          const long long c63 = __shfl(c, 63, 64);
-          const int f63 = __shfl(f, 63, 64);
+          const long long c63 = readlane_i64(c, 63);
+          const int f63 = __builtin_amdgcn_readlane(f, 63);
           run = f63 ? c63 : run + c63;
           seen_start = seen_start || (f63 != 0);
-          cgx = __shfl(o.gx, 63, 64); cgy = __shfl(o.gy, 63, 64); ct = __shfl(o.t, 63, 64);
+          cgx = readlane_f64(o.gx, 63); cgy = readlane_f64(o.gy, 63); ct = readlane_f64(o.t, 63);
         }
       }
       if (WS) {
@@ -1241,7 +1301,8 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
   const int TS = 64 * K - 1;
   EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr, stage != 0);
   if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", K);
-  hipLaunchKernelGGL(emit_prepare_kernel, dim3(256), dim3(256), 0, s, off, L, TS, v.tile_link,
+  const unsigned prep_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (L + 255) / 256), 8192);
+  hipLaunchKernelGGL(emit_prepare_kernel, dim3(prep_grid), dim3(256), 0, s, off, L, TS, v.tile_link,
                      v.desc, v.st, cap, w.max_tiles);
   EmitArgs a;
   a.B = *b; a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
