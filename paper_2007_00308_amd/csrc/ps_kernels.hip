@@ -684,7 +684,7 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
 
 // Link window staged in LDS, one per wave: kWin consecutive link slots
 // starting at `base`, their offsets and their records.
-constexpr int kWin = 32;
+constexpr int kWin = 12;
 struct WinLDS {
   long long off[kWin + 1];
   LinkRec rec[kWin];
@@ -727,6 +727,11 @@ __device__ __forceinline__ long long readlane_i64(long long v, int l) {
 }
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(readlane_i64(__double_as_longlong(v), l));
+}
+// one step of a plain 32-bit inclusive scan (the add takes the DPP operand)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned scan_step_u32(unsigned v) {
+  return v + (unsigned)dpp_i32<CTRL, ROWS>((int)v);
 }
 // one step of the segmented scan: (c, f) <- (left) op (c, f), where op keeps
 // the right sum when it holds a path start
@@ -863,15 +868,30 @@ emit_kernel(EmitArgs A) {
             c = llrint(sqrt64(dx * dx + dy * dy) * kFix);
           }
           int f = (mine && o.path_start) ? 1 : 0;
-          // segmented inclusive scan across the wave (a path start resets
-          // the sum): Hillis-Steele inside each row of 16 lanes, then the
-          // row totals broadcast from lanes 15 and 31
-          seg_scan_step<0x111, 0xf>(c, f);   // row_shr:1
-          seg_scan_step<0x112, 0xf>(c, f);   // row_shr:2
-          seg_scan_step<0x114, 0xf>(c, f);   // row_shr:4
-          seg_scan_step<0x118, 0xf>(c, f);   // row_shr:8
-          seg_scan_step<0x142, 0xa>(c, f);   // row_bcast:15 into rows 1, 3
-          seg_scan_step<0x143, 0xc>(c, f);   // row_bcast:31 into rows 2, 3
+          // inclusive scan across the wave: Hillis-Steele inside each row of
+          // 16 lanes, then the row totals broadcast from lanes 15 and 31
+          if (__ballot(f != 0 || c >= (1ll << 50)) == 0ull) {
+            // no path start among these ribs (the common case) and every
+            // chord below 2^50 units (2^18 px): a plain sum, as two exact
+            // 32-bit scans of the chord's low 24 and high bits, neither of
+            // which can overflow over 64 lanes
+            unsigned lo = (unsigned)c & 0xffffffu, hi = (unsigned)(c >> 24);
+            lo = scan_step_u32<0x111, 0xf>(lo); hi = scan_step_u32<0x111, 0xf>(hi);
+            lo = scan_step_u32<0x112, 0xf>(lo); hi = scan_step_u32<0x112, 0xf>(hi);
+            lo = scan_step_u32<0x114, 0xf>(lo); hi = scan_step_u32<0x114, 0xf>(hi);
+            lo = scan_step_u32<0x118, 0xf>(lo); hi = scan_step_u32<0x118, 0xf>(hi);
+            lo = scan_step_u32<0x142, 0xa>(lo); hi = scan_step_u32<0x142, 0xa>(hi);
+            lo = scan_step_u32<0x143, 0xc>(lo); hi = scan_step_u32<0x143, 0xc>(hi);
+            c = (long long)(((unsigned long long)hi << 24) + lo);
+          } else {
+            // segmented, in 64 bits: a path start resets the sum
+            seg_scan_step<0x111, 0xf>(c, f);   // row_shr:1
+            seg_scan_step<0x112, 0xf>(c, f);   // row_shr:2
+            seg_scan_step<0x114, 0xf>(c, f);   // row_shr:4
+            seg_scan_step<0x118, 0xf>(c, f);   // row_shr:8
+            seg_scan_step<0x142, 0xa>(c, f);   // row_bcast:15 into rows 1, 3
+            seg_scan_step<0x143, 0xc>(c, f);   // row_bcast:31 into rows 2, 3
+          }
           srel[k * 64 + lane] = f ? c : run + c;
           if (!(f || seen_start)) need_prefix |= (1u << k);
           const long long c63 = readlane_i64(c, 63);

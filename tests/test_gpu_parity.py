@@ -168,6 +168,18 @@ def test_mappings_agree_and_are_deterministic():
         assert np.array_equal(vs, outs[0][3]), cfg
 
 
+def test_long_chords_take_the_64_bit_scan():
+    # chords longer than 2^18 px (2^50 fixed-point units) are summed by the
+    # 64-bit scan; FP32 outputs at these coordinates carry half an ulp of 2^-5 px
+    segs = [(W.KIND_L, [(0, 0), (400000, 0)], 1.0),
+            (W.KIND_L, [(400000, 0), (400000, 300000)], 1.0),
+            (W.KIND_C, [(400000, 300000), (500000, 300000), (300000, 500000), (450000, 520000)], 1.0)]
+    b = W.path(segs, width=8.0, q=math.pi / 8, join=W.JOIN_BEVEL, cap=W.CAP_BUTT)
+    tol = 2.0 * float(np.spacing(np.float32(600000.0)))
+    r = _compare(b, vertex_tol=tol)
+    assert r["R"] > 4
+
+
 def test_arclen_only_matches_emit():
     import torch
     b = W.config3(n_segs=800)
