@@ -95,7 +95,7 @@ def main() -> int:
     plan = ps.Plan(db, b.q, vertex_capacity=cap, precision=prec)
     ps.ps_set_plan_autotune(True)
     K, waves, stage = plan.config()
-    log(f"plan: autotuned emit mapping K={K} waves/group={waves} lds-staged={stage}")
+    log(f"plan: autotuned emit mapping K={K} waves/group={waves} stage={stage}")
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -228,7 +228,7 @@ def main() -> int:
                                "q=pi/64, round joins, butt caps",
                    "paths": b.n_paths, "segments": b.n_segs, "ribs": R, "vertices": V,
                    "precision": args.precision, "emit_K": K, "emit_waves_per_group": waves,
-                   "emit_lds_staged": stage},
+                   "emit_stage": stage},
         "gb_per_s": B_alg / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": emit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": emit_gbs / HBM_PEAK_GBS, "traffic": None,
@@ -337,13 +337,13 @@ def study_c5(args, torch, ps, W, dev):
             e1.record(stream)
             torch.cuda.synchronize()
             emit_ms[name] = e0.elapsed_time(e1) / args.steps
-        ps.ps_set_emit_config(8, 4, 1)
+        ps.ps_set_emit_config(8, 4, 2)
         plan.close()
         V = 2 * R
         row = {"q": f"pi/{qn}", "ribs": R, "vertices": V, "ms_per_step": ms,
                "vertices_per_s": V / (ms * 1e-3),
                "gb_per_s": algorithmic_bytes(V, b.n_segs, b.n_paths) / (ms * 1e-3) / 1e9,
-               "autotuned": {"K": K, "waves": waves, "lds_staged": stage},
+               "autotuned": {"K": K, "waves": waves, "stage": stage},
                "emit_ms_autotuned": emit_ms["autotuned"], "emit_ms_fixed_K8_w4_staged": emit_ms["fixed"]}
         rows.append(row)
         log(str(row))
@@ -356,7 +356,7 @@ def study_c5(args, torch, ps, W, dev):
 def study_emit(args, torch, ps, W, dev):
     """The emit stage of the benchmark batch by output mode and mapping: vertices
     and arc length (ps_emit), vertices only (ps_emit without vs), arc length only
-    (ps_arclen), for every mapping K x waves (LDS-staged)."""
+    (ps_arclen), for every mapping K x waves, rib-major (stage 1) and role-split (stage 2)."""
     b = W.config2_fast()
     db = ps.DeviceBatch(b, device=dev)
     first = ps.stroke(db, b.q)
@@ -378,16 +378,18 @@ def study_emit(args, torch, ps, W, dev):
 
     P, cap, ws = plan.params, 2 * R, plan.ws
     rows = []
-    for K in (4, 8, 16):
-        for waves in (1, 2, 4):
-            ps.ps_set_emit_config(K, waves, 1)
-            row = {"K": K, "waves": waves,
-                   "ms_xy_s": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, plan.vs, cap, ws)),
-                   "ms_xy": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, None, cap, ws)),
-                   "ms_s": timed(lambda: ps.ps_arclen(db, P, plan.offsets, plan.vs, cap, ws))}
-            rows.append(row)
-            log(str(row))
-    ps.ps_set_emit_config(8, 4, 1)
+    for stage in (1, 2):
+        for K in (4, 8, 16):
+            for waves in (1, 2, 4):
+                ps.ps_set_emit_config(K, waves, stage)
+                row = {"stage": stage, "K": K, "waves": waves,
+                       "ms_xy_s": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, plan.vs,
+                                                           cap, ws)),
+                       "ms_xy": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, None, cap, ws)),
+                       "ms_s": timed(lambda: ps.ps_arclen(db, P, plan.offsets, plan.vs, cap, ws))}
+                rows.append(row)
+                log(str(row))
+    ps.ps_set_emit_config(8, 4, 2)
     plan.close()
     print(json.dumps({"study": "emit", "ribs": R, "rows": rows}), flush=True)
     return 0

@@ -219,16 +219,19 @@ int ps_plan_create(const ps_batch* batch, const ps_params* params, int32_t* link
                    ps_plan** out);
 int ps_plan_launch(ps_plan* plan, void* stream);
 int ps_plan_destroy(ps_plan* plan);
-/* The emit mapping a plan chose: K, waves per workgroup, LDS staging (0/1). */
+/* The emit mapping a plan chose: K, waves per workgroup, stage (0, 1 or 2). */
 int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_per_group,
                    int32_t* stage);
 
 /*
  * Emit mapping for the unplanned calls: each wavefront tile is K iterations of
- * 64 consecutive ribs (K = 4, 8 or 16), workgroups hold 1..4 wavefronts, and
- * stage = 1 stages the tile's link records in LDS (0 reads them from global
- * memory per rib; -1 keeps the current choice).  0 for K or waves keeps the
- * current value.  Output bits do not depend on the mapping.
+ * 64 consecutive ribs (K = 4, 8 or 16) and workgroups hold 1..4 wavefronts.
+ * stage selects how a tile is walked: 0 rib-major with link records read
+ * from global memory per rib, 1 rib-major with the records staged in LDS,
+ * 2 role-split (records in LDS; the tile's segment ribs and its join and cap
+ * ribs are swept separately, so a wavefront never mixes the two); -1 keeps
+ * the current choice.  0 for K or waves keeps the current value.  Output bits
+ * do not depend on the mapping.
  */
 int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group, int32_t stage);
 

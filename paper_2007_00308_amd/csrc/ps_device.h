@@ -33,7 +33,7 @@ struct alignas(16) LinkRec {
   uint8_t role;           // Role
   uint8_t n_iv;           // intervals (segments); 1 for pivots
   uint8_t kind;           // segment form (segments)
-  uint8_t flags;          // bit 0: first link with ribs of its path; bits 4..7: cap style
+  uint8_t flags;          // kFirstInPath, kFirstSegInPath; bits 4..7: cap style
   float r;                // half the stroke width
   int32_t dsum[kMaxIv];   // cumulative steps Delta_Sigma(1..n_iv); pivots: dsum[0] = J
   float w;                // conic weight (conics)
@@ -43,7 +43,8 @@ struct alignas(16) LinkRec {
 };
 static_assert(sizeof(LinkRec) == 144, "LinkRec must stay 144 bytes");
 
-constexpr uint8_t kFirstInPath = 1;
+constexpr uint8_t kFirstInPath = 1;     // first link with ribs of its path
+constexpr uint8_t kFirstSegInPath = 2;  // first segment with ribs of its path
 
 // Device status word kept at the start of the workspace.
 struct DevStatus {

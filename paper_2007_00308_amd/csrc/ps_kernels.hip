@@ -330,11 +330,12 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
           r.y[k] = B.cy[(int64_t)kk * S + i];
         }
         r.w = (r.kind == PS_KIND_CONIC) ? B.conic_w[i] : 1.0f;
-        // the first link with ribs of the path: no start cap ribs and no
-        // usable segment before this one
-        bool first = cap_steps(B.cap[p], A.q) == 0;
-        for (int k = i - 1; first && k >= b; --k) first = !seg_usable(B, k, A.st, false);
-        if (first) r.flags |= kFirstInPath;
+        // the first segment with ribs of the path (no usable segment before
+        // it), and the first link with ribs (also no start cap ribs)
+        bool first_seg = true;
+        for (int k = i - 1; first_seg && k >= b; --k) first_seg = !seg_usable(B, k, A.st, false);
+        if (first_seg) r.flags |= kFirstSegInPath;
+        if (first_seg && cap_steps(B.cap[p], A.q) == 0) r.flags |= kFirstInPath;
       }
     }
     A.rec[slot] = r;
@@ -574,7 +575,8 @@ struct RibOut {
   double gx, gy, t;
   float Nx, Ny, Px, Py;
   bool chord_ok;
-  bool path_start;
+  bool path_start;       // first rib with ribs of its path
+  bool seg_path_start;   // first segment rib of its path
   bool fixed;
 };
 
@@ -582,14 +584,18 @@ struct RibOut {
 // tangent-angle solve), a pivot for joins and caps, then Eqs.
 // RibVertices-N/P.  A pivot is one interval [0, J] of its own, so the angle
 // and the direction are computed once for both roles (a wavefront usually
-// holds ribs of both) and only the t solve and the point differ.  The record
-// may live in LDS or in global memory.
-template <int PREC, typename Rec>
+// holds ribs of both) and only the t solve and the point differ.  ROLES says
+// which roles the caller can pass: kAnyRole, kSegOnly or kPivotOnly (the
+// other branch is then not compiled).  The record may live in LDS or in
+// global memory.
+constexpr int kAnyRole = 0, kSegOnly = 1, kPivotOnly = 2;
+template <int PREC, int ROLES = kAnyRole, typename Rec>
 __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol, RibOut& o) {
   const uint8_t role = rp.role;
-  const bool seg = role == ROLE_SEG;
+  const bool seg = ROLES == kSegOnly || (ROLES == kAnyRole && role == ROLE_SEG);
   const double rad = (double)rp.r;
   o.path_start = (rp.flags & kFirstInPath) && j == 0;
+  o.seg_path_start = (rp.flags & kFirstSegInPath) && j == 0;
   o.fixed = false;
   // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]; pivots have one
   const int n_iv = rp.n_iv;
@@ -953,6 +959,239 @@ emit_kernel(EmitArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Role-split emit (mapping stage 2).  The same tiles, tickets, look-back and
+// outputs as emit_kernel, but each window of link slots is swept twice: once
+// over its segment ribs, 64 at a time in rib order, then over its pivot ribs.
+// A wavefront never holds both roles, so the t solve and the point run with
+// every lane busy, and pivot ribs cost only their angle, direction and
+// vertices.  Chords join consecutive ribs of one segment, so the arc length
+// is a scan over the segment ribs alone (a path restarts at its first segment
+// rib); a pivot's s is the s of its segment's last rib, or 0 for a start cap.
+struct SplitLDS {
+  long long off[kWin + 1];
+  LinkRec rec[kWin];
+  long long ends[kWin + 1];   // ends[i + 1]: s at slot i's last rib (bit 63: add the tile prefix)
+  int segpos[kWin + 1];       // exclusive positions of the slots' segment ribs
+  int pivpos[kWin + 1];       // ... and of their pivot ribs
+  int first[kWin];            // first rib of the slot in this tile, minus (r0 - 1)
+};
+
+__host__ __device__ constexpr size_t emit_split_lds_per_wave(int K, bool ws) {
+  return sizeof(SplitLDS) + (ws ? (size_t)K * 64 * sizeof(long long) : 0);
+}
+
+template <int K, int PREC, bool WXY, bool WS>
+__global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
+  extern __shared__ unsigned char smem_raw[];
+  unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_split_lds_per_wave(K, WS);
+  SplitLDS& w = *reinterpret_cast<SplitLDS*>(wave_lds);
+  long long* srel = reinterpret_cast<long long*>(wave_lds + sizeof(SplitLDS));   // by rib - r0
+  const int lane = threadIdx.x & 63;
+  const int64_t L = A.n_links;
+  const int64_t R = A.off[L];
+  constexpr int TS = 64 * K - 1;
+  constexpr unsigned long long kNeed = 1ull << 63;   // "add the tile's prefix"
+  const int64_t n_tiles = (R + TS - 1) / TS;
+  if (2 * R > A.capacity || n_tiles > A.max_tiles) return;
+  unsigned long long fixups = 0;
+  __shared__ unsigned int group_ticket;
+  const int n_waves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) group_ticket = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
+    __syncthreads();
+    const int64_t first_tile = (int64_t)group_ticket * n_waves;
+    __syncthreads();   // every wave has read the ticket before the next round writes it
+    if (first_tile >= n_tiles) break;
+    const int64_t tile = first_tile + wave;
+    if (tile < n_tiles) {
+      const int64_t r0 = tile * TS;
+      const int64_t r1 = (r0 + TS < R) ? r0 + TS : R;
+      int64_t base = A.tile_link[tile];
+      long long run = 0;                 // segment chord sum since the tile start or its last path start
+      bool seen_start = false;
+      bool any_need = false;
+      double cgx = 0, cgy = 0, ct = 0;   // the previous segment rib
+      unsigned long long carry_end = kNeed;
+      for (;;) {
+        // ---- stage the window: offsets and records of kWin slots
+        const int64_t idx = base + lane;
+        const long long o_i = (lane <= kWin && idx <= L) ? A.off[idx] : LLONG_MAX;
+        if (lane <= kWin) w.off[lane] = o_i;
+        const long long o_n = __shfl(o_i, lane + 1 < 64 ? lane + 1 : 63, 64);
+        {
+          const int n_rec = (int)(L - base < kWin ? L - base : kWin);
+          const int4* src = reinterpret_cast<const int4*>(A.rec + base);
+          int4* dst = reinterpret_cast<int4*>(w.rec);
+          for (int c = lane; c < n_rec * (int)(sizeof(LinkRec) / 16); c += 64) dst[c] = src[c];
+        }
+        // ---- each slot's ribs inside the tile; the link holding r0 also
+        // gives rib r0 - 1 when it is a segment begun earlier (first chord)
+        int ns = 0, np = 0, fr = 0;
+        if (lane < kWin && idx < L) {
+          const bool segl = w.rec[lane].role == ROLE_SEG;
+          long long a = o_i > r0 ? o_i : r0;
+          if (segl && r0 > 0 && o_i < r0 && r0 < o_n) a = r0 - 1;
+          const long long b = o_n < r1 ? o_n : r1;
+          const int n = b > a ? (int)(b - a) : 0;
+          ns = segl ? n : 0;
+          np = segl ? 0 : n;
+          fr = (int)(a - (r0 - 1));
+        }
+        const int ns_in = wave_incl_scan(ns), np_in = wave_incl_scan(np);
+        const int NS = __builtin_amdgcn_readlane(ns_in, 63), NP = __builtin_amdgcn_readlane(np_in, 63);
+        if (lane <= kWin) {
+          w.segpos[lane] = ns_in - ns;
+          w.pivpos[lane] = np_in - np;
+          if (WS) w.ends[lane] = (lane == 0) ? (long long)carry_end : (long long)kNeed;
+        }
+        if (lane < kWin) w.first[lane] = fr;
+        // ---- sweep A: segment ribs
+        for (int q0 = 0; q0 < NS; q0 += 64) {
+          const int q = q0 + lane;
+          RibOut o;
+          o.gx = o.gy = o.t = 0; o.chord_ok = false; o.seg_path_start = false; o.fixed = false;
+          int64_t r = -1;
+          int i = 0;
+          if (q < NS) {
+            // largest i with segpos[i] <= q (it holds segment ribs)
+            int a = 0, b = kWin - 1;
+            while (a < b) {
+              const int m = (a + b + 1) >> 1;
+              if (w.segpos[m] <= q) a = m; else b = m - 1;
+            }
+            i = a;
+            r = (r0 - 1) + w.first[i] + (q - w.segpos[i]);
+            compute_rib<PREC, kSegOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, o);
+            if (WXY && r >= r0) {
+              *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
+              *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
+            }
+            fixups += o.fixed ? 1 : 0;
+          }
+          if (WS) {
+            const bool mine = q < NS && r >= r0;
+            double pgx = wave_shr1(o.gx), pgy = wave_shr1(o.gy), pt = wave_shr1(o.t);
+            if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
+            long long c = 0;
+            if (mine && o.chord_ok && o.t >= pt) {
+              const double dx = o.gx - pgx, dy = o.gy - pgy;
+              c = llrint(sqrt64(dx * dx + dy * dy) * kFix);
+            }
+            int f = (mine && o.seg_path_start) ? 1 : 0;
+            if (__ballot(f != 0 || c >= (1ll << 50)) == 0ull) {
+              unsigned lo = (unsigned)c & 0xffffffu, hi = (unsigned)(c >> 24);
+              lo = scan_step_u32<0x111, 0xf>(lo); hi = scan_step_u32<0x111, 0xf>(hi);
+              lo = scan_step_u32<0x112, 0xf>(lo); hi = scan_step_u32<0x112, 0xf>(hi);
+              lo = scan_step_u32<0x114, 0xf>(lo); hi = scan_step_u32<0x114, 0xf>(hi);
+              lo = scan_step_u32<0x118, 0xf>(lo); hi = scan_step_u32<0x118, 0xf>(hi);
+              lo = scan_step_u32<0x142, 0xa>(lo); hi = scan_step_u32<0x142, 0xa>(hi);
+              lo = scan_step_u32<0x143, 0xc>(lo); hi = scan_step_u32<0x143, 0xc>(hi);
+              c = (long long)(((unsigned long long)hi << 24) + lo);
+            } else {
+              seg_scan_step<0x111, 0xf>(c, f);
+              seg_scan_step<0x112, 0xf>(c, f);
+              seg_scan_step<0x114, 0xf>(c, f);
+              seg_scan_step<0x118, 0xf>(c, f);
+              seg_scan_step<0x142, 0xa>(c, f);
+              seg_scan_step<0x143, 0xc>(c, f);
+            }
+            const bool need = !(f || seen_start);
+            const unsigned long long v =
+                (unsigned long long)(f ? c : run + c) | (need ? kNeed : 0ull);
+            if (mine) {
+              srel[r - r0] = (long long)v;
+              if (r == w.off[i + 1] - 1) w.ends[i + 1] = (long long)v;   // the segment's last rib
+            }
+            any_need = any_need || (__ballot(mine && need) != 0ull);
+            const long long c63 = readlane_i64(c, 63);
+            const int f63 = __builtin_amdgcn_readlane(f, 63);
+            run = f63 ? c63 : run + c63;
+            seen_start = seen_start || (f63 != 0);
+            // the last segment rib of this batch carries into the next one
+            const int last = (NS - q0 < 64) ? NS - q0 - 1 : 63;
+            cgx = readlane_f64(o.gx, last); cgy = readlane_f64(o.gy, last); ct = readlane_f64(o.t, last);
+          }
+        }
+        // ---- sweep B: pivot ribs
+        for (int p0 = 0; p0 < NP; p0 += 64) {
+          const int pq = p0 + lane;
+          if (pq < NP) {
+            int a = 0, b = kWin - 1;
+            while (a < b) {
+              const int m = (a + b + 1) >> 1;
+              if (w.pivpos[m] <= pq) a = m; else b = m - 1;
+            }
+            const int i = a;
+            const int64_t r = (r0 - 1) + w.first[i] + (pq - w.pivpos[i]);
+            RibOut o;
+            compute_rib<PREC, kPivotOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, o);
+            if (WXY) {
+              *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
+              *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
+            }
+            if (WS) {
+              // a join or end cap takes its segment's end value (slot i - 1)
+              const long long v = (w.rec[i].role == ROLE_SCAP) ? 0ll : w.ends[i];
+              srel[r - r0] = v;
+              any_need = any_need || ((unsigned long long)v & kNeed);
+            }
+          }
+          if (WS) any_need = __ballot(any_need) != 0ull;
+        }
+        if (WS) carry_end = (unsigned long long)w.ends[kWin];
+        const long long wend = w.off[kWin];   // first rib past the window
+        if (wend >= r1) break;
+        base += kWin;
+      }
+      if (WS) {
+        // look-back exactly as in emit_kernel
+        const unsigned long long agg = (unsigned long long)run & kValMask;
+        any_need = __ballot(any_need) != 0ull;
+        if (lane == 0) desc_publish(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg);
+        unsigned long long prefix = 0;
+        if (any_need) {
+          int64_t bT = tile - 1;
+          for (;;) {
+            const int64_t Ti = bT - lane;
+            const unsigned long long wd = Ti >= 0 ? desc_read(&A.desc[Ti]) : (2ull << 62);
+            const unsigned stt = (unsigned)(wd >> 62);
+            const unsigned long long incl = __ballot(stt == 2);
+            const int stop = incl ? __builtin_ctzll(incl) : 64;
+            const unsigned long long upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
+            if (__ballot(stt == 0) & upto) { __builtin_amdgcn_s_sleep(1); continue; }
+            unsigned long long v = lane <= stop ? (wd & kValMask) : 0ull;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+            prefix += v;
+            if (stop < 64) break;
+            bT -= 64;
+          }
+          if (lane == 0 && !seen_start)
+            desc_publish(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask));
+        }
+        const long long pre = (long long)prefix;
+#pragma unroll 2
+        for (int k = 0; k < K; ++k) {
+          const int64_t d = 64 * k + lane;
+          if (d < r1 - r0) {
+            const unsigned long long sv = (unsigned long long)srel[d];
+            const long long sf = (long long)(sv & ~kNeed) + ((sv & kNeed) ? pre : 0);
+            const float sx = (float)((double)sf * (1.0 / kFix));
+            *reinterpret_cast<float2*>(A.vs + 2 * (r0 + d)) = make_float2(sx, sx);
+          }
+        }
+      }
+    }
+  }
+  if (PREC == PS_PREC_FP32_FIXUP) {
+    unsigned long long v = fixups;
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0 && v) atomicAdd(&A.st->fixups, v);
+  }
+}
+
 // ===========================================================================
 // Dash (Sec. "Dashing")
 // ===========================================================================
@@ -1135,7 +1374,7 @@ int fail(int code, const char* fmt, ...) {
 struct EmitConfig {
   int K = 8;
   int waves = 4;
-  int stage = 1;   // 1: link records staged in LDS per wave; 0: read from global memory
+  int stage = 2;   // 0 rib-major (global records), 1 rib-major (LDS records), 2 role-split
 };
 EmitConfig g_cfg;
 bool g_autotune = true;
@@ -1244,48 +1483,65 @@ int do_scan_i32(const int32_t* in, int64_t n_max, const int64_t* n_dev, int64_t*
   return PS_OK;
 }
 
-template <int K, int PREC, bool WXY, bool WS, bool STAGE>
+// Emit mappings: 0 rib-major with records read from global memory, 1
+// rib-major with records staged in LDS, 2 role-split (records in LDS).
+template <int K, int PREC, bool WXY, bool WS, int MAP>
 void emit_launcher(EmitArgs a, int grid, int block, hipStream_t s) {
-  const size_t lds = (size_t)(block / 64) * emit_lds_per_wave(K, WS, STAGE);
-  // above 64 KiB of dynamic LDS the kernel has to be allowed it once (every
+  // above 64 KiB of dynamic LDS a kernel has to be allowed it once (every
   // configuration is first launched eagerly, before any graph capture)
-  static const hipError_t allowed = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&emit_kernel<K, PREC, WXY, WS, STAGE>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * emit_lds_per_wave(K, WS, STAGE)));
-  (void)allowed;
-  hipLaunchKernelGGL((emit_kernel<K, PREC, WXY, WS, STAGE>), dim3(grid), dim3(block), lds, s, a);
+  if constexpr (MAP == 2) {
+    const size_t lds = (size_t)(block / 64) * emit_split_lds_per_wave(K, WS);
+    static const hipError_t allowed = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&emit_split_kernel<K, PREC, WXY, WS>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * emit_split_lds_per_wave(K, WS)));
+    (void)allowed;
+    hipLaunchKernelGGL((emit_split_kernel<K, PREC, WXY, WS>), dim3(grid), dim3(block), lds, s, a);
+  } else {
+    constexpr bool STAGE = MAP == 1;
+    const size_t lds = (size_t)(block / 64) * emit_lds_per_wave(K, WS, STAGE);
+    static const hipError_t allowed = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&emit_kernel<K, PREC, WXY, WS, STAGE>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * emit_lds_per_wave(K, WS, STAGE)));
+    (void)allowed;
+    hipLaunchKernelGGL((emit_kernel<K, PREC, WXY, WS, STAGE>), dim3(grid), dim3(block), lds, s, a);
+  }
 }
 
 using EmitLaunch = void (*)(EmitArgs, int, int, hipStream_t);
 
-template <int PREC, bool WXY, bool WS, bool STAGE>
+template <int PREC, bool WXY, bool WS, int MAP>
 EmitLaunch pick_k(int K) {
   switch (K) {
-    case 4: return emit_launcher<4, PREC, WXY, WS, STAGE>;
-    case 8: return emit_launcher<8, PREC, WXY, WS, STAGE>;
-    case 16: return emit_launcher<16, PREC, WXY, WS, STAGE>;
+    case 4: return emit_launcher<4, PREC, WXY, WS, MAP>;
+    case 8: return emit_launcher<8, PREC, WXY, WS, MAP>;
+    case 16: return emit_launcher<16, PREC, WXY, WS, MAP>;
     default: return nullptr;
   }
 }
 
-template <bool WXY, bool WS, bool STAGE>
+template <bool WXY, bool WS, int MAP>
 EmitLaunch pick_prec(int prec, int K) {
   switch (prec) {
-    case PS_PREC_FP32: return pick_k<PS_PREC_FP32, WXY, WS, STAGE>(K);
-    case PS_PREC_FP32_FIXUP: return pick_k<PS_PREC_FP32_FIXUP, WXY, WS, STAGE>(K);
-    default: return pick_k<PS_PREC_FP64, WXY, WS, STAGE>(K);
+    case PS_PREC_FP32: return pick_k<PS_PREC_FP32, WXY, WS, MAP>(K);
+    case PS_PREC_FP32_FIXUP: return pick_k<PS_PREC_FP32_FIXUP, WXY, WS, MAP>(K);
+    default: return pick_k<PS_PREC_FP64, WXY, WS, MAP>(K);
   }
 }
 
-template <bool STAGE>
+template <int MAP>
 EmitLaunch pick_mode(int prec, int K, bool wxy, bool ws) {
-  if (wxy && ws) return pick_prec<true, true, STAGE>(prec, K);
-  if (wxy) return pick_prec<true, false, STAGE>(prec, K);
-  return pick_prec<false, true, STAGE>(prec, K);
+  if (wxy && ws) return pick_prec<true, true, MAP>(prec, K);
+  if (wxy) return pick_prec<true, false, MAP>(prec, K);
+  return pick_prec<false, true, MAP>(prec, K);
 }
 
-EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws, bool stage) {
-  return stage ? pick_mode<true>(prec, K, wxy, ws) : pick_mode<false>(prec, K, wxy, ws);
+EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws, int map) {
+  switch (map) {
+    case 0: return pick_mode<0>(prec, K, wxy, ws);
+    case 1: return pick_mode<1>(prec, K, wxy, ws);
+    case 2: return pick_mode<2>(prec, K, wxy, ws);
+    default: return nullptr;
+  }
 }
 
 bool valid_k(int K) { return K == 4 || K == 8 || K == 16; }
@@ -1319,7 +1575,7 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
                 int stage, hipStream_t s) {
   const int64_t L = n_links_of(b);
   const int TS = 64 * K - 1;
-  EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr, stage != 0);
+  EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr, stage);
   if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", K);
   const unsigned prep_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (L + 255) / 256), 8192);
   hipLaunchKernelGGL(emit_prepare_kernel, dim3(prep_grid), dim3(256), 0, s, off, L, TS, v.tile_link,
@@ -1455,7 +1711,7 @@ size_t ps_workspace_bytes(const ps_batch* b, const ps_params* p, int64_t vertex_
 int ps_set_emit_config(int32_t K, int32_t waves, int32_t stage) {
   if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 4, 8 or 16");
   if (waves < 0 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
-  if (stage < -1 || stage > 1) return fail(PS_E_ARG, "stage must be -1 (keep), 0 or 1");
+  if (stage < -1 || stage > 2) return fail(PS_E_ARG, "stage must be -1 (keep), 0, 1 or 2");
   std::lock_guard<std::mutex> lk(g_mu);
   if (K) g_cfg.K = K;
   if (waves) g_cfg.waves = waves;
@@ -1588,7 +1844,7 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   float best = 1e30f;
   const int Ks[3] = {4, 8, 16};
   const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
-  for (int st = 1; tune && st >= 0; --st)
+  for (int st = 2; tune && st >= 0; --st)
     for (int ki = 0; ki < 3; ++ki)
       for (int wi = 0; wi < 3; ++wi) {
         float ms = 0;

@@ -155,14 +155,14 @@ def test_mappings_agree_and_are_deterministic():
     b = W.config2(n_paths=48, max_segs=96)
     outs = []
     try:
-        for stage in (1, 0):
+        for stage in (2, 1, 0):
             for K in (4, 8, 16):
                 for waves in (1, 4):
                     ps.ps_set_emit_config(K, waves, stage)
                     _, o = _gpu(b)
                     outs.append(((K, waves, stage), _np(o["vx"]), _np(o["vy"]), _np(o["vs"])))
     finally:
-        ps.ps_set_emit_config(8, 4, 1)
+        ps.ps_set_emit_config(8, 4, 2)
     for cfg, vx, vy, vs in outs[1:]:
         assert np.array_equal(vx, outs[0][1]) and np.array_equal(vy, outs[0][2]), cfg
         assert np.array_equal(vs, outs[0][3]), cfg
