@@ -32,6 +32,32 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_source_digest() -> str:
+    """sha256 over the kernel sources; a stored counter summary applies only to
+    the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ps_kernels.hip", "ps_device.h"):
+        with open(os.path.join(ROOT, "paper_2007_00308_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(per_launch_config: str):
+    """HBM bytes per emit launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    stored in profiles/ (scaled by the copy-kernel calibration), or None when
+    they were taken on other kernel sources or another emit mapping."""
+    path = os.path.join(ROOT, "profiles", "emit_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    return rec.get("emit_configs", {}).get(per_launch_config)
+
+
 def algorithmic_bytes(V: int, S: int, P: int) -> int:
     # each vertex written once as x, y, s (FP32); control data read once per
     # segment (4 x,y FP32 points, kind, weight); path data (CSR, width, styles)
@@ -52,7 +78,7 @@ def main() -> int:
                          "instead of the plan's autotuning, e.g. for profiles of one mapping")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit"], default=None,
+    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit", "c1"], default=None,
                     help="secondary measurements: the near-degenerate precision study, the long "
                          "dashed path, or the stress configuration at q in {pi/16, pi/64, pi/256}")
     args = ap.parse_args()
@@ -231,7 +257,7 @@ def main() -> int:
                    "emit_stage": stage},
         "gb_per_s": B_alg / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": emit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": emit_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": emit_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(f"{K},{waves},{stage}"),
                      "kernel": "emit (prepare + persistent emit, one ps_emit call)",
                      "ms_per_launch": emit_ms, "algorithmic_bytes_per_launch": emit_bytes},
         "per_path": per_path,
@@ -395,7 +421,43 @@ def study_emit(args, torch, ps, W, dev):
     return 0
 
 
-STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5, "emit": study_emit}
+def study_c1(args, torch, ps, W, dev):
+    """C1, one path of 64 cubics: latency of the whole chain per path (one plan
+    replay, and the three unplanned calls) and its vertices/s."""
+    b = W.config1()
+    db = ps.DeviceBatch(b, device=dev)
+    first = ps.stroke(db, b.q)
+    R = first["total_ribs"]
+    del first
+    plan = ps.Plan(db, b.q, vertex_capacity=2 * R)
+    ms = _time_plan(torch, plan, max(args.steps, 50), args.warmup)
+    lr = torch.empty(db.n_links, dtype=torch.int32, device=dev)
+    of = torch.empty(db.n_links + 1, dtype=torch.int64, device=dev)
+
+    def calls():
+        ps.ps_count(db, plan.params, lr, plan.ws)
+        ps.ps_scan(lr, db.n_links, of, plan.ws)
+        ps.ps_emit(db, plan.params, of, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
+
+    for _ in range(5):
+        calls()
+    torch.cuda.synchronize()
+    n = max(args.steps, 50)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        calls()
+    torch.cuda.synchronize()
+    ms_calls = 1e3 * (time.perf_counter() - t0) / n
+    plan.close()
+    row = {"study": "c1", "workload": "C1: 1 path x 64 cubics, q=pi/90, round joins", "ribs": R,
+           "us_per_path_plan": 1e3 * ms, "us_per_path_calls": 1e3 * ms_calls,
+           "vertices_per_s_plan": 2 * R / (ms * 1e-3)}
+    log(str(row))
+    print(json.dumps(row), flush=True)
+    return 0
+
+
+STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5, "emit": study_emit, "c1": study_c1}
 
 
 if __name__ == "__main__":

@@ -977,8 +977,66 @@ struct SplitLDS {
   int first[kWin];            // first rib of the slot in this tile, minus (r0 - 1)
 };
 
+// two buffers of per-rib partial sums: a tile whose predecessors have not all
+// published yet is parked in one while the wavefront computes its next tile
 __host__ __device__ constexpr size_t emit_split_lds_per_wave(int K, bool ws) {
-  return sizeof(SplitLDS) + (ws ? (size_t)K * 64 * sizeof(long long) : 0);
+  return sizeof(SplitLDS) + (ws ? 2 * (size_t)K * 64 * sizeof(long long) : 0);
+}
+
+// A computed tile whose arc length still needs its prefix.
+struct TileState {
+  int64_t tile, r0, r1;
+  unsigned long long agg;
+  bool seen_start, any_need;
+  int buf;
+};
+
+// Finish a tile: collect its prefix from the look-back words of earlier tiles,
+// publish its inclusive word, write vs.  Without `block`, gives up (returns
+// false, nothing written) when a needed earlier word is not published yet.
+template <int K>
+__device__ __forceinline__ bool finish_tile(const EmitArgs& A, const TileState& T, const long long* srel,
+                                            bool block) {
+  constexpr unsigned long long kNeed = 1ull << 63;
+  const int lane = threadIdx.x & 63;
+  unsigned long long prefix = 0;
+  if (T.any_need) {
+    int64_t bT = T.tile - 1;
+    for (;;) {
+      const int64_t Ti = bT - lane;
+      const unsigned long long wd = Ti >= 0 ? desc_read(&A.desc[Ti]) : (2ull << 62);
+      const unsigned stt = (unsigned)(wd >> 62);
+      const unsigned long long incl = __ballot(stt == 2);
+      const int stop = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive word
+      const unsigned long long upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
+      if (__ballot(stt == 0) & upto) {
+        if (!block) return false;
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      unsigned long long v = lane <= stop ? (wd & kValMask) : 0ull;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+      prefix += v;
+      if (stop < 64) break;
+      bT -= 64;
+    }
+    if (lane == 0 && !T.seen_start)
+      desc_publish(&A.desc[T.tile], (2ull << 62) | ((prefix + T.agg) & kValMask));
+  }
+  const long long pre = (long long)prefix;
+  const long long* sr = srel + (size_t)T.buf * (64 * K);
+#pragma unroll 2
+  for (int k = 0; k < K; ++k) {
+    const int64_t d = 64 * k + lane;
+    if (d < T.r1 - T.r0) {
+      const unsigned long long sv = (unsigned long long)sr[d];
+      const long long sf = (long long)(sv & ~kNeed) + ((sv & kNeed) ? pre : 0);
+      const float sx = (float)((double)sf * (1.0 / kFix));
+      *reinterpret_cast<float2*>(A.vs + 2 * (T.r0 + d)) = make_float2(sx, sx);
+    }
+  }
+  return true;
 }
 
 template <int K, int PREC, bool WXY, bool WS>
@@ -986,7 +1044,7 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
   extern __shared__ unsigned char smem_raw[];
   unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_split_lds_per_wave(K, WS);
   SplitLDS& w = *reinterpret_cast<SplitLDS*>(wave_lds);
-  long long* srel = reinterpret_cast<long long*>(wave_lds + sizeof(SplitLDS));   // by rib - r0
+  long long* const srel_base = reinterpret_cast<long long*>(wave_lds + sizeof(SplitLDS));   // 2 x (rib - r0)
   const int lane = threadIdx.x & 63;
   const int64_t L = A.n_links;
   const int64_t R = A.off[L];
@@ -998,6 +1056,9 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
   __shared__ unsigned int group_ticket;
   const int n_waves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
+  TileState parked;
+  parked.tile = -1; parked.r0 = parked.r1 = 0; parked.agg = 0;
+  parked.seen_start = parked.any_need = false; parked.buf = 0;
   for (;;) {
     if (threadIdx.x == 0) group_ticket = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
     __syncthreads();
@@ -1006,6 +1067,8 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
     if (first_tile >= n_tiles) break;
     const int64_t tile = first_tile + wave;
     if (tile < n_tiles) {
+      const int buf = (WS && parked.tile >= 0) ? 1 - parked.buf : 0;
+      long long* const srel = srel_base + (size_t)buf * (64 * K);
       const int64_t r0 = tile * TS;
       const int64_t r1 = (r0 + TS < R) ? r0 + TS : R;
       int64_t base = A.tile_link[tile];
@@ -1146,45 +1209,22 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
         base += kWin;
       }
       if (WS) {
-        // look-back exactly as in emit_kernel
         const unsigned long long agg = (unsigned long long)run & kValMask;
         any_need = __ballot(any_need) != 0ull;
         if (lane == 0) desc_publish(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg);
-        unsigned long long prefix = 0;
-        if (any_need) {
-          int64_t bT = tile - 1;
-          for (;;) {
-            const int64_t Ti = bT - lane;
-            const unsigned long long wd = Ti >= 0 ? desc_read(&A.desc[Ti]) : (2ull << 62);
-            const unsigned stt = (unsigned)(wd >> 62);
-            const unsigned long long incl = __ballot(stt == 2);
-            const int stop = incl ? __builtin_ctzll(incl) : 64;
-            const unsigned long long upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
-            if (__ballot(stt == 0) & upto) { __builtin_amdgcn_s_sleep(1); continue; }
-            unsigned long long v = lane <= stop ? (wd & kValMask) : 0ull;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-            prefix += v;
-            if (stop < 64) break;
-            bT -= 64;
-          }
-          if (lane == 0 && !seen_start)
-            desc_publish(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask));
+        TileState cur;
+        cur.tile = tile; cur.r0 = r0; cur.r1 = r1; cur.agg = agg;
+        cur.seen_start = seen_start; cur.any_need = any_need; cur.buf = buf;
+        // the parked tile's predecessors have had a whole tile's time
+        if (parked.tile >= 0) {
+          finish_tile<K>(A, parked, srel_base, true);
+          parked.tile = -1;
         }
-        const long long pre = (long long)prefix;
-#pragma unroll 2
-        for (int k = 0; k < K; ++k) {
-          const int64_t d = 64 * k + lane;
-          if (d < r1 - r0) {
-            const unsigned long long sv = (unsigned long long)srel[d];
-            const long long sf = (long long)(sv & ~kNeed) + ((sv & kNeed) ? pre : 0);
-            const float sx = (float)((double)sf * (1.0 / kFix));
-            *reinterpret_cast<float2*>(A.vs + 2 * (r0 + d)) = make_float2(sx, sx);
-          }
-        }
+        if (!finish_tile<K>(A, cur, srel_base, false)) parked = cur;
       }
     }
   }
+  if (WS && parked.tile >= 0) finish_tile<K>(A, parked, srel_base, true);
   if (PREC == PS_PREC_FP32_FIXUP) {
     unsigned long long v = fixups;
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
