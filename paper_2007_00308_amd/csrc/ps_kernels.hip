@@ -709,6 +709,15 @@ __device__ __forceinline__ unsigned long long desc_read(const unsigned long long
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// round(x) to int64 for x >= 0 (ties to even, as llrint): below 2^52 the sum
+// x + 2^52 is rounded to an integer by the FP64 add itself, and its bits
+// minus those of 2^52 are that integer
+__device__ __forceinline__ long long fix_round(double x) {
+  if (x < 4503599627370496.0)
+    return __double_as_longlong(x + 4503599627370496.0) - 0x4330000000000000ll;
+  return llrint(x);
+}
+
 // Cross-lane moves on the VALU (DPP) rather than through the LDS crossbar.
 // A lane whose source lies outside its row, or that row_mask leaves out,
 // reads 0: the identity of the sums below.
@@ -871,7 +880,7 @@ emit_kernel(EmitArgs A) {
           long long c = 0;
           if (mine && o.chord_ok && o.t >= pt) {
             const double dx = o.gx - pgx, dy = o.gy - pgy;
-            c = llrint(sqrt64(dx * dx + dy * dy) * kFix);
+            c = fix_round(sqrt64(dx * dx + dy * dy) * kFix);
           }
           int f = (mine && o.path_start) ? 1 : 0;
           // inclusive scan across the wave: Hillis-Steele inside each row of
@@ -1048,7 +1057,7 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
   const int lane = threadIdx.x & 63;
   const int64_t L = A.n_links;
   const int64_t R = A.off[L];
-  constexpr int TS = 64 * K - 1;
+  constexpr int TS = 64 * K;   // whole cache lines per tile (the first chord needs no lane of its own)
   constexpr unsigned long long kNeed = 1ull << 63;   // "add the tile's prefix"
   const int64_t n_tiles = (R + TS - 1) / TS;
   if (2 * R > A.capacity || n_tiles > A.max_tiles) return;
@@ -1140,7 +1149,7 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
             long long c = 0;
             if (mine && o.chord_ok && o.t >= pt) {
               const double dx = o.gx - pgx, dy = o.gy - pgy;
-              c = llrint(sqrt64(dx * dx + dy * dy) * kFix);
+              c = fix_round(sqrt64(dx * dx + dy * dy) * kFix);
             }
             int f = (mine && o.seg_path_start) ? 1 : 0;
             if (__ballot(f != 0 || c >= (1ll << 50)) == 0ull) {
@@ -1614,7 +1623,7 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
                 float* vs, int64_t cap, const WsView& v, const WsLayout& w, int K, int waves,
                 int stage, hipStream_t s) {
   const int64_t L = n_links_of(b);
-  const int TS = 64 * K - 1;
+  const int TS = (stage == 2) ? 64 * K : 64 * K - 1;   // the role-split tile has no overlap lane
   EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr, stage);
   if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", K);
   const unsigned prep_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (L + 255) / 256), 8192);
