@@ -46,7 +46,8 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Workspace
 // ===========================================================================
 struct WsLayout {
-  size_t status, rec, scan, tile_link, desc, dash_r, dash_d, dash_rpos, dash_dpos, dash_scan, total;
+  size_t status, rec, seg_ang, seg_ok, scan, tile_link, desc, dash_r, dash_d, dash_rpos, dash_dpos,
+      dash_scan, total;
   int64_t max_tiles, n_links, max_ribs, nb_links, nb_ribs;
 };
 
@@ -63,6 +64,8 @@ WsLayout ws_layout(int64_t n_links, int64_t vertex_capacity, int n_dash) {
   size_t o = 0;
   w.status = o; o = align_up(o + 256, 256);
   w.rec = o; o = align_up(o + (size_t)n_links * sizeof(LinkRec), 256);
+  w.seg_ang = o; o = align_up(o + (size_t)n_links * 16, 256);   // n_links >= n_segs
+  w.seg_ok = o; o = align_up(o + (size_t)n_links, 256);
   w.scan = o; o = align_up(o + (size_t)(w.nb_links + 1) * 8, 256);
   w.tile_link = o; o = align_up(o + (size_t)(w.max_tiles + 1) * 4, 256);
   w.desc = o; o = align_up(o + (size_t)w.max_tiles * 8, 256);
@@ -86,6 +89,8 @@ struct CountArgs {
   double q;
   int32_t* link_ribs;
   LinkRec* rec;
+  double2* seg_ang;
+  uint8_t* seg_ok;
   DevStatus* st;
 };
 
@@ -114,11 +119,11 @@ __device__ inline bool seg_usable(const ps_batch& B, int i, DevStatus* st, bool 
 
 #pragma clang fp contract(off)
 
-// Intervals of one usable segment, written into rec, and the end tangent
-// angle (as the joins use it) into psi_end.  Returns the step count N (the
-// segment has N+1 ribs), or -1 if it needs more than kMaxIv intervals.
-__device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, double& psi_end,
-                             DevStatus* st) {
+// Intervals of one usable segment, written into rec, from its start and end
+// tangent angles.  Returns the step count N (the segment has N+1 ribs), or -1
+// if it needs more than kMaxIv intervals.
+__device__ int segment_setup(const ps_batch& B, int i, double q, double psi_start, double psi_end,
+                             LinkRec& rec, DevStatus* st) {
   const Seg s = load_seg(B, i);
   float X[4], Y[4];
   const int64_t S = B.n_segs;
@@ -129,7 +134,7 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, d
   }
   double sx, sy;
   start_dir(s, sx, sy);
-  const double psi0 = unit_angle(sx, sy);
+  const double psi0 = psi_start;   // unit_angle(sx, sy), computed by the angles kernel
   const double ax = s.x[1] - s.x[0], ay = s.y[1] - s.y[0];
   const double bx = s.x[2] - s.x[1], by = s.y[2] - s.y[1];
   const double cx = s.x[3] - s.x[2], cy = s.y[3] - s.y[2];
@@ -150,9 +155,6 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, LinkRec& rec, d
   int n = 0, N = 0;
   double psi_run = psi0;
   rec.psi[0] = psi0;
-  double ex, ey;
-  end_dir(s, ex, ey);
-  psi_end = unit_angle(ex, ey);
   if (collinear) {
     // flat pieces of one step, split by +pi pivots at the simple roots of
     // g'(t).d where the segment reverses along its line (a cusp)
@@ -263,11 +265,24 @@ __device__ int cap_steps(int style, double q) {
   return 0;
 }
 
-__device__ inline double seg_start_angle(const ps_batch& B, int i) {
-  const Seg s = load_seg(B, i);
-  double dx, dy;
-  start_dir(s, dx, dy);
-  return unit_angle(dx, dy);
+// First count pass, one thread per segment: whether it is usable and its
+// start and end tangent angles (Eq. Psi at t = 0 and 1, through the end
+// gradients and their fallbacks).  Reports bad or non-finite segments.
+__global__ void __launch_bounds__(256) count_angles_kernel(CountArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.B.n_segs) return;
+  const bool ok = seg_usable(A.B, (int)i, A.st, true);
+  double2 ang = make_double2(0.0, 0.0);
+  if (ok) {
+    const Seg s = load_seg(A.B, (int)i);
+    double sx, sy, ex, ey;
+    start_dir(s, sx, sy);
+    end_dir(s, ex, ey);
+    ang.x = unit_angle(sx, sy);
+    ang.y = unit_angle(ex, ey);
+  }
+  A.seg_ang[i] = ang;
+  A.seg_ok[i] = ok ? 1 : 0;
 }
 
 #pragma clang fp contract(on)
@@ -310,16 +325,17 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     const bool sok = (B.join[p] <= PS_JOIN_TRIANGLE) && (B.cap[p] <= PS_CAP_TRIANGLE);
     if (!isfinite(wd)) set_flag(A.st, PS_STATUS_NONFINITE);
     else if (!wok || !sok) set_flag(A.st, PS_STATUS_BAD_VALUE);
-    const bool usable = wok && sok && seg_usable(B, i, A.st, true);
+    const bool usable = wok && sok && A.seg_ok[i];   // segment problems: reported by the angles pass
     const float half_w = 0.5f * wd;
     LinkRec r;
     clear_rec(r);
     r.kind = B.kind[i];
     r.r = half_w;
     int ribs = 0;
-    double psi_e = 0;
+    const double2 ang = A.seg_ang[i];
+    const double psi_e = ang.y;
     if (usable) {
-      const int N = segment_setup(B, i, A.q, r, psi_e, A.st);
+      const int N = segment_setup(B, i, A.q, ang.x, ang.y, r, A.st);
       if (N > 0) {
         ribs = N + 1;
         r.role = ROLE_SEG;
@@ -333,7 +349,7 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
         // the first segment with ribs of the path (no usable segment before
         // it), and the first link with ribs (also no start cap ribs)
         bool first_seg = true;
-        for (int k = i - 1; first_seg && k >= b; --k) first_seg = !seg_usable(B, k, A.st, false);
+        for (int k = i - 1; first_seg && k >= b; --k) first_seg = !A.seg_ok[k];
         if (first_seg) r.flags |= kFirstSegInPath;
         if (first_seg && cap_steps(B.cap[p], A.q) == 0) r.flags |= kFirstInPath;
       }
@@ -349,8 +365,8 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     const int n = npts_of(B.kind[i]);
     const float ex = B.cx[(int64_t)(n - 1) * S + i], ey = B.cy[(int64_t)(n - 1) * S + i];
     for (int k = i + 1; k < e; ++k) {
-      if (!seg_usable(B, k, A.st, false)) continue;
-      double d = adiff(seg_start_angle(B, k), psi_e);
+      if (!A.seg_ok[k]) continue;
+      double d = adiff(A.seg_ang[k].x, psi_e);
       if (d == -kPi) d = kPi;   // antiparallel: turn +pi
       const int J = join_steps(B.join[p], d, A.q);
       write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, psi_e, d, J, ex, ey, 0, half_w, false);
@@ -369,8 +385,8 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
                     B.join[p] <= PS_JOIN_TRIANGLE;
     if (ok) {
       for (int k = b; k < e; ++k) {
-        if (!seg_usable(B, k, A.st, false)) continue;
-        const double psi_s = seg_start_angle(B, k);
+        if (!A.seg_ok[k]) continue;
+        const double psi_s = A.seg_ang[k].x;
         const int J = cap_steps(B.cap[p], A.q);
         // start cap: from the reversed start tangent, +pi round to it
         write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, psi_s - kPi, kPi, J, B.cx[k], B.cy[k],
@@ -597,10 +613,18 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
   o.path_start = (rp.flags & kFirstInPath) && j == 0;
   o.seg_path_start = (rp.flags & kFirstSegInPath) && j == 0;
   o.fixed = false;
-  // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]; pivots have one
+  // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]; pivots have one.  The
+  // cumulative counts increase strictly, so k - 1 is the number of interior
+  // boundaries j has passed: counted without a chain of dependent reads
   const int n_iv = rp.n_iv;
   int k = 1, d0 = 0;
-  while (k < n_iv && j > rp.dsum[k - 1]) { d0 = rp.dsum[k - 1]; ++k; }
+#pragma unroll
+  for (int m = 0; m < kMaxIv - 1; ++m) {
+    const int dm = rp.dsum[m];
+    const bool past = (m < n_iv - 1) && (j > dm);
+    k += past ? 1 : 0;
+    d0 = past ? dm : d0;
+  }
   const int d1 = rp.dsum[k - 1];
   const double psa = rp.psi[k - 1], psb = rp.psi[k];
   const bool at0 = j == d0, at1 = j == d1;
@@ -1127,13 +1151,10 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
           int64_t r = -1;
           int i = 0;
           if (q < NS) {
-            // largest i with segpos[i] <= q (it holds segment ribs)
-            int a = 0, b = kWin - 1;
-            while (a < b) {
-              const int m = (a + b + 1) >> 1;
-              if (w.segpos[m] <= q) a = m; else b = m - 1;
-            }
-            i = a;
+            // largest i with segpos[i] <= q (it holds segment ribs); the
+            // positions do not decrease, so i counts the slots at or below q
+#pragma unroll
+            for (int m = 1; m < kWin; ++m) i += (w.segpos[m] <= q) ? 1 : 0;
             r = (r0 - 1) + w.first[i] + (q - w.segpos[i]);
             compute_rib<PREC, kSegOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, o);
             if (WXY && r >= r0) {
@@ -1190,12 +1211,9 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
         for (int p0 = 0; p0 < NP; p0 += 64) {
           const int pq = p0 + lane;
           if (pq < NP) {
-            int a = 0, b = kWin - 1;
-            while (a < b) {
-              const int m = (a + b + 1) >> 1;
-              if (w.pivpos[m] <= pq) a = m; else b = m - 1;
-            }
-            const int i = a;
+            int i = 0;
+#pragma unroll
+            for (int m = 1; m < kWin; ++m) i += (w.pivpos[m] <= pq) ? 1 : 0;
             const int64_t r = (r0 - 1) + w.first[i] + (pq - w.pivpos[i]);
             RibOut o;
             compute_rib<PREC, kPivotOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, o);
@@ -1477,6 +1495,8 @@ int check_ws(const void* ws, size_t have, size_t need) {
 struct WsView {
   DevStatus* st;
   LinkRec* rec;
+  double2* seg_ang;   // per segment: start and end tangent angles (usable segments)
+  uint8_t* seg_ok;    // per segment: usable (finite, valid, not a single point)
   long long* scan;
   int32_t* tile_link;
   unsigned long long* desc;
@@ -1492,6 +1512,8 @@ WsView ws_view(void* ws, const WsLayout& w) {
   WsView v;
   v.st = (DevStatus*)(b + w.status);
   v.rec = (LinkRec*)(b + w.rec);
+  v.seg_ang = (double2*)(b + w.seg_ang);
+  v.seg_ok = (uint8_t*)(b + w.seg_ok);
   v.scan = (long long*)(b + w.scan);
   v.tile_link = (int32_t*)(b + w.tile_link);
   v.desc = (unsigned long long*)(b + w.desc);
@@ -1612,7 +1634,9 @@ int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, cons
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, v.st);
   const int64_t n = (int64_t)b->n_segs + b->n_paths;
   if (n > 0) {
-    CountArgs a{*b, p->q, link_ribs, v.rec, v.st};
+    CountArgs a{*b, p->q, link_ribs, v.rec, v.seg_ang, v.seg_ok, v.st};
+    if (b->n_segs > 0)
+      hipLaunchKernelGGL(count_angles_kernel, dim3(grid_for(b->n_segs, 256)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(count_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, a);
   }
   PS_HIP(hipGetLastError());
