@@ -42,8 +42,14 @@ extern "C" {
 /* Segment forms (Table "path segment forms"): line, quadratic Bezier,
  * rational quadratic conic with middle weight w_B, cubic Bezier. */
 enum { PS_KIND_LINE = 0, PS_KIND_QUAD = 1, PS_KIND_CONIC = 2, PS_KIND_CUBIC = 3 };
-/* Join styles (Sec. "Easy Joins"): J = 0, 1, 2 or ceil(|delta|/q) steps. */
-enum { PS_JOIN_NONE = 0, PS_JOIN_BEVEL = 1, PS_JOIN_ROUND = 2, PS_JOIN_TRIANGLE = 3 };
+/* Join styles (Secs. "Easy Joins", "Harder Joins: Miter Truncate and Revert"):
+ * J = 0, 1, ceil(|delta|/q), 2 steps, and J = 3 for the two miter styles, whose
+ * outer vertices of ribs 1 and 2 are the miter vertices.  The miter ratio is
+ * 1/cos(|delta|/2) (miter length over stroke width); beyond params->miter_limit
+ * PS_JOIN_MITER reverts to a bevel and PS_JOIN_MITER_CLIP cuts the miter at
+ * miter_limit * w/2 from the join point, square to its bisector. */
+enum { PS_JOIN_NONE = 0, PS_JOIN_BEVEL = 1, PS_JOIN_ROUND = 2, PS_JOIN_TRIANGLE = 3,
+       PS_JOIN_MITER = 4, PS_JOIN_MITER_CLIP = 5 };
 /* Cap styles (Secs. "Easy Caps", "Harder Caps"): J = 0, ceil(pi/q), 4, 2. */
 enum { PS_CAP_BUTT = 0, PS_CAP_ROUND = 1, PS_CAP_SQUARE = 2, PS_CAP_TRIANGLE = 3 };
 /* Arithmetic of the per-rib direction and tangent-angle solve (Eq. angle2t);
@@ -86,6 +92,11 @@ enum {
  *   conic_w   [n_segs]     w_B of conics (> 0); ignored for other kinds
  *   width     [n_paths]    stroke width w (> 0)
  *   join, cap [n_paths]    PS_JOIN_*, PS_CAP_*
+ *   closed    [n_paths]    1: a closed contour (a join from the last segment
+ *                          with ribs back to the first, no caps); 0: open.
+ *                          May be NULL (every path open).  Closing adds no
+ *                          segment: a closed contour's last segment should end
+ *                          where its first begins.
  */
 typedef struct {
   int32_t n_paths;
@@ -98,6 +109,7 @@ typedef struct {
   const float* width;
   const uint8_t* join;
   const uint8_t* cap;
+  const uint8_t* closed;
 } ps_batch;
 
 /*
@@ -106,6 +118,8 @@ typedef struct {
  * Dashing (Sec. "Dashing"): n_dash on/off lengths (even count >= 2, all >= 0,
  * positive sum) in the HOST array dash, starting at pattern position
  * dash_phase >= 0 at arc length 0 of every path; n_dash = 0 disables it.
+ * miter_limit >= 1 bounds the miter ratio of the miter joins (4 is the usual
+ * default of path-rendering standards).
  */
 typedef struct {
   double q;
@@ -113,6 +127,7 @@ typedef struct {
   int32_t n_dash;
   const double* dash;
   double dash_phase;
+  double miter_limit;
 } ps_params;
 
 /* Status read back from a workspace. */

@@ -39,10 +39,10 @@ def _load():
             build(force=True)
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
-        lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_int] + [P] * 8 + [ctypes.c_double, P, ctypes.c_int]
+        lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_int] + [P] * 9 + [ctypes.c_double, P, ctypes.c_int]
         lib.oracle_count.restype = ctypes.c_int
-        lib.oracle_emit.argtypes = ([ctypes.c_int, ctypes.c_int] + [P] * 8 + [ctypes.c_double, P]
-                                    + [P] * 6 + [ctypes.c_int])
+        lib.oracle_emit.argtypes = ([ctypes.c_int, ctypes.c_int] + [P] * 9
+                                    + [ctypes.c_double, ctypes.c_double, P] + [P] * 6 + [ctypes.c_int])
         lib.oracle_emit.restype = ctypes.c_int
         lib.oracle_segment_intervals.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double,
                                                  P, P, P, P, P, ctypes.c_int]
@@ -61,8 +61,9 @@ def _p(a: np.ndarray):
 
 
 def _batch_args(b):
+    closed = getattr(b, "closed", None)
     return [b.n_paths, b.n_segs, _p(b.seg_begin), _p(b.kind), _p(b.cx), _p(b.cy), _p(b.conic_w),
-            _p(b.width), _p(b.join), _p(b.cap)]
+            _p(b.width), _p(b.join), _p(b.cap), None if closed is None else _p(closed)]
 
 
 def num_threads() -> int:
@@ -94,8 +95,9 @@ def emit(b, off: np.ndarray, q: float | None = None, nthreads: int = 0) -> dict:
     vx = np.zeros(2 * R); vy = np.zeros(2 * R); vs = np.zeros(R)
     t = np.zeros(R); psi = np.zeros(R); role = np.zeros(R, np.uint8)
     off = np.ascontiguousarray(off, np.int64)
-    rc = _load().oracle_emit(*_batch_args(b), ctypes.c_double(q), _p(off), _p(vx), _p(vy), _p(vs),
-                             _p(t), _p(psi), _p(role), nthreads)
+    limit = float(getattr(b, "miter_limit", 4.0))
+    rc = _load().oracle_emit(*_batch_args(b), ctypes.c_double(limit), ctypes.c_double(q), _p(off),
+                             _p(vx), _p(vy), _p(vs), _p(t), _p(psi), _p(role), nthreads)
     if rc != 0:
         raise ValueError(f"oracle_emit failed ({rc})")
     return dict(vx=vx, vy=vy, vs=vs, t=t, psi=psi, role=role)

@@ -47,7 +47,8 @@ const double kCountEps = 1e-9;   // ceil(x - eps): knife-edge guard for exact k*
 const double kUnwrapGuard = 1e-12;
 
 enum { KIND_L = 0, KIND_Q = 1, KIND_K = 2, KIND_C = 3 };
-enum { JOIN_NONE = 0, JOIN_BEVEL = 1, JOIN_ROUND = 2, JOIN_TRIANGLE = 3 };
+enum { JOIN_NONE = 0, JOIN_BEVEL = 1, JOIN_ROUND = 2, JOIN_TRIANGLE = 3, JOIN_MITER = 4,
+       JOIN_MITER_CLIP = 5 };
 enum { CAP_BUTT = 0, CAP_ROUND = 1, CAP_SQUARE = 2, CAP_TRIANGLE = 3 };
 enum { ROLE_SEGMENT = 0, ROLE_JOIN = 1, ROLE_START_CAP = 2, ROLE_END_CAP = 3 };
 
@@ -408,7 +409,11 @@ struct Batch {
   const float* width;
   const uint8_t* join;
   const uint8_t* cap;
+  const uint8_t* closed;   // NULL: every path open
+  double miter_limit;
 };
+
+bool path_closed(const Batch& B, int p) { return B.closed && B.closed[p]; }
 
 Seg load_seg(const Batch& B, int i) {
   Seg s;
@@ -429,6 +434,7 @@ struct Pivot {
   int J;           // 0 => no ribs
   int role;
   int cap_style;   // square caps enlarge the corner ribs
+  int join_style;  // miter joins move the outer vertices of ribs 1 and 2
 };
 
 int join_steps(int style, double delta, double q) {
@@ -437,6 +443,8 @@ int join_steps(int style, double delta, double q) {
     case JOIN_BEVEL: return 1;
     case JOIN_TRIANGLE: return 2;
     case JOIN_ROUND: return (int)std::ceil(std::fabs(delta) / q - kCountEps);
+    case JOIN_MITER:
+    case JOIN_MITER_CLIP: return 3;   // Sec. "Harder Joins: Miter Truncate and Revert"
     default: return 0;
   }
 }
@@ -468,14 +476,15 @@ Link make_link(const Batch& B, int p, int slot, double q) {
   L.role = ROLE_SEGMENT;
   int rel = slot - (2 * b + p);
   if (rel == 0) {
-    // start cap of the first segment with nonzero length
+    // start cap of the first segment with nonzero length (closed contours
+    // have none)
     L.role = ROLE_START_CAP;
-    for (int i = b; i < e; ++i) {
+    for (int i = b; i < e && !path_closed(B, p); ++i) {
       Seg s = load_seg(B, i);
       if (zero_length(s)) continue;
       int J = cap_steps(B.cap[p], q);
       double psi_s = angle_of(grad_start(s));
-      L.pv = {s.P[0], psi_s - kPi, kPi, J, ROLE_START_CAP, B.cap[p]};
+      L.pv = {s.P[0], psi_s - kPi, kPi, J, ROLE_START_CAP, B.cap[p], 0};
       if (J > 0) { L.empty = false; L.ribs = J + 1; }
       break;
     }
@@ -495,22 +504,57 @@ Link make_link(const Batch& B, int p, int slot, double q) {
   // join after segment i, or the end cap
   if (zero_length(s)) { L.role = ROLE_JOIN; return L; }
   double psi_e = angle_of(grad_end(s));
-  for (int k = i + 1; k < e; ++k) {
-    Seg sb = load_seg(B, k);
-    if (zero_length(sb)) continue;
-    double d = angle_diff(angle_of(grad_start(sb)), psi_e);
+  // the next segment with nonzero length; after the last one, a closed
+  // contour joins back to its first
+  int next = -1;
+  for (int k = i + 1; k < e && next < 0; ++k)
+    if (!zero_length(load_seg(B, k))) next = k;
+  for (int k = b; k <= i && next < 0 && path_closed(B, p); ++k)
+    if (!zero_length(load_seg(B, k))) next = k;
+  if (next >= 0) {
+    double d = angle_diff(angle_of(grad_start(load_seg(B, next))), psi_e);
     if (d == -kPi) d = kPi;                   // antiparallel: turn +pi
     int J = join_steps(B.join[p], d, q);
     L.role = ROLE_JOIN;
-    L.pv = {end_point(s), psi_e, d, J, ROLE_JOIN, 0};
+    L.pv = {end_point(s), psi_e, d, J, ROLE_JOIN, 0, B.join[p]};
     if (J > 0) { L.empty = false; L.ribs = J + 1; }
     return L;
   }
   L.role = ROLE_END_CAP;
   int J = cap_steps(B.cap[p], q);
-  L.pv = {end_point(s), psi_e, -kPi, J, ROLE_END_CAP, B.cap[p]};
+  L.pv = {end_point(s), psi_e, -kPi, J, ROLE_END_CAP, B.cap[p], 0};
   if (J > 0) { L.empty = false; L.ribs = J + 1; }
   return L;
+}
+
+// Miter vertex of rib j (1 or 2) of a miter join; the paper leaves its
+// construction to standard stroking practice, taken here as: o0, o3 the outer
+// unit normals at the two ends of the join, M = c + r (o0 + o3) / (1 + o0.o3)
+// the meeting point of the two outer offset lines, miter ratio 1/cos(|delta|/2)
+// (miter length over stroke width).  Within the limit both ribs take M; beyond
+// it the miter either reverts to the bevel (rib 1 at c + r o0, rib 2 at
+// c + r o3) or is cut square to the bisector b at distance limit * r from c
+// (rib 1 on the incoming offset line, rib 2 on the outgoing one).
+V2 miter_vertex(const Pivot& pv, double r, double limit, int j) {
+  double sgn = pv.delta > 0 ? -1.0 : 1.0;   // outer side: -n for a left turn
+  V2 o0 = {sgn * -std::sin(pv.psi0), sgn * std::cos(pv.psi0)};
+  double psi3 = pv.psi0 + pv.delta;
+  V2 o3 = {sgn * -std::sin(psi3), sgn * std::cos(psi3)};
+  V2 sum = {o0.x + o3.x, o0.y + o3.y};
+  double half_len = 0.5 * std::sqrt(sum.x * sum.x + sum.y * sum.y);   // cos(|delta| / 2)
+  if (half_len * limit >= 1.0) {
+    double f = r / (1.0 + (o0.x * o3.x + o0.y * o3.y));
+    return {pv.c.x + f * sum.x, pv.c.y + f * sum.y};
+  }
+  if (pv.join_style == JOIN_MITER) {
+    V2 o = j == 1 ? o0 : o3;
+    return {pv.c.x + r * o.x, pv.c.y + r * o.y};
+  }
+  V2 t0 = {std::cos(pv.psi0), std::sin(pv.psi0)}, t3 = {std::cos(psi3), std::sin(psi3)};
+  V2 bis = half_len > 0 ? V2{sum.x / (2 * half_len), sum.y / (2 * half_len)} : t0;
+  double u = (limit * r - r * (o0.x * bis.x + o0.y * bis.y)) / (t0.x * bis.x + t0.y * bis.y);
+  if (j == 1) return {pv.c.x + r * o0.x + u * t0.x, pv.c.y + r * o0.y + u * t0.y};
+  return {pv.c.x + r * o3.x - u * t3.x, pv.c.y + r * o3.y - u * t3.y};
 }
 
 struct Out {
@@ -567,6 +611,14 @@ void emit_path(const Batch& B, int p, double q, const int64_t* off, const Out& o
         int64_t r = r0 + j;
         o.vx[2 * r] = pv.c.x - rN * n.x; o.vy[2 * r] = pv.c.y - rN * n.y;
         o.vx[2 * r + 1] = pv.c.x + rP * n.x; o.vy[2 * r + 1] = pv.c.y + rP * n.y;
+        if (pv.role == ROLE_JOIN && (pv.join_style == JOIN_MITER || pv.join_style == JOIN_MITER_CLIP) &&
+            (j == 1 || j == 2)) {
+          // the outer vertex of ribs 1 and 2 (N side of a left turn, P side
+          // of a right turn) becomes the miter vertex
+          V2 m = miter_vertex(pv, L.r, B.miter_limit, j);
+          int k = pv.delta > 0 ? 2 * r : 2 * r + 1;
+          o.vx[k] = m.x; o.vy[k] = m.y;
+        }
         o.vs[r] = s_acc; o.rib_t[r] = -1.0; o.rib_psi[r] = psi; o.rib_role[r] = (uint8_t)pv.role;
       }
     }
@@ -593,10 +645,10 @@ int oracle_num_threads(void) { return (int)std::max(1u, std::thread::hardware_co
 // Ribs of every link slot (Eqs. Delta_i, DeltaSigmaK; joins and caps).
 int oracle_count(int n_paths, int n_segs, const int32_t* seg_begin, const uint8_t* kind,
                  const float* cx, const float* cy, const float* conic_w, const float* width,
-                 const uint8_t* join, const uint8_t* cap, double q, int32_t* link_ribs,
-                 int nthreads) {
+                 const uint8_t* join, const uint8_t* cap, const uint8_t* closed, double q,
+                 int32_t* link_ribs, int nthreads) {
   if (n_paths < 0 || n_segs < 0 || !(q > 0 && q <= kPi)) return -1;
-  Batch B{n_paths, n_segs, seg_begin, kind, cx, cy, conic_w, width, join, cap};
+  Batch B{n_paths, n_segs, seg_begin, kind, cx, cy, conic_w, width, join, cap, closed, 4.0};
   parallel_paths(n_paths, nthreads, [&](int p) {
     int b = seg_begin[p], e = seg_begin[p + 1];
     for (int slot = 2 * b + p; slot <= 2 * e + p; ++slot)
@@ -609,11 +661,11 @@ int oracle_count(int n_paths, int n_segs, const int32_t* seg_begin, const uint8_
 // (the exclusive prefix sum of oracle_count's output).
 int oracle_emit(int n_paths, int n_segs, const int32_t* seg_begin, const uint8_t* kind,
                 const float* cx, const float* cy, const float* conic_w, const float* width,
-                const uint8_t* join, const uint8_t* cap, double q, const int64_t* offsets,
-                double* vx, double* vy, double* vs, double* rib_t, double* rib_psi,
-                uint8_t* rib_role, int nthreads) {
-  if (n_paths < 0 || n_segs < 0 || !(q > 0 && q <= kPi)) return -1;
-  Batch B{n_paths, n_segs, seg_begin, kind, cx, cy, conic_w, width, join, cap};
+                const uint8_t* join, const uint8_t* cap, const uint8_t* closed, double miter_limit,
+                double q, const int64_t* offsets, double* vx, double* vy, double* vs,
+                double* rib_t, double* rib_psi, uint8_t* rib_role, int nthreads) {
+  if (n_paths < 0 || n_segs < 0 || !(q > 0 && q <= kPi) || !(miter_limit >= 1.0)) return -1;
+  Batch B{n_paths, n_segs, seg_begin, kind, cx, cy, conic_w, width, join, cap, closed, miter_limit};
   Out o{vx, vy, vs, rib_t, rib_psi, rib_role};
   parallel_paths(n_paths, nthreads, [&](int p) { emit_path(B, p, q, offsets, o); });
   return 0;

@@ -31,12 +31,12 @@ _vp = ctypes.c_void_p
 class ps_batch(ctypes.Structure):
     _fields_ = [("n_paths", ctypes.c_int32), ("n_segs", ctypes.c_int32), ("seg_begin", _vp),
                 ("kind", _vp), ("cx", _vp), ("cy", _vp), ("conic_w", _vp), ("width", _vp),
-                ("join", _vp), ("cap", _vp)]
+                ("join", _vp), ("cap", _vp), ("closed", _vp)]
 
 
 class ps_params(ctypes.Structure):
     _fields_ = [("q", ctypes.c_double), ("precision", ctypes.c_int32), ("n_dash", ctypes.c_int32),
-                ("dash", _vp), ("dash_phase", ctypes.c_double)]
+                ("dash", _vp), ("dash_phase", ctypes.c_double), ("miter_limit", ctypes.c_double)]
 
 
 class ps_status(ctypes.Structure):
@@ -136,17 +136,20 @@ class DeviceBatch:
         self.width = t(b.width)
         self.join = t(b.join)
         self.cap = t(b.cap)
+        self.closed = None if b.closed is None else t(b.closed)
+        self.miter_limit = float(b.miter_limit)
         self.n_paths, self.n_segs = b.n_paths, b.n_segs
         self.n_links = 2 * b.n_segs + b.n_paths
         self.struct = ps_batch(self.n_paths, self.n_segs, _ptr(self.seg_begin), _ptr(self.kind),
                                _ptr(self.cx), _ptr(self.cy), _ptr(self.conic_w), _ptr(self.width),
-                               _ptr(self.join), _ptr(self.cap))
+                               _ptr(self.join), _ptr(self.cap), _ptr(self.closed))
 
 
-def make_params(q: float, precision: int = PS_PREC_FP64, dash=(), dash_phase: float = 0.0):
+def make_params(q: float, precision: int = PS_PREC_FP64, dash=(), dash_phase: float = 0.0,
+                miter_limit: float = 4.0):
     arr = (ctypes.c_double * max(1, len(dash)))(*dash) if len(dash) else None
     p = ps_params(float(q), int(precision), len(dash), ctypes.cast(arr, _vp) if arr else None,
-                  float(dash_phase))
+                  float(dash_phase), float(miter_limit))
     p._keep = arr   # keep the host pattern alive with the struct
     return p
 
@@ -228,7 +231,7 @@ def stroke(db: DeviceBatch, q: float, precision: int = PS_PREC_FP64, vertex_capa
     """count -> scan -> (read total) -> emit [-> dash]; returns device tensors."""
     import torch
     dev = db.seg_begin.device
-    params = make_params(q, precision, dash, dash_phase)
+    params = make_params(q, precision, dash, dash_phase, db.miter_limit)
     link_ribs = torch.empty(max(1, db.n_links), dtype=torch.int32, device=dev)
     offsets = torch.empty(db.n_links + 1, dtype=torch.int64, device=dev)
     ws0 = alloc_workspace(ps_workspace_bytes(db, params, 0), dev)
@@ -274,7 +277,7 @@ class Plan:
         import torch
         dev = db.seg_begin.device
         self.db = db
-        self.params = make_params(q, precision, dash, dash_phase)
+        self.params = make_params(q, precision, dash, dash_phase, db.miter_limit)
         self.capacity = int(vertex_capacity)
         self.link_ribs = torch.empty(max(1, db.n_links), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(db.n_links + 1, dtype=torch.int64, device=dev)

@@ -251,6 +251,7 @@ __device__ int join_steps(int style, double delta, double q) {
   if (delta == 0.0) return 0;
   if (style == PS_JOIN_BEVEL) return 1;
   if (style == PS_JOIN_TRIANGLE) return 2;
+  if (style == PS_JOIN_MITER || style == PS_JOIN_MITER_CLIP) return 3;   // Sec. "Harder Joins"
   if (style == PS_JOIN_ROUND) {
     const double x = ceil(fabs(delta) / q - kCountEps);
     return x < 0 ? 0 : (int)x;
@@ -295,7 +296,8 @@ __device__ inline void clear_rec(LinkRec& r) {
   for (int k = 0; k <= kMaxIv; ++k) r.psi[k] = 0;
 }
 
-// A pivot link (join or cap) with J steps from psi0 through psi0 + delta.
+// A pivot link (join or cap) with J steps from psi0 through psi0 + delta;
+// `cap` is the cap style of a cap and the join style of a join.
 __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slot, uint8_t role,
                                    double psi0, double delta, int J, float px, float py,
                                    uint8_t cap, float half_w, bool first) {
@@ -307,6 +309,13 @@ __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slo
   r.r = half_w;
   r.dsum[0] = J; r.psi[0] = psi0; r.psi[1] = psi0 + delta;
   r.x[0] = px; r.y[0] = py;
+  if (role == ROLE_JOIN && (cap == PS_JOIN_MITER || cap == PS_JOIN_MITER_CLIP)) {
+    // unit normals n = (-sin, cos) at both ends, for the miter vertices
+    double s0, c0, s1, c1;
+    sincos(psi0, &s0, &c0);
+    sincos(psi0 + delta, &s1, &c1);
+    r.p[0] = -s0; r.p[1] = c0; r.p[2] = -s1; r.p[3] = c1;
+  }
   rec[slot] = r;
   link_ribs[slot] = J > 0 ? J + 1 : 0;
 }
@@ -322,7 +331,8 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     const int64_t slot = 2 * (int64_t)i + p + 1;
     const float wd = B.width[p];
     const bool wok = isfinite(wd) && wd > 0;
-    const bool sok = (B.join[p] <= PS_JOIN_TRIANGLE) && (B.cap[p] <= PS_CAP_TRIANGLE);
+    const bool sok = (B.join[p] <= PS_JOIN_MITER_CLIP) && (B.cap[p] <= PS_CAP_TRIANGLE);
+    const bool closed = B.closed && B.closed[p];
     if (!isfinite(wd)) set_flag(A.st, PS_STATUS_NONFINITE);
     else if (!wok || !sok) set_flag(A.st, PS_STATUS_BAD_VALUE);
     const bool usable = wok && sok && A.seg_ok[i];   // segment problems: reported by the angles pass
@@ -351,7 +361,7 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
         bool first_seg = true;
         for (int k = i - 1; first_seg && k >= b; --k) first_seg = !A.seg_ok[k];
         if (first_seg) r.flags |= kFirstSegInPath;
-        if (first_seg && cap_steps(B.cap[p], A.q) == 0) r.flags |= kFirstInPath;
+        if (first_seg && (closed || cap_steps(B.cap[p], A.q) == 0)) r.flags |= kFirstInPath;
       }
     }
     A.rec[slot] = r;
@@ -364,12 +374,18 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     }
     const int n = npts_of(B.kind[i]);
     const float ex = B.cx[(int64_t)(n - 1) * S + i], ey = B.cy[(int64_t)(n - 1) * S + i];
-    for (int k = i + 1; k < e; ++k) {
-      if (!A.seg_ok[k]) continue;
-      double d = adiff(A.seg_ang[k].x, psi_e);
+    // the next usable segment; after the last one a closed contour joins
+    // back to its first
+    int next = -1;
+    for (int k = i + 1; k < e && next < 0; ++k)
+      if (A.seg_ok[k]) next = k;
+    for (int k = b; k <= i && next < 0 && closed; ++k)
+      if (A.seg_ok[k]) next = k;
+    if (next >= 0) {
+      double d = adiff(A.seg_ang[next].x, psi_e);
       if (d == -kPi) d = kPi;   // antiparallel: turn +pi
       const int J = join_steps(B.join[p], d, A.q);
-      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, psi_e, d, J, ex, ey, 0, half_w, false);
+      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, psi_e, d, J, ex, ey, B.join[p], half_w, false);
       return;
     }
     const int J = cap_steps(B.cap[p], A.q);
@@ -382,8 +398,8 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     const int64_t slot = 2 * (int64_t)b + p;
     const float wd = B.width[p];
     const bool ok = isfinite(wd) && wd > 0 && B.cap[p] <= PS_CAP_TRIANGLE &&
-                    B.join[p] <= PS_JOIN_TRIANGLE;
-    if (ok) {
+                    B.join[p] <= PS_JOIN_MITER_CLIP;
+    if (ok && !(B.closed && B.closed[p])) {   // a closed contour has no caps
       for (int k = b; k < e; ++k) {
         if (!A.seg_ok[k]) continue;
         const double psi_s = A.seg_ang[k].x;
@@ -536,6 +552,7 @@ struct EmitArgs {
   DevStatus* st;
   int64_t max_tiles;
   float fix_tol;   // largest FP64 Newton step accepted on an FP32 root; beyond it the rib is re-solved in FP64
+  double miter_limit;
 };
 
 __device__ __forceinline__ int link_of(const int64_t* off, int lo, int hi, int64_t r) {
@@ -605,8 +622,45 @@ struct RibOut {
 // other branch is then not compiled).  The record may live in LDS or in
 // global memory.
 constexpr int kAnyRole = 0, kSegOnly = 1, kPivotOnly = 2;
+
+// The outer vertex of rib j (1 or 2) of a miter join (Sec. "Harder Joins:
+// Miter Truncate and Revert", which leaves the construction to standard
+// practice): with o0, o3 the outer unit normals at the join's two ends (the
+// -n side of a left turn), the two outer offset lines meet at
+// M = c + r (o0 + o3) / (1 + o0.o3); the miter ratio (miter length over
+// stroke width) is 1/cos(|delta|/2) = 2/|o0 + o3|.  Within the limit both ribs
+// take M; beyond it PS_JOIN_MITER reverts to the bevel's ends and
+// PS_JOIN_MITER_CLIP cuts the miter square to its bisector b at limit * r
+// from c, rib 1 on the incoming offset line, rib 2 on the outgoing one.
+template <typename Rec>
+__device__ __forceinline__ void miter_vertex(const Rec& rp, int j, int style, double limit,
+                                             double& vx, double& vy) {
+  const double cx = rp.x[0], cy = rp.y[0], r = rp.r;
+  const double sg = (rp.psi[1] - rp.psi[0]) > 0 ? -1.0 : 1.0;
+  const double n0x = rp.p[0], n0y = rp.p[1], n3x = rp.p[2], n3y = rp.p[3];
+  const double o0x = sg * n0x, o0y = sg * n0y, o3x = sg * n3x, o3y = sg * n3y;
+  const double sx = o0x + o3x, sy = o0y + o3y;
+  const double half = 0.5 * sqrt(sx * sx + sy * sy);   // cos(|delta| / 2)
+  if (half * limit >= 1.0) {
+    const double f = r / (1.0 + o0x * o3x + o0y * o3y);
+    vx = cx + f * sx; vy = cy + f * sy;
+    return;
+  }
+  if (style == PS_JOIN_MITER) {
+    vx = cx + r * (j == 1 ? o0x : o3x);
+    vy = cy + r * (j == 1 ? o0y : o3y);
+    return;
+  }
+  // tangents t = (cos, sin) = (n.y, -n.x); b = t0 for an exact reversal
+  const double t0x = n0y, t0y = -n0x, t3x = n3y, t3y = -n3x;
+  const double bx = half > 0 ? sx / (2 * half) : t0x, by = half > 0 ? sy / (2 * half) : t0y;
+  const double u = (limit * r - r * (o0x * bx + o0y * by)) / (t0x * bx + t0y * by);
+  if (j == 1) { vx = cx + r * o0x + u * t0x; vy = cy + r * o0y + u * t0y; }
+  else { vx = cx + r * o3x - u * t3x; vy = cy + r * o3y - u * t3y; }
+}
 template <int PREC, int ROLES = kAnyRole, typename Rec>
-__device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol, RibOut& o) {
+__device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol, double miter_limit,
+                                            RibOut& o) {
   const uint8_t role = rp.role;
   const bool seg = ROLES == kSegOnly || (ROLES == kAnyRole && role == ROLE_SEG);
   const double rad = (double)rp.r;
@@ -710,6 +764,15 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
   }
   o.Nx = (float)(o.gx - rN * nx); o.Ny = (float)(o.gy - rN * ny);
   o.Px = (float)(o.gx + rP * nx); o.Py = (float)(o.gy + rP * ny);
+  if (!seg && role == ROLE_JOIN && (j == 1 || j == 2)) {
+    const int style = rp.flags >> 4;
+    if (style == PS_JOIN_MITER || style == PS_JOIN_MITER_CLIP) {
+      double vx, vy;
+      miter_vertex(rp, j, style, miter_limit, vx, vy);
+      if (rp.psi[1] - rp.psi[0] > 0) { o.Nx = (float)vx; o.Ny = (float)vy; }
+      else { o.Px = (float)vx; o.Py = (float)vy; }
+    }
+  }
 }
 
 // Link window staged in LDS, one per wave: kWin consecutive link slots
@@ -878,7 +941,7 @@ emit_kernel(EmitArgs A) {
                 const int m = (a + b + 1) >> 1;
                 if (win.off[m] <= r) a = m; else b = m - 1;
               }
-              compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, o);
+              compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, A.miter_limit, o);
               pending = false;
             }
             const unsigned long long pm = __ballot(pending);
@@ -888,7 +951,7 @@ emit_kernel(EmitArgs A) {
           }
         } else if (valid) {
           l = link_of(A.off, l, lhi, r);
-          compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, o);
+          compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, A.miter_limit, o);
         }
         if (valid) {
           if (WXY && mine) {
@@ -1156,7 +1219,7 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
 #pragma unroll
             for (int m = 1; m < kWin; ++m) i += (w.segpos[m] <= q) ? 1 : 0;
             r = (r0 - 1) + w.first[i] + (q - w.segpos[i]);
-            compute_rib<PREC, kSegOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, o);
+            compute_rib<PREC, kSegOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, A.miter_limit, o);
             if (WXY && r >= r0) {
               *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
               *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
@@ -1216,7 +1279,7 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
             for (int m = 1; m < kWin; ++m) i += (w.pivpos[m] <= pq) ? 1 : 0;
             const int64_t r = (r0 - 1) + w.first[i] + (pq - w.pivpos[i]);
             RibOut o;
-            compute_rib<PREC, kPivotOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, o);
+            compute_rib<PREC, kPivotOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, A.miter_limit, o);
             if (WXY) {
               *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
               *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
@@ -1468,6 +1531,8 @@ int check_params(const ps_params* p) {
   if (!(p->q >= 1e-4 && p->q <= M_PI)) return fail(PS_E_ARG, "q must be in [1e-4, pi] (got %g)", p->q);
   if (p->precision < PS_PREC_FP32 || p->precision > PS_PREC_FP64)
     return fail(PS_E_ARG, "unknown precision mode %d", p->precision);
+  if (!(p->miter_limit >= 1.0) || !std::isfinite(p->miter_limit))
+    return fail(PS_E_ARG, "miter_limit must be finite and >= 1 (got %g)", p->miter_limit);
   if (p->n_dash != 0) {
     if (p->n_dash < 2 || (p->n_dash & 1) || p->n_dash > kMaxDash)
       return fail(PS_E_ARG, "dash pattern needs an even count in [2, %d]", kMaxDash);
@@ -1658,6 +1723,7 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
   a.max_tiles = w.max_tiles;
   a.fix_tol = fixup_tolerance();
+  a.miter_limit = p->miter_limit;
   if (waves < 1 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   const int block = 64 * waves;   // never above the kernel's launch bound of 256
   const int grid = num_cus() * (16 / waves);

@@ -12,6 +12,7 @@ Batch layout (the interface of the C ABI, see include/ps.h):
   conic_w   [S]   float32 middle weight w_B (conics only)
   width     [P]   float32 stroke width w
   join, cap [P]   uint8   join / cap style per path
+  closed    [P]   uint8   1 for a closed contour (or None: every path open)
 The paper gives no concrete path data (its figures and test paths are not
 published with it), so every workload is synthetic with the shapes named in
 the configuration descriptions below.
@@ -25,7 +26,7 @@ import numpy as np
 
 KIND_L, KIND_Q, KIND_K, KIND_C = 0, 1, 2, 3
 NPTS = {KIND_L: 2, KIND_Q: 3, KIND_K: 3, KIND_C: 4}
-JOIN_NONE, JOIN_BEVEL, JOIN_ROUND, JOIN_TRIANGLE = 0, 1, 2, 3
+JOIN_NONE, JOIN_BEVEL, JOIN_ROUND, JOIN_TRIANGLE, JOIN_MITER, JOIN_MITER_CLIP = 0, 1, 2, 3, 4, 5
 CAP_BUTT, CAP_ROUND, CAP_SQUARE, CAP_TRIANGLE = 0, 1, 2, 3
 
 GRID = 2.0 ** -8   # coordinate grid that keeps cusp and mirror constructions exact in FP32
@@ -46,6 +47,8 @@ class Batch:
     dash_phase: float = 0.0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    closed: np.ndarray | None = None
+    miter_limit: float = 4.0
 
     @property
     def n_paths(self) -> int:
@@ -70,6 +73,7 @@ class Batch:
         assert self.width.dtype == np.float32 and self.width.shape == (P,)
         assert self.join.dtype == np.uint8 and self.join.shape == (P,)
         assert self.cap.dtype == np.uint8 and self.cap.shape == (P,)
+        assert self.closed is None or (self.closed.dtype == np.uint8 and self.closed.shape == (P,))
 
     def subset(self, paths) -> "Batch":
         """Batch holding only the listed paths (in the given order)."""
@@ -82,7 +86,8 @@ class Batch:
         return Batch(sb, self.kind[idx].copy(), np.ascontiguousarray(self.cx[:, idx]),
                      np.ascontiguousarray(self.cy[:, idx]), self.conic_w[idx].copy(),
                      self.width[paths].copy(), self.join[paths].copy(), self.cap[paths].copy(),
-                     self.q, self.dash, self.dash_phase, self.name + "[subset]", dict(self.meta))
+                     self.q, self.dash, self.dash_phase, self.name + "[subset]", dict(self.meta),
+                     None if self.closed is None else self.closed[paths].copy(), self.miter_limit)
 
 
 def _empty(S: int):
@@ -366,12 +371,14 @@ def single(kind: int, pts, *, w: float = 1.0, width: float = 2.0, q: float = mat
 
 
 def path(segs, *, width: float = 2.0, q: float = math.pi / 64, join: int = JOIN_ROUND,
-         cap: int = CAP_BUTT) -> Batch:
+         cap: int = CAP_BUTT, closed: bool = False, miter_limit: float = 4.0) -> Batch:
     """One path from a list of (kind, points, conic_weight) tuples."""
-    return paths([segs], widths=[width], q=q, joins=[join], caps=[cap])
+    return paths([segs], widths=[width], q=q, joins=[join], caps=[cap],
+                 closed=[closed] if closed else None, miter_limit=miter_limit)
 
 
-def paths(list_of_segs, *, widths, q: float = math.pi / 64, joins=None, caps=None) -> Batch:
+def paths(list_of_segs, *, widths, q: float = math.pi / 64, joins=None, caps=None, closed=None,
+          miter_limit: float = 4.0) -> Batch:
     P = len(list_of_segs)
     S = sum(len(s) for s in list_of_segs)
     kind, cx, cy, cw = _empty(S)
@@ -388,7 +395,9 @@ def paths(list_of_segs, *, widths, q: float = math.pi / 64, joins=None, caps=Non
         sb.append(i)
     joins = [JOIN_ROUND] * P if joins is None else joins
     caps = [CAP_BUTT] * P if caps is None else caps
-    return _finish(sb, kind, cx, cy, cw, widths, joins, caps, q=q, name="explicit")
+    cl = None if closed is None else np.asarray(closed, np.uint8)
+    return _finish(sb, kind, cx, cy, cw, widths, joins, caps, q=q, name="explicit", closed=cl,
+                   miter_limit=miter_limit)
 
 
 def random_mixed(seed: int, n_paths: int, max_segs: int, extent: float = 1024.0,

@@ -96,6 +96,15 @@ def test_bad_precision_and_emit_config_rejected():
     assert lib.ps_set_plan_autotune(1) == ps.PS_OK
 
 
+@pytest.mark.parametrize("limit", [0.0, 0.999, float("nan"), float("inf")])
+def test_bad_miter_limit_rejected(limit):
+    lib = ps.load()
+    b = _batch()
+    p = ps.make_params(0.1, miter_limit=limit)
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    assert b"miter_limit" in lib.ps_last_error()
+
+
 def test_plan_rejects_null_buffers():
     lib = ps.load()
     b = _batch()

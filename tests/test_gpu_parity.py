@@ -87,9 +87,41 @@ def test_config5_reduced(q):
 
 
 @pytest.mark.parametrize("join,cap", [(W.JOIN_ROUND, W.CAP_ROUND), (W.JOIN_BEVEL, W.CAP_SQUARE),
-                                      (W.JOIN_TRIANGLE, W.CAP_TRIANGLE), (W.JOIN_NONE, W.CAP_BUTT)])
+                                      (W.JOIN_TRIANGLE, W.CAP_TRIANGLE), (W.JOIN_NONE, W.CAP_BUTT),
+                                      (W.JOIN_MITER, W.CAP_BUTT), (W.JOIN_MITER_CLIP, W.CAP_ROUND)])
 def test_styles(join, cap):
     _compare(W.random_mixed(21, n_paths=60, max_segs=20, extent=2048.0, join=join, cap=cap))
+
+
+@pytest.mark.parametrize("limit", [1.0, 1.5, 4.0, 50.0])
+@pytest.mark.parametrize("join", [W.JOIN_MITER, W.JOIN_MITER_CLIP])
+def test_miter_limits(join, limit):
+    # polylines with turns of every size, both senses: miters within, beyond
+    # and exactly at (limit 1) the limit, reverted or clipped
+    b = W.random_mixed(33, n_paths=40, max_segs=12, extent=512.0, join=join, cap=W.CAP_SQUARE)
+    b.kind[:] = W.KIND_L
+    b.miter_limit = limit
+    _compare(b)
+
+
+def test_closed_contours():
+    # every other path closed: the last segment ends at the first one's start
+    # and a join replaces both caps
+    b = W.random_mixed(45, n_paths=50, max_segs=9, extent=1024.0, join=W.JOIN_MITER, cap=W.CAP_ROUND)
+    closed = np.zeros(b.n_paths, np.uint8)
+    closed[::2] = 1
+    for p in range(b.n_paths):
+        s0, s1 = int(b.seg_begin[p]), int(b.seg_begin[p + 1]) - 1
+        if closed[p]:
+            n = W.NPTS[int(b.kind[s1])]
+            b.cx[n - 1, s1], b.cy[n - 1, s1] = b.cx[0, s0], b.cy[0, s0]
+    b.closed = closed
+    r = _compare(b)
+    ref = oracle.stroke(b)
+    # closed contours have no cap ribs
+    sb = b.seg_begin.astype(np.int64)
+    start_caps = ref["link_ribs"][2 * sb[:-1] + np.arange(b.n_paths)]
+    assert np.all(start_caps[closed == 1] == 0) and np.any(start_caps[closed == 0] > 0)
 
 
 def test_fp32_only_is_reported():

@@ -104,6 +104,81 @@ def test_golden_join():
     assert np.all(o["vx"][0::2][j] >= 100 - 1e-9) and np.all(o["vy"][0::2][j] <= 1e-9)
 
 
+def _gold_path(c):
+    segs = [(k, pts, (rest[0] if rest else 1.0)) for k, pts, *rest in c["segments"]]
+    return W.path(segs, width=c["width"], q=math.radians(c["q_deg"]), join=c["join"], cap=c["cap"],
+                  closed=bool(c["closed"]), miter_limit=c["miter_limit"])
+
+
+def test_golden_closed_square_miter():
+    c = gold("closed square with miter joins")
+    b = _gold_path(c)
+    o = oracle.stroke(b)
+    assert o["link_ribs"].tolist() == c["link_ribs"]
+    off = o["offsets"]
+    for n, corner in enumerate(c["miter_corners"]):
+        slot = 2 * n + 2                       # the join after segment n
+        r1 = int(off[slot]) + 1                # ribs 1 and 2 of the join
+        for r in (r1, r1 + 1):
+            # left turns: the outer vertex is the N one (even index)
+            assert (o["vx"][2 * r], o["vy"][2 * r]) == pytest.approx(tuple(corner), abs=1e-12)
+    assert o["vs"][-1] == pytest.approx(c["total_length"], abs=1e-9)
+    assert o["vs"][0] == 0.0
+    # no caps: the first rib belongs to the first segment
+    assert o["role"][0] == 0
+
+
+def test_golden_miter_clip():
+    c = gold("right-angle miter clipped")
+    o = oracle.stroke(_gold_path(c))
+    r1 = int(o["offsets"][2]) + 1
+    assert (o["vx"][2 * r1], o["vy"][2 * r1]) == pytest.approx(tuple(c["rib1_outer"]), abs=1e-12)
+    assert (o["vx"][2 * r1 + 2], o["vy"][2 * r1 + 2]) == pytest.approx(tuple(c["rib2_outer"]), abs=1e-12)
+
+
+def test_golden_miter_revert():
+    c = gold("sharp miter reverted to bevel")
+    o = oracle.stroke(_gold_path(c))
+    r0 = int(o["offsets"][2])
+    assert o["link_ribs"][2] == 4
+    V = lambda r: (o["vx"][2 * r], o["vy"][2 * r])
+    assert V(r0 + 1) == pytest.approx(V(r0), abs=1e-12)
+    assert V(r0 + 2) == pytest.approx(V(r0 + 3), abs=1e-12)
+    # and those ends are at w/2 from the corner, on the offset lines
+    assert math.dist(V(r0), (100, 0)) == pytest.approx(5.0, abs=1e-12)
+    assert V(r0) == pytest.approx((100, -5), abs=1e-12)
+
+
+def test_golden_closed_circle():
+    c = gold("closed circle of conic quarters")
+    o = oracle.stroke(_gold_path(c))
+    assert o["link_ribs"].tolist() == c["link_ribs"]
+    # w_B = cos 45 deg rounded to FP32 bends the arcs by ~1e-9 relative
+    assert o["vs"][-1] == pytest.approx(c["chord_sum"], rel=1e-8)
+
+
+def test_miter_within_limit_is_on_both_offset_lines():
+    # any turn: within the limit the miter vertex lies at w/2 from both
+    # segments' lines (the meeting point of the two offset lines)
+    rng = np.random.default_rng(17)
+    for _ in range(40):
+        a = rng.uniform(-3.0, 3.0)
+        pts = [(0.0, 0.0), (64.0, 0.0), (64.0 + 64.0 * math.cos(a), 64.0 * math.sin(a))]
+        b = W.path([(W.KIND_L, pts[:2], 1.0), (W.KIND_L, pts[1:], 1.0)], width=6.0, q=math.pi / 32,
+                   join=W.JOIN_MITER, cap=W.CAP_BUTT, miter_limit=1e6)
+        o = oracle.stroke(b)
+        if o["link_ribs"][2] == 0:
+            continue
+        r1 = int(o["offsets"][2]) + 1
+        k = 2 * r1 if a > 0 else 2 * r1 + 1
+        M = np.array([o["vx"][k], o["vy"][k]])
+        d1 = abs(M[1])                                                  # line y = 0
+        end = np.array([b.cx[1, 1], b.cy[1, 1]], np.float64)            # the stored (FP32) end point
+        u = (end - (64.0, 0.0)) / np.linalg.norm(end - (64.0, 0.0))
+        d2 = abs((M[0] - 64.0) * u[1] - M[1] * u[0])                    # line through (64,0) along u
+        assert d1 == pytest.approx(3.0, rel=1e-9) and d2 == pytest.approx(3.0, rel=1e-9)
+
+
 @pytest.mark.parametrize("cap", [0, 1, 2, 3])
 def test_golden_caps(cap):
     c = gold("caps")
