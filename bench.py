@@ -78,7 +78,7 @@ def main() -> int:
                          "instead of the plan's autotuning, e.g. for profiles of one mapping")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit", "c1"], default=None,
+    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit", "c1", "facets"], default=None,
                     help="secondary measurements: the near-degenerate precision study, the long "
                          "dashed path, or the stress configuration at q in {pi/16, pi/64, pi/256}")
     args = ap.parse_args()
@@ -457,7 +457,50 @@ def study_c1(args, torch, ps, W, dev):
     return 0
 
 
-STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5, "emit": study_emit, "c1": study_c1}
+def study_facets(args, torch, ps, W, dev):
+    """Polar stroking vs the uniform parametric baseline at the same quad budget
+    (Sec. "Versus Uniform Parametric Tessellation"): ordinary facet angles on
+    synthetic cubic serpentines and loops (w = 100, q = 4 deg, as the paper's
+    serpentine figure) and on exact cusps, and the time of both emits."""
+    rng = np.random.default_rng(2026)
+
+    def batch(n, cusp):
+        segs = []
+        for _ in range(n):
+            P0 = rng.uniform(0, 512, 2); P3 = P0 + rng.uniform(-300, 300, 2)
+            P1 = P0 + rng.uniform(-200, 200, 2)
+            P2 = (P0 + P1 - P3) if cusp else P3 + rng.uniform(-200, 200, 2)
+            segs.append([(W.KIND_C, [tuple(np.round(P * 256) / 256) for P in (P0, P1, P2, P3)], 1.0)])
+        return W.paths(segs, widths=[100.0] * n, q=math.radians(4.0))
+
+    rows = []
+    for name, b in (("serpentines and loops", batch(4096, False)), ("exact cusps", batch(4096, True))):
+        db = ps.DeviceBatch(b, device=dev)
+        out = ps.stroke(db, b.q)
+        R = out["total_ribs"]
+        vxu, vyu = torch.empty_like(out["vx"]), torch.empty_like(out["vy"])
+        stats = torch.zeros(4, dtype=torch.float64, device=dev)
+        row = {"segments": name, "n": b.n_segs, "quads": R - b.n_paths}   # one segment, butt caps per path
+        for mode in ("polar", "uniform"):
+            if mode == "uniform":
+                ps.ps_emit_uniform(db, out["params"], out["offsets"], vxu, vyu, out["capacity"], out["ws"])
+                vx, vy = vxu, vyu
+            else:
+                vx, vy = out["vx"], out["vy"]
+            ps.ps_facet_stats(db, out["offsets"], vx, vy, stats)
+            torch.cuda.synchronize()
+            n, mx, s1, s2 = (float(x) for x in stats.cpu().numpy())
+            mean = s1 / n
+            row[mode] = {"count": int(n), "max_deg": math.degrees(mx), "mean_deg": math.degrees(mean),
+                         "sd_deg": math.degrees(math.sqrt(max(0.0, s2 / n - mean * mean)))}
+        rows.append(row)
+        log(str(row))
+    print(json.dumps({"study": "facets", "rows": rows}), flush=True)
+    return 0
+
+
+STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5, "emit": study_emit, "c1": study_c1,
+           "facets": study_facets}
 
 
 if __name__ == "__main__":

@@ -200,6 +200,38 @@ int ps_arclen(const ps_batch* batch, const ps_params* params, const int64_t* off
               float* vs, int64_t vertex_capacity, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * ps_emit_uniform -- the uniform parametric baseline the paper compares
+ * against (Sec. "Versus Uniform Parametric Tessellation"): the stroked region
+ * of Eq. NaiveStroking sampled at t_j = j/N for every segment, with the rib
+ * counts of ps_count (the same quad budget as polar stroking); n(t_j) is the
+ * unit left normal of g'(t_j), taken 2^-20/N further into the segment where
+ * g' vanishes.  Joins and caps are emitted as by ps_emit.  Writes vx, vy
+ * [2R] like ps_emit (no arc length); same requirements as ps_emit.
+ */
+int ps_emit_uniform(const ps_batch* batch, const ps_params* params, const int64_t* offsets,
+                    float* vx, float* vy, int64_t vertex_capacity, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/*
+ * ps_facet_stats -- ordinary facet angles of the segment ribs of a rib stream
+ * (Sec. "Uniform Tangent Angle Step Tessellation": the angle at which one quad
+ * meets the next; ordinary ones are below 2q for polar stroking).  On each side
+ * of a segment's strip the facet at interior rib j is the angle between the
+ * boundary edges E_{j-1} = V_{j-1}V_j and E_j = V_jV_{j+1}.  An edge is regular
+ * when it is not empty and runs with the direction of travel at both of its
+ * ribs (n rotated by -90 deg, n = P - N; a rib of zero width has none); the
+ * boundary inside an offset cusp reverses.  A facet is ordinary when every edge
+ * of the segment within one rib of it (E_{j-2} .. E_{j+1}) is regular, which
+ * leaves out the facets beside offset cusps.  vx, vy [2R] and offsets as
+ * written by ps_emit or ps_emit_uniform.  stats: DEVICE double[4] = count,
+ * maximum, sum, sum of squares of the ordinary facet angles (radians),
+ * overwritten.  Sums are accumulated with atomics, so their last bits may
+ * depend on the order threads finish.
+ */
+int ps_facet_stats(const ps_batch* batch, const int64_t* offsets, const float* vx,
+                   const float* vy, double* stats, void* stream);
+
+/*
  * ps_dash -- dashing by arc length (Sec. "Dashing").  Reads the rib stream of
  * ps_emit (vx, vy, vs of vertex_capacity entries, the capacity the workspace
  * was sized with; offsets from ps_scan) and writes the "on" pieces: dx, dy

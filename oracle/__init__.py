@@ -42,7 +42,10 @@ def _load():
         lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_int] + [P] * 9 + [ctypes.c_double, P, ctypes.c_int]
         lib.oracle_count.restype = ctypes.c_int
         lib.oracle_emit.argtypes = ([ctypes.c_int, ctypes.c_int] + [P] * 9
-                                    + [ctypes.c_double, ctypes.c_double, P] + [P] * 6 + [ctypes.c_int])
+                                    + [ctypes.c_double, ctypes.c_double, P] + [P] * 6
+                                    + [ctypes.c_int, ctypes.c_int])
+        lib.oracle_facet_stats.argtypes = [ctypes.c_int, P, P, P, P, P]
+        lib.oracle_facet_stats.restype = None
         lib.oracle_emit.restype = ctypes.c_int
         lib.oracle_segment_intervals.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double,
                                                  P, P, P, P, P, ctypes.c_int]
@@ -87,9 +90,9 @@ def offsets(link_ribs: np.ndarray) -> np.ndarray:
     return off
 
 
-def emit(b, off: np.ndarray, q: float | None = None, nthreads: int = 0) -> dict:
+def emit(b, off: np.ndarray, q: float | None = None, nthreads: int = 0, uniform: bool = False) -> dict:
     """Vertices (vx, vy: [2R], N then P per rib), arc length vs [R], and per-rib
-    t, psi and role."""
+    t, psi and role.  uniform: segment ribs at t = j/N instead (the baseline)."""
     q = b.q if q is None else q
     R = int(off[-1])
     vx = np.zeros(2 * R); vy = np.zeros(2 * R); vs = np.zeros(R)
@@ -97,16 +100,34 @@ def emit(b, off: np.ndarray, q: float | None = None, nthreads: int = 0) -> dict:
     off = np.ascontiguousarray(off, np.int64)
     limit = float(getattr(b, "miter_limit", 4.0))
     rc = _load().oracle_emit(*_batch_args(b), ctypes.c_double(limit), ctypes.c_double(q), _p(off),
-                             _p(vx), _p(vy), _p(vs), _p(t), _p(psi), _p(role), nthreads)
+                             _p(vx), _p(vy), _p(vs), _p(t), _p(psi), _p(role), int(uniform), nthreads)
     if rc != 0:
         raise ValueError(f"oracle_emit failed ({rc})")
     return dict(vx=vx, vy=vy, vs=vs, t=t, psi=psi, role=role)
 
 
-def stroke(b, q: float | None = None, nthreads: int = 0) -> dict:
+def facet_stats(b, off: np.ndarray, vx: np.ndarray, vy: np.ndarray) -> dict:
+    """Ordinary facet angles of the segment ribs of a rib stream (FP32 vertices,
+    [2R] each): count, max, mean and standard deviation, in degrees."""
+    vx = np.ascontiguousarray(vx, np.float32); vy = np.ascontiguousarray(vy, np.float32)
+    off = np.ascontiguousarray(off, np.int64)
+    st = np.zeros(4)
+    _load().oracle_facet_stats(b.n_paths, _p(b.seg_begin), _p(off), _p(vx), _p(vy), _p(st))
+    return stats_from_sums(st)
+
+
+def stats_from_sums(st) -> dict:
+    n, mx, s1, s2 = (float(x) for x in st)
+    mean = s1 / n if n else 0.0
+    var = max(0.0, s2 / n - mean * mean) if n else 0.0
+    d = 180.0 / np.pi
+    return dict(count=int(n), max_deg=mx * d, mean_deg=mean * d, sd_deg=np.sqrt(var) * d)
+
+
+def stroke(b, q: float | None = None, nthreads: int = 0, uniform: bool = False) -> dict:
     ribs = count(b, q, nthreads)
     off = offsets(ribs)
-    out = emit(b, off, q, nthreads)
+    out = emit(b, off, q, nthreads, uniform)
     out.update(link_ribs=ribs, offsets=off)
     return out
 

@@ -565,8 +565,21 @@ struct Out {
   uint8_t* rib_role;        // [R]  ROLE_*
 };
 
+// Direction of g'(t) for the uniform baseline; where g' vanishes (a cusp hit
+// exactly) it is taken a step of 2^-20 / N further into the segment.
+V2 uniform_tangent(const Seg& s, double t, int N) {
+  V2 d = seg_deriv(s, t);
+  if (d.x == 0 && d.y == 0) {
+    double h = std::ldexp(1.0, -20) / N;
+    d = seg_deriv(s, t < 0.5 ? t + h : t - h);
+  }
+  return d;
+}
+
 // Emit the ribs of one path (Sec. "Complete Algorithm") with its arc length.
-void emit_path(const Batch& B, int p, double q, const int64_t* off, const Out& o) {
+// uniform: the baseline of Eq. NaiveStroking sampled at t_j = j/N with the
+// same rib count per segment (joins and caps unchanged).
+void emit_path(const Batch& B, int p, double q, const int64_t* off, const Out& o, bool uniform) {
   int b = B.seg_begin[p], e = B.seg_begin[p + 1];
   int first = 2 * b + p, last = 2 * e + p;   // inclusive slot range
   double s_acc = 0.0;
@@ -584,7 +597,11 @@ void emit_path(const Batch& B, int p, double q, const int64_t* off, const Out& o
         int jstart = (k == 0) ? 0 : 1;   // boundary ribs are shared
         for (int i = jstart; i <= v.steps; ++i, ++j) {
           double psi, t;
-          if (i == 0) { psi = v.psi0; t = v.t0; }
+          if (uniform) {
+            int N = L.ribs - 1;
+            t = (double)j / (double)N;
+            psi = angle_of(uniform_tangent(s, t, N));
+          } else if (i == 0) { psi = v.psi0; t = v.t0; }
           else if (i == v.steps) { psi = v.psi0 + v.delta; t = v.t1; }
           else {
             psi = v.psi0 + v.delta * (double)i / (double)v.steps;
@@ -663,12 +680,63 @@ int oracle_emit(int n_paths, int n_segs, const int32_t* seg_begin, const uint8_t
                 const float* cx, const float* cy, const float* conic_w, const float* width,
                 const uint8_t* join, const uint8_t* cap, const uint8_t* closed, double miter_limit,
                 double q, const int64_t* offsets, double* vx, double* vy, double* vs,
-                double* rib_t, double* rib_psi, uint8_t* rib_role, int nthreads) {
+                double* rib_t, double* rib_psi, uint8_t* rib_role, int uniform, int nthreads) {
   if (n_paths < 0 || n_segs < 0 || !(q > 0 && q <= kPi) || !(miter_limit >= 1.0)) return -1;
   Batch B{n_paths, n_segs, seg_begin, kind, cx, cy, conic_w, width, join, cap, closed, miter_limit};
   Out o{vx, vy, vs, rib_t, rib_psi, rib_role};
-  parallel_paths(n_paths, nthreads, [&](int p) { emit_path(B, p, q, offsets, o); });
+  parallel_paths(n_paths, nthreads, [&](int p) { emit_path(B, p, q, offsets, o, uniform != 0); });
   return 0;
+}
+
+// Facet angles of the segment ribs of a rib stream (Sec. "Uniform Tangent
+// Angle Step Tessellation": the angle where one quad meets the next).  On each
+// side of a segment's strip, the facet at interior rib j (0 < j < N) is the
+// angle between the boundary edges E_{j-1} = V_{j-1}V_j and E_j = V_jV_{j+1}.
+// An edge E_k is regular when it is not empty and runs with the generator's
+// direction of travel at both of its ribs; that direction at rib k is
+// n rotated by -90 degrees, n = P_k - N_k (a rib of zero width has none).  The
+// boundary inside an offset cusp reverses, so its edges are not regular; the
+// paper leaves out the few facets beside such cusps, and here a facet is
+// ordinary when every edge of the segment within one rib of it (E_{j-2} ..
+// E_{j+1}) is regular.  Writes the count, the maximum, the sum and the sum of
+// squares of the ordinary facet angles (radians) into stats[0..3].
+static bool facet_edge_regular(const float* vx, const float* vy, int64_t k, int side) {
+  double ex = (double)vx[2 * (k + 1) + side] - vx[2 * k + side];
+  double ey = (double)vy[2 * (k + 1) + side] - vy[2 * k + side];
+  if (ex == 0 && ey == 0) return false;
+  for (int64_t r = k; r <= k + 1; ++r) {
+    double nx = (double)vx[2 * r + 1] - vx[2 * r], ny = (double)vy[2 * r + 1] - vy[2 * r];
+    if (nx == 0 && ny == 0) return false;
+    // E . (n.y, -n.x) >= 0, scaled by |n|
+    if (ex * ny - ey * nx < 0) return false;
+  }
+  return true;
+}
+
+void oracle_facet_stats(int n_paths, const int32_t* seg_begin, const int64_t* offsets,
+                        const float* vx, const float* vy, double* stats) {
+  double cnt = 0, mx = 0, sum = 0, sq = 0;
+  for (int p = 0; p < n_paths; ++p) {
+    for (int i = seg_begin[p]; i < seg_begin[p + 1]; ++i) {
+      int64_t slot = 2 * (int64_t)i + p + 1;
+      int64_t r0 = offsets[slot], r1 = offsets[slot + 1];
+      for (int side = 0; side < 2; ++side) {
+        for (int64_t r = r0 + 1; r + 1 < r1; ++r) {
+          bool ordinary = true;
+          for (int64_t k = std::max(r0, r - 2); k <= std::min(r1 - 2, r + 1); ++k)
+            ordinary = ordinary && facet_edge_regular(vx, vy, k, side);
+          if (!ordinary) continue;
+          V2 a = {vx[2 * (r - 1) + side], vy[2 * (r - 1) + side]};
+          V2 b = {vx[2 * r + side], vy[2 * r + side]};
+          V2 c = {vx[2 * (r + 1) + side], vy[2 * (r + 1) + side]};
+          V2 e1 = sub(b, a), e2 = sub(c, b);
+          double ang = std::atan2(std::fabs(e1.x * e2.y - e1.y * e2.x), e1.x * e2.x + e1.y * e2.y);
+          cnt += 1; sum += ang; sq += ang * ang; mx = std::max(mx, ang);
+        }
+      }
+    }
+  }
+  stats[0] = cnt; stats[1] = mx; stats[2] = sum; stats[3] = sq;
 }
 
 // Per-segment intervals for inspection: writes up to cap entries of

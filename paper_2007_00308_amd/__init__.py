@@ -84,6 +84,9 @@ def load(path: str = LIB_PATH):
         "ps_plan_config": (ctypes.c_int, [_vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
         "ps_set_emit_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "ps_set_plan_autotune": (ctypes.c_int, [ctypes.c_int32]),
+        "ps_emit_uniform": (ctypes.c_int, [P(ps_batch), P(ps_params), _vp, _vp, _vp, ctypes.c_int64, _vp,
+                                           ctypes.c_size_t, _vp]),
+        "ps_facet_stats": (ctypes.c_int, [P(ps_batch), _vp, _vp, _vp, _vp, _vp]),
         "ps_last_error": (ctypes.c_char_p, []),
         "ps_version": (ctypes.c_char_p, []),
     }
@@ -180,6 +183,17 @@ def ps_emit(db, params, offsets, vx, vy, vs, vertex_capacity, ws, stream=None):
     _check(load().ps_emit(ctypes.byref(db.struct), ctypes.byref(params), _ptr(offsets), _ptr(vx),
                           _ptr(vy), _ptr(vs), int(vertex_capacity), _ptr(ws),
                           ws.numel() * ws.element_size(), _stream(stream)), "ps_emit")
+
+
+def ps_emit_uniform(db, params, offsets, vx, vy, vertex_capacity, ws, stream=None):
+    _check(load().ps_emit_uniform(ctypes.byref(db.struct), ctypes.byref(params), _ptr(offsets), _ptr(vx),
+                                  _ptr(vy), int(vertex_capacity), _ptr(ws), ws.numel() * ws.element_size(),
+                                  _stream(stream)), "ps_emit_uniform")
+
+
+def ps_facet_stats(db, offsets, vx, vy, stats, stream=None):
+    _check(load().ps_facet_stats(ctypes.byref(db.struct), _ptr(offsets), _ptr(vx), _ptr(vy), _ptr(stats),
+                                 _stream(stream)), "ps_facet_stats")
 
 
 def ps_arclen(db, params, offsets, vs, vertex_capacity, ws, stream=None):

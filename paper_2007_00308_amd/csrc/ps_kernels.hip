@@ -1323,6 +1323,127 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
 }
 
 // ===========================================================================
+// Uniform parametric baseline and facet statistics (Sec. "Versus Uniform
+// Parametric Tessellation")
+// ===========================================================================
+struct UniformArgs {
+  const LinkRec* rec;
+  const int64_t* off;
+  int64_t n_links;
+  float* vx;
+  float* vy;
+  int64_t capacity;
+  double miter_limit;
+};
+
+// One thread per link slot: segment ribs at t_j = j/N on Eq. NaiveStroking,
+// joins and caps as the polar emit.
+__global__ void __launch_bounds__(256) uniform_emit_kernel(UniformArgs A) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= A.n_links || 2 * A.off[A.n_links] > A.capacity) return;
+  const int64_t r0 = A.off[l], n = A.off[l + 1] - r0;
+  if (n <= 0) return;
+  const LinkRec& rp = A.rec[l];
+  if (rp.role != ROLE_SEG) {
+    for (int j = 0; j < (int)n; ++j) {
+      RibOut o;
+      compute_rib<PS_PREC_FP64, kPivotOnly>(rp, j, 0.f, A.miter_limit, o);
+      *reinterpret_cast<float2*>(A.vx + 2 * (r0 + j)) = make_float2(o.Nx, o.Px);
+      *reinterpret_cast<float2*>(A.vy + 2 * (r0 + j)) = make_float2(o.Ny, o.Py);
+    }
+    return;
+  }
+  double X[4], Y[4];
+  for (int i = 0; i < 4; ++i) { X[i] = rp.x[i]; Y[i] = rp.y[i]; }
+  const double w = rp.w, rad = rp.r;
+  const Hodo<double> h = hodo_of<double>(rp.kind, X, Y, w);
+  const int N = (int)n - 1;
+  for (int j = 0; j <= N; ++j) {
+    const double t = (double)j / (double)N;
+    double gx, gy, hx, hy;
+    eval_point(rp.kind, X, Y, w, t, gx, gy);
+    hodo_eval(h, t, hx, hy);   // a positive multiple of g'(t)
+    if (hx == 0.0 && hy == 0.0) {
+      const double d = ldexp(1.0, -20) / N;
+      hodo_eval(h, t < 0.5 ? t + d : t - d, hx, hy);
+    }
+    const double inv = 1.0 / sqrt(hx * hx + hy * hy);
+    const double nx = -hy * inv, ny = hx * inv;
+    const int64_t r = r0 + j;
+    *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2((float)(gx - rad * nx), (float)(gx + rad * nx));
+    *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2((float)(gy - rad * ny), (float)(gy + rad * ny));
+  }
+}
+
+__global__ void clear_stats_kernel(double* stats) {
+  if (threadIdx.x < 4) stats[threadIdx.x] = 0.0;
+}
+
+// Boundary edge k -> k+1 on one side is regular when it is not empty and
+// runs with the direction of travel (n rotated by -90 deg, n = P - N) at both
+// of its ribs; the sign test is taken on the unnormalised product, without
+// contraction, so that it is exact for coordinates of one magnitude.
+__device__ bool facet_edge_ok(const float* vx, const float* vy, int64_t k, int side) {
+#pragma clang fp contract(off)
+  const double ex = (double)vx[2 * (k + 1) + side] - vx[2 * k + side];
+  const double ey = (double)vy[2 * (k + 1) + side] - vy[2 * k + side];
+  bool ok = !(ex == 0 && ey == 0);
+  for (int64_t r = k; r <= k + 1; ++r) {
+    const double nx = (double)vx[2 * r + 1] - vx[2 * r], ny = (double)vy[2 * r + 1] - vy[2 * r];
+    ok = ok && !(nx == 0 && ny == 0) && !(ex * ny - ey * nx < 0);
+  }
+  return ok;
+}
+
+// One thread per segment: its ordinary facets on both sides (those with every
+// edge within one rib regular; the reversed edges are the boundary inside an
+// offset cusp), reduced per wavefront, then added into stats (max through the
+// bit pattern, which orders non-negative doubles).
+__global__ void __launch_bounds__(256) facet_stats_kernel(const int32_t* seg_begin, int n_paths,
+                                                          int n_segs, const int64_t* off,
+                                                          const float* vx, const float* vy,
+                                                          double* stats) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double cnt = 0, mx = 0, sum = 0, sq = 0;
+  if (i < n_segs) {
+    const int p = path_of_seg(seg_begin, n_paths, (int)i);
+    const int64_t slot = 2 * i + p + 1;
+    const int64_t r0 = off[slot], r1 = off[slot + 1];
+    for (int side = 0; side < 2; ++side) {
+      // bit m of ok: edge r - 2 + m regular (edges outside the segment count as regular)
+      unsigned ok = 0;
+      for (int m = 0; m < 4; ++m) {
+        const int64_t k = r0 - 1 + m;
+        ok |= (unsigned)(k < r0 || k > r1 - 2 || facet_edge_ok(vx, vy, k, side)) << m;
+      }
+      for (int64_t r = r0 + 1; r + 1 < r1; ++r) {
+        if (ok == 15u) {
+          const double ax = vx[2 * (r - 1) + side], ay = vy[2 * (r - 1) + side];
+          const double bx = vx[2 * r + side], by = vy[2 * r + side];
+          const double cx = vx[2 * (r + 1) + side], cy = vy[2 * (r + 1) + side];
+          const double e1x = bx - ax, e1y = by - ay, e2x = cx - bx, e2y = cy - by;
+          const double ang = atan2(fabs(e1x * e2y - e1y * e2x), e1x * e2x + e1y * e2y);
+          cnt += 1; sum += ang; sq += ang * ang; mx = fmax(mx, ang);
+        }
+        const int64_t k = r + 2;  // enters the window of rib r + 1
+        ok = (ok >> 1) | ((unsigned)(k > r1 - 2 || facet_edge_ok(vx, vy, k, side)) << 3);
+      }
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    cnt += __shfl_xor(cnt, d, 64); sum += __shfl_xor(sum, d, 64); sq += __shfl_xor(sq, d, 64);
+    mx = fmax(mx, __shfl_xor(mx, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0 && cnt > 0) {
+    atomicAdd(&stats[0], cnt);
+    atomicMax(reinterpret_cast<unsigned long long*>(&stats[1]),
+              (unsigned long long)__double_as_longlong(mx));
+    atomicAdd(&stats[2], sum);
+    atomicAdd(&stats[3], sq);
+  }
+}
+
+// ===========================================================================
 // Dash (Sec. "Dashing")
 // ===========================================================================
 struct DashArgs {
@@ -1910,6 +2031,39 @@ int ps_arclen(const ps_batch* b, const ps_params* p, const int64_t* offsets, flo
   const EmitConfig c = current_cfg();
   return launch_emit(b, p, offsets, nullptr, nullptr, vs, cap, ws_view(ws, w), w, c.K, c.waves,
                      c.stage, (hipStream_t)stream);
+}
+
+int ps_emit_uniform(const ps_batch* b, const ps_params* p, const int64_t* offsets, float* vx,
+                    float* vy, int64_t cap, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_batch(b)) || (rc = check_params(p))) return rc;
+  if (!offsets || !vx || !vy) return fail(PS_E_ARG, "NULL array");
+  if (cap < 0) return fail(PS_E_ARG, "negative capacity");
+  const WsLayout w = ws_layout(n_links_of(b), cap, 0);
+  if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+  const WsView v = ws_view(ws, w);
+  UniformArgs a;
+  a.rec = v.rec; a.off = offsets; a.n_links = n_links_of(b); a.vx = vx; a.vy = vy;
+  a.capacity = cap; a.miter_limit = p->miter_limit;
+  if (a.n_links > 0)
+    hipLaunchKernelGGL(uniform_emit_kernel, dim3(grid_for(a.n_links, 256)), dim3(256), 0,
+                       (hipStream_t)stream, a);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
+int ps_facet_stats(const ps_batch* b, const int64_t* offsets, const float* vx, const float* vy,
+                   double* stats, void* stream) {
+  int rc;
+  if ((rc = check_batch(b))) return rc;
+  if (!offsets || !vx || !vy || !stats) return fail(PS_E_ARG, "NULL array");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(clear_stats_kernel, dim3(1), dim3(64), 0, s, stats);
+  if (b->n_segs > 0)
+    hipLaunchKernelGGL(facet_stats_kernel, dim3(grid_for(b->n_segs, 256)), dim3(256), 0, s,
+                       b->seg_begin, b->n_paths, b->n_segs, offsets, vx, vy, stats);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
 }
 
 int ps_dash(const ps_batch* b, const ps_params* p, const int64_t* offsets, const float* vx,

@@ -281,3 +281,54 @@ def test_plan_graph_replays_match_eager():
         torch.ones(1 << 20, device="cuda").sum().item()
     assert plan.status().flags == 0
     plan.close()
+
+
+# ------------------------------------------------ uniform baseline, facet angles
+def _serpentines(seed, n, width=100.0, q=math.radians(4.0)):
+    # cubic serpentines (one inflection) and loops drawn on the 2^-8 grid
+    rng = np.random.default_rng(seed)
+    segs = []
+    for _ in range(n):
+        P0 = rng.uniform(0, 512, 2); P3 = P0 + rng.uniform(-300, 300, 2)
+        P1 = P0 + rng.uniform(-200, 200, 2); P2 = P3 + rng.uniform(-200, 200, 2)
+        pts = [tuple(np.round(P * 256) / 256) for P in (P0, P1, P2, P3)]
+        segs.append([(W.KIND_C, pts, 1.0)])
+    return W.paths(segs, widths=[width] * n, q=q)
+
+
+def test_uniform_baseline_matches_oracle():
+    b = _serpentines(5, 64)
+    ref = oracle.stroke(b, uniform=True)
+    db, out = _gpu(b)
+    import torch
+    vx, vy = torch.empty_like(out["vx"]), torch.empty_like(out["vy"])
+    ps.ps_emit_uniform(db, out["params"], out["offsets"], vx, vy, out["capacity"], out["ws"])
+    torch.cuda.synchronize()
+    R = out["total_ribs"]
+    err = np.hypot(_np(vx)[:2 * R] - ref["vx"], _np(vy)[:2 * R] - ref["vy"])
+    assert err.max() <= VERTEX_TOL, err.max()
+
+
+def test_facet_stats_match_oracle():
+    import torch
+    b = _serpentines(6, 64)
+    db, out = _gpu(b)
+    R = out["total_ribs"]
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    for uniform in (False, True):
+        vx, vy = out["vx"], out["vy"]
+        if uniform:
+            vx, vy = torch.empty_like(vx), torch.empty_like(vy)
+            ps.ps_emit_uniform(db, out["params"], out["offsets"], vx, vy, out["capacity"], out["ws"])
+        ps.ps_facet_stats(db, out["offsets"], vx, vy, stats)
+        torch.cuda.synchronize()
+        got = oracle.stats_from_sums(_np(stats))
+        # the same statistics of the same vertices, summed in another order
+        ref = oracle.facet_stats(b, _np(out["offsets"]), _np(vx)[:2 * R], _np(vy)[:2 * R])
+        assert got["count"] == ref["count"]
+        for k in ("max_deg", "mean_deg", "sd_deg"):
+            assert got[k] == pytest.approx(ref[k], rel=1e-9, abs=1e-12), (uniform, k)
+    # polar stroking keeps ordinary facets below 2q
+    ps.ps_facet_stats(db, out["offsets"], out["vx"], out["vy"], stats)
+    torch.cuda.synchronize()
+    assert oracle.stats_from_sums(_np(stats))["max_deg"] < 2 * 4.0 + 0.05

@@ -471,3 +471,58 @@ def test_dash_phase_and_restart():
     # pattern position 7 at s=0 is in the gap (4..10): first dash starts at s=3
     starts = d["ds"][d["ranges"][:, 0]]
     np.testing.assert_allclose(starts, [3, 13, 23, 33, 43, 3, 13, 23, 33, 43])
+
+
+# --------------------------------------------------- uniform baseline, facets
+def test_facets_of_a_circle_equal_the_step():
+    # polar stroking of a circular arc is a regular polygon on both sides:
+    # every facet turns by the step 90/32 deg
+    c = gold("quarter circle as a conic")
+    b = W.single(c["kind"], c["points"], w=c["w"], width=c["width"], q=math.radians(c["q_deg"]))
+    o = oracle.stroke(b)
+    st = oracle.facet_stats(b, o["offsets"], o["vx"], o["vy"])
+    assert st["count"] == 2 * (c["ribs"] - 2)
+    assert st["max_deg"] == pytest.approx(90 / 32, abs=1e-3)
+    assert st["mean_deg"] == pytest.approx(90 / 32, abs=1e-3)
+    assert st["sd_deg"] < 1e-3
+
+
+def test_facets_of_a_straight_segment_are_zero():
+    b = W.single(W.KIND_C, [(0, 0), (10, 0), (30, 0), (60, 0)], width=4.0, q=math.pi / 16)
+    for uniform in (False, True):
+        o = oracle.stroke(b, uniform=uniform)
+        st = oracle.facet_stats(b, o["offsets"], o["vx"], o["vy"])
+        assert st["max_deg"] == 0.0
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_polar_facets_are_below_twice_q(case):
+    # ordinary facet angles are bounded by 2q (Sec. "Uniform Tangent Angle
+    # Step Tessellation")
+    kind, pts, w = TINY[case]
+    q = math.pi / 32
+    b = W.single(kind, pts, w=w, width=3.0, q=q)
+    o = oracle.stroke(b)
+    st = oracle.facet_stats(b, o["offsets"], o["vx"], o["vy"])
+    assert st["max_deg"] < 2 * math.degrees(q) + 1e-6
+
+
+@pytest.mark.parametrize("case", range(len(TINY)))
+def test_uniform_ribs_sit_at_uniform_parameters(case):
+    # Eq. NaiveStroking sampled at t_j = j/N: rib centres on the curve at j/N,
+    # rib direction along the normal of g'(j/N) (independent evaluator)
+    kind, pts, w = TINY[case]
+    b = W.single(kind, pts, w=w, width=3.0, q=math.pi / 32)
+    o = oracle.stroke(b, uniform=True)
+    sl = seg_ribs(o, b)
+    N = sl.stop - sl.start - 1
+    t = np.arange(N + 1) / N
+    Gx = 0.5 * (o["vx"][0::2][sl] + o["vx"][1::2][sl]); Gy = 0.5 * (o["vy"][0::2][sl] + o["vy"][1::2][sl])
+    ref = G.point(kind, pts, t, w)
+    np.testing.assert_allclose(Gx, ref[:, 0], atol=1e-9 * (1 + np.abs(ref).max()))
+    np.testing.assert_allclose(Gy, ref[:, 1], atol=1e-9 * (1 + np.abs(ref).max()))
+    d, speed = G.tangent_dirs(kind, pts, t, w)
+    nx = o["vx"][1::2][sl] - o["vx"][0::2][sl]; ny = o["vy"][1::2][sl] - o["vy"][0::2][sl]
+    ok = speed > 1e-3 * speed.max()          # away from a cusp the normal is defined
+    cross = (d[:, 0] * ny - d[:, 1] * nx) / 3.0          # |n| = width, so cross = +1
+    np.testing.assert_allclose(cross[ok], 1.0, atol=1e-5)
