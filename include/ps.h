@@ -76,7 +76,7 @@ enum {
 enum {
   PS_STATUS_OVERFLOW = 1u,       /* 2 * total ribs > vertex capacity: no emit  */
   PS_STATUS_NONFINITE = 2u,      /* a control point, weight or width not finite */
-  PS_STATUS_BAD_VALUE = 4u,      /* unknown kind/style, w_B <= 0, width <= 0    */
+  PS_STATUS_BAD_VALUE = 4u,      /* unknown kind/style, w_B <= -1, width <= 0   */
   PS_STATUS_DASH_OVERFLOW = 8u,  /* dash output exceeded its capacity           */
   PS_STATUS_INTERVALS = 16u      /* a segment needed more than 5 intervals      */
 };
@@ -89,7 +89,9 @@ enum {
  *   kind      [n_segs]     PS_KIND_*
  *   cx, cy    [4*n_segs]   control point k of segment i at [k*n_segs + i];
  *                          a line uses k<2, a quadratic or conic k<3
- *   conic_w   [n_segs]     w_B of conics (> 0); ignored for other kinds
+ *   conic_w   [n_segs]     w_B of conics (> -1; a negative weight draws the
+ *                          external arc, 0 the chord P0 P2); ignored for
+ *                          other kinds
  *   width     [n_paths]    stroke width w (> 0)
  *   join, cap [n_paths]    PS_JOIN_*, PS_CAP_*
  *   closed    [n_paths]    1: a closed contour (a join from the last segment

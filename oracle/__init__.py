@@ -148,6 +148,8 @@ def segment_intervals(kind: int, pts, q: float, w: float = 1.0):
     st = np.zeros(cap, np.int32)
     n = _load().oracle_segment_intervals(kind, _p(px), _p(py), ctypes.c_double(np.float32(w)),
                                          ctypes.c_double(q), _p(t0), _p(t1), _p(p0), _p(d), _p(st), cap)
+    if n < 0:
+        raise ValueError("unbounded conic (w_B <= -1)")
     return [(t0[k], t1[k], p0[k], d[k], int(st[k])) for k in range(n)]
 
 

@@ -124,7 +124,12 @@ V2 seg_deriv(const Seg& s, double t) {
   }
 }
 
+// A segment whose control points coincide has zero length.  A conic with
+// w_B = 0 reduces to the chord P0 P2 whatever P1 is (the middle term of the
+// numerator and the denominator vanish together), so it has zero length when
+// its end points coincide.
 bool zero_length(const Seg& s) {
+  if (s.kind == KIND_K && s.w == 0) return s.P[2].x == s.P[0].x && s.P[2].y == s.P[0].y;
   for (int i = 1; i < s.npts; ++i)
     if (s.P[i].x != s.P[0].x || s.P[i].y != s.P[0].y) return false;
   return true;
@@ -271,13 +276,21 @@ int rotation_sense(const Seg& s, double t0, double t1) {
     }
     return 0;
   }
-  if (s.kind == KIND_Q || s.kind == KIND_K)
+  if (s.kind == KIND_Q)
     return sgn(cross(sub(s.P[1], s.P[0]), sub(s.P[2], s.P[1])));
+  if (s.kind == KIND_K) {
+    // g' x g'' = 4 w_B ((P1-P0) x (P2-P1)) / D(t)^3 with D(t) > 0 for w_B > -1:
+    // a negative weight turns the tangent the other way, so an external
+    // ellipse runs the long way round (Sec. "Bounding Total Curvature Within
+    // Tangent Angle Intervals")
+    return sgn(s.w) * sgn(cross(sub(s.P[1], s.P[0]), sub(s.P[2], s.P[1])));
+  }
   return 0;
 }
 
 bool exactly_collinear(const Seg& s) {
   if (s.kind == KIND_L) return true;
+  if (s.kind == KIND_K && s.w == 0) return true;   // the chord P0 P2
   V2 a = sub(s.P[1], s.P[0]), b = sub(s.P[2], s.P[1]);
   if (s.kind == KIND_C) {
     V2 c = sub(s.P[3], s.P[2]);
@@ -653,6 +666,16 @@ void parallel_paths(int n_paths, int nthreads, F fn) {
   for (auto& t : th) t.join();
 }
 
+
+// A conic with w_B <= -1 has a root of its denominator in [0, 1] (at
+// t = 1/2 +- sqrt((-1 - w_B) / (1 - w_B)) / 2): the curve runs through a point
+// at infinity and its stroke is unbounded, so no batch may hold one.
+bool weights_bounded(int n_segs, const uint8_t* kind, const float* conic_w) {
+  for (int i = 0; i < n_segs; ++i)
+    if (kind[i] == KIND_K && !((double)conic_w[i] > -1.0)) return false;
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -665,6 +688,7 @@ int oracle_count(int n_paths, int n_segs, const int32_t* seg_begin, const uint8_
                  const uint8_t* join, const uint8_t* cap, const uint8_t* closed, double q,
                  int32_t* link_ribs, int nthreads) {
   if (n_paths < 0 || n_segs < 0 || !(q > 0 && q <= kPi)) return -1;
+  if (!weights_bounded(n_segs, kind, conic_w)) return -2;
   Batch B{n_paths, n_segs, seg_begin, kind, cx, cy, conic_w, width, join, cap, closed, 4.0};
   parallel_paths(n_paths, nthreads, [&](int p) {
     int b = seg_begin[p], e = seg_begin[p + 1];
@@ -682,6 +706,7 @@ int oracle_emit(int n_paths, int n_segs, const int32_t* seg_begin, const uint8_t
                 double q, const int64_t* offsets, double* vx, double* vy, double* vs,
                 double* rib_t, double* rib_psi, uint8_t* rib_role, int uniform, int nthreads) {
   if (n_paths < 0 || n_segs < 0 || !(q > 0 && q <= kPi) || !(miter_limit >= 1.0)) return -1;
+  if (!weights_bounded(n_segs, kind, conic_w)) return -2;
   Batch B{n_paths, n_segs, seg_begin, kind, cx, cy, conic_w, width, join, cap, closed, miter_limit};
   Out o{vx, vy, vs, rib_t, rib_psi, rib_role};
   parallel_paths(n_paths, nthreads, [&](int p) { emit_path(B, p, q, offsets, o, uniform != 0); });
@@ -746,6 +771,7 @@ int oracle_segment_intervals(int kind, const double* px, const double* py, doubl
                              int cap) {
   Seg s;
   s.kind = kind; s.npts = npts_of(kind); s.w = kind == KIND_K ? w : 1.0;
+  if (!(s.w > -1.0)) return -1;
   for (int k = 0; k < 4; ++k) { s.P[k].x = k < s.npts ? px[k] : 0; s.P[k].y = k < s.npts ? py[k] : 0; }
   if (zero_length(s)) return 0;
   std::vector<Interval> iv = segment_intervals(s, q);

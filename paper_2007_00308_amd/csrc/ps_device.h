@@ -91,6 +91,8 @@ __device__ inline Seg load_seg(const ps_batch& B, int i) {
 
 // (the padded points repeat the last one, so all four can be tested)
 __device__ __forceinline__ bool seg_is_point(const Seg& s) {
+  // a conic of weight 0 is its chord P0 P2, whatever P1 is
+  if (s.kind == PS_KIND_CONIC && s.w == 0.0) return s.x[2] == s.x[0] && s.y[2] == s.y[0];
   bool same = true;
 #pragma unroll
   for (int k = 1; k < 4; ++k) same = same && s.x[k] == s.x[0] && s.y[k] == s.y[0];
@@ -123,9 +125,12 @@ __device__ inline void start_dir(const Seg& s, double& dx, double& dy) {
   if (s.kind == PS_KIND_CUBIC) {
     if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
     if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[0]; dy = s.y[3] - s.y[0]; }
-  } else if (s.kind != PS_KIND_LINE) {
-    // quadratic, conic (w_B > 0 here, so sgn(w_B) = +1)
+  } else if (s.kind == PS_KIND_QUAD) {
     if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+  } else if (s.kind == PS_KIND_CONIC) {
+    // g'(0) = 2 w_B (P1 - P0): a negative weight starts backwards
+    if ((dx == 0 && dy == 0) || s.w == 0.0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+    else if (s.w < 0.0) { dx = -dx; dy = -dy; }
   }
 }
 
@@ -137,6 +142,10 @@ __device__ inline void end_dir(const Seg& s, double& dx, double& dy) {
   if (s.kind == PS_KIND_CUBIC) {
     if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[1]; dy = s.y[3] - s.y[1]; }
     if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[0]; dy = s.y[3] - s.y[0]; }
+  } else if (s.kind == PS_KIND_CONIC) {
+    // g'(1) = 2 w_B (P2 - P1)
+    if ((dx == 0 && dy == 0) || s.w == 0.0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+    else if (s.w < 0.0) { dx = -dx; dy = -dy; }
   } else {
     if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
   }
@@ -391,7 +400,7 @@ __device__ __forceinline__ void eval_point(int kind, const double* X, const doub
   } else {
     const double ww = (kind == PS_KIND_CONIC) ? w : 1.0;
     const double b0 = u * u, b1 = 2.0 * u * t * ww, b2 = t * t;
-    const double inv = rcp64(b0 + b1 + b2);   // > 0 for t in [0,1], w > 0
+    const double inv = rcp64(b0 + b1 + b2);   // >= (1 + w)/2 > 0 on [0,1] for w > -1
     gx = (b0 * X[0] + b1 * X[1] + b2 * X[2]) * inv;
     gy = (b0 * Y[0] + b1 * Y[1] + b2 * Y[2]) * inv;
   }

@@ -113,7 +113,9 @@ __device__ inline bool seg_usable(const ps_batch& B, int i, DevStatus* st, bool 
   if (k > PS_KIND_CUBIC) { if (report) set_flag(st, PS_STATUS_BAD_VALUE); return false; }
   const Seg s = load_seg(B, i);
   if (!seg_finite(s)) { if (report) set_flag(st, PS_STATUS_NONFINITE); return false; }
-  if (k == PS_KIND_CONIC && !(s.w > 0)) { if (report) set_flag(st, PS_STATUS_BAD_VALUE); return false; }
+  // w_B <= -1 puts a root of the conic's denominator in [0,1]: the curve runs
+  // through a point at infinity and its stroke is unbounded
+  if (k == PS_KIND_CONIC && !(s.w > -1.0)) { if (report) set_flag(st, PS_STATUS_BAD_VALUE); return false; }
   return !seg_is_point(s);
 }
 
@@ -146,7 +148,8 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
     X3 = crs(ax, ay, bx, by); Y3 = crs(ax, ay, cx, cy); Z3 = crs(bx, by, cx, cy);
     collinear = (X3 == 0 && Y3 == 0 && Z3 == 0);
   } else {
-    collinear = crs(ax, ay, bx, by) == 0;
+    // a conic of weight 0 is the chord P0 P2
+    collinear = crs(ax, ay, bx, by) == 0 || (s.kind == PS_KIND_CONIC && s.w == 0.0);
   }
 
   // interval n gets dsum[n], its end parameter p[n] and end angle psi[n+1];
@@ -222,7 +225,9 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
       if (sigma == 0) sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.25 * w));
       if (sigma == 0) sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.75 * w));
     } else {
-      sigma = sgn_d(crsQ);
+      // conics: g' x g'' = 4 w_B (a x b) / D^3 with D > 0, so a negative
+      // weight (an external ellipse) turns the other way, the long way round
+      sigma = sgn_d(crsQ) * (s.kind == PS_KIND_CONIC ? sgn_d(s.w) : 1.0);
     }
     if (sigma != 0 && d != 0 && sgn_d(d) != sigma && fabs(d) > kUnwrapGuard) d += kTwoPi * sigma;
     if (fabs(d) >= kPi) {

@@ -124,6 +124,62 @@ def test_closed_contours():
     assert np.all(start_caps[closed == 1] == 0) and np.any(start_caps[closed == 0] > 0)
 
 
+@pytest.mark.parametrize("prec", [ps.PS_PREC_FP32_FIXUP, ps.PS_PREC_FP64])
+def test_external_conics(prec):
+    # conic weights in [-0.8, 0): external ellipses, turning the long way
+    # round (split in two halves); every tenth conic of weight 0 (its chord)
+    b = W.random_mixed(52, n_paths=80, max_segs=16, extent=512.0)
+    k = np.flatnonzero(b.kind == W.KIND_K)
+    rng = np.random.default_rng(52)
+    b.conic_w[k] = -rng.uniform(0.02, 0.8, k.size).astype(np.float32)
+    b.conic_w[k[::10]] = 0.0
+    assert k.size > 50
+    _compare(b, precision=prec)
+
+
+def _ellipse_arc(cx, cy, ax, by, a0, a1):
+    # the conic control points of an arc of the ellipse (affine image of a
+    # circular arc: tangent-intersection middle point, weight cos(half angle))
+    m, h = 0.5 * (a0 + a1), 0.5 * (a1 - a0)
+    unit = [(math.cos(a0), math.sin(a0)), (math.cos(m) / math.cos(h), math.sin(m) / math.cos(h)),
+            (math.cos(a1), math.sin(a1))]
+    return [(cx + ax * u, cy + by * v) for u, v in unit], math.cos(h)
+
+
+def test_two_conic_ellipses():
+    # ellipses of two conic segments, the second external (the same control
+    # points backwards with the weight negated), closed, at several sizes
+    segs, widths = [], []
+    rng = np.random.default_rng(8)
+    for _ in range(32):
+        a0 = rng.uniform(-math.pi, math.pi); span = rng.uniform(0.3, 2.8)
+        pts, w = _ellipse_arc(rng.uniform(200, 800), rng.uniform(200, 800), rng.uniform(20, 300),
+                              rng.uniform(20, 300), a0, a0 + span)
+        segs.append([(W.KIND_K, pts, w), (W.KIND_K, pts[::-1], -w)])
+        widths.append(float(rng.uniform(1, 40)))
+    b = W.paths(segs, widths=widths, q=math.pi / 64, closed=[1] * len(segs))
+    r = _compare(b)
+    ref = oracle.stroke(b)
+    # five slots per ellipse: no caps (closed), and both joins are smooth
+    assert np.all(ref["link_ribs"].reshape(-1, 5)[:, [0, 2, 4]] == 0)
+    assert r["R"] > 32 * 128
+
+
+def test_unbounded_conics_flagged():
+    # w_B <= -1 runs through a point at infinity: flagged, no ribs
+    b = W.random_mixed(4, n_paths=6, max_segs=6)
+    k = np.flatnonzero(b.kind == W.KIND_K)
+    assert k.size >= 2
+    b.conic_w[k[0]] = -1.0
+    b.conic_w[k[1]] = -7.5
+    _, out = _gpu(b)
+    assert out["status"].flags & ps.PS_STATUS_BAD_VALUE
+    lr = _np(out["link_ribs"])
+    for i in k[:2]:
+        p = int(np.searchsorted(b.seg_begin, i, side="right")) - 1
+        assert lr[2 * i + p + 1] == 0
+
+
 def test_fp32_only_is_reported():
     # single precision alone is allowed a looser bound; it is not the default
     b = W.config2(n_paths=64, max_segs=32)

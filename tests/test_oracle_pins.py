@@ -157,6 +157,103 @@ def test_golden_closed_circle():
     assert o["vs"][-1] == pytest.approx(c["chord_sum"], rel=1e-8)
 
 
+def test_golden_two_conic_circle():
+    c = gold("closed circle of two conics, one external")
+    b = _gold_path(c)
+    o = oracle.stroke(b)
+    assert o["link_ribs"].tolist() == c["link_ribs"]
+    seg2 = c["segments"][1]
+    iv = oracle.segment_intervals(seg2[0], seg2[1], math.radians(c["q_deg"]), w=seg2[2])
+    got = [(math.degrees(p0) % 360, math.degrees(d), n) for _, _, p0, d, n in iv]
+    for g, e in zip(got, c["intervals_external"]):
+        assert g == pytest.approx(tuple(e), abs=1e-9)
+    assert len(got) == len(c["intervals_external"])
+    # every segment rib on the circle, at the point whose tangent is psi
+    R = c["radius"]
+    Gx = 0.5 * (o["vx"][0::2] + o["vx"][1::2])
+    Gy = 0.5 * (o["vy"][0::2] + o["vy"][1::2])
+    psi = o["psi"]
+    np.testing.assert_allclose(Gx, R * np.sin(psi), atol=2e-5)
+    np.testing.assert_allclose(Gy, -R * np.cos(psi), atol=2e-5)
+    # w_B = -cos 45 deg rounded to FP32 pulls the external arc up to 1e-5 px
+    # inside the circle; the chord sum moves with the arc length, measured here
+    # by dense sampling
+    short = sum(c["radius"] * abs(v[3]) for sg in c["segments"]
+                for v in oracle.segment_intervals(sg[0], sg[1], math.pi / 64, w=sg[2]))
+    short -= sum(G.arc_length(sg[0], sg[1], w=sg[2]) for sg in c["segments"])
+    assert 1e-5 < short < 3e-5
+    assert o["vs"][-1] == pytest.approx(c["chord_sum"] - short, abs=2e-7)
+
+
+def test_golden_zero_weight_conic_is_its_chord():
+    c = gold("conic of weight zero is its chord")
+    o = oracle.stroke(_gold_path(c))
+    assert o["link_ribs"].tolist() == c["link_ribs"]
+    line = dict(c, segments=[[W.KIND_L, c["line"]]])
+    ol = oracle.stroke(_gold_path(line))
+    for k in ("vx", "vy", "vs", "psi"):
+        np.testing.assert_array_equal(o[k], ol[k])
+    # the same conic with P0 == P2 is a point: no ribs
+    pt = dict(c, segments=[[W.KIND_K, [[10, 20], [-37, 55], [10, 20]], 0.0]])
+    assert oracle.stroke(_gold_path(pt))["link_ribs"].tolist() == [0, 0, 0]
+
+
+@pytest.mark.parametrize("w", [-1.0, -1.5, -40.0])
+def test_unbounded_conics_are_rejected(w):
+    # w_B <= -1: the denominator (1-t)^2 + 2 w_B (1-t) t + t^2 has a root in
+    # [0,1] (at t = 1/2 for w_B = -1), so the curve runs to infinity there
+    pts = [(0, 0), (5, 5), (10, -1)]
+    with pytest.raises(ValueError):
+        oracle.segment_intervals(W.KIND_K, pts, math.pi / 64, w=w)
+    b = W.single(W.KIND_K, pts, w=w, width=2.0, q=math.pi / 64)
+    with pytest.raises(ValueError):
+        oracle.count(b)
+    t = 0.5 + 0.5 * math.sqrt((-1 - w) / (1 - w))
+    assert (1 - t) ** 2 + 2 * w * (1 - t) * t + t * t == pytest.approx(0.0, abs=1e-12)
+
+
+def test_external_conic_is_the_complementary_arc():
+    # the same control points with weights w and -w trace complementary arcs
+    # of one conic: together they turn a full 2 pi, and the external arc
+    # leaves P0 backwards along -(P1 - P0)
+    pts = [(0, 0), (30, 40), (90, 10)]
+    for w in (0.2, 0.6, 0.95):
+        q = math.pi / 256
+        ti = sum(v[3] for v in oracle.segment_intervals(W.KIND_K, pts, q, w=w))
+        te = sum(v[3] for v in oracle.segment_intervals(W.KIND_K, pts, q, w=-w))
+        assert abs(ti) + abs(te) == pytest.approx(2 * math.pi, abs=1e-12)
+        assert np.sign(ti) == -np.sign(te)
+        iv = oracle.segment_intervals(W.KIND_K, pts, q, w=-w)
+        assert iv[0][2] == pytest.approx(math.atan2(-40, -30), abs=1e-12)
+        # points of the external arc satisfy the implicit equation of the
+        # conic through the internal arc (fit on the internal arc)
+        ti_ = np.linspace(0.05, 0.95, 7)
+        P = G.point(W.KIND_K, pts, ti_, w)
+        M = np.column_stack([P[:, 0] ** 2, P[:, 0] * P[:, 1], P[:, 1] ** 2, P[:, 0], P[:, 1], np.ones(7)])
+        coef = np.linalg.svd(M)[2][-1]
+        Q = G.point(W.KIND_K, pts, np.linspace(0.01, 0.99, 50), -w)
+        res = (coef[0] * Q[:, 0] ** 2 + coef[1] * Q[:, 0] * Q[:, 1] + coef[2] * Q[:, 1] ** 2
+               + coef[3] * Q[:, 0] + coef[4] * Q[:, 1] + coef[5])
+        scale = np.abs(M @ coef).max() + np.abs(coef[:3]).max() * 1e4
+        assert np.abs(res).max() < 1e-9 * scale
+
+
+def test_collinear_external_conic_folds():
+    # collinear control points with a negative weight: the curve leaves P0
+    # backwards (along -(P1 - P0)), turns round (a +pi pivot at the fold),
+    # overshoots P2 and turns round again to arrive along -(P2 - P1)
+    pts = [(0, 0), (40, 0), (100, 0)]
+    iv = oracle.segment_intervals(W.KIND_K, pts, math.pi / 64, w=-0.5)
+    assert [v[3] for v in iv] == [0.0, math.pi, 0.0, math.pi, 0.0]
+    assert [v[4] for v in iv] == [1, 64, 1, 64, 1]
+    ts = np.linspace(0, 1, 200_001)
+    x = G.point(W.KIND_K, pts, ts, -0.5)[:, 0]
+    assert iv[1][0] == pytest.approx(ts[np.argmin(x)], abs=1e-5)
+    assert iv[3][0] == pytest.approx(ts[np.argmax(x)], abs=1e-5)
+    assert x.min() < 0 and x.max() > 100
+    assert abs(angdiff(iv[0][2], math.pi)) < 1e-15
+
+
 def test_miter_within_limit_is_on_both_offset_lines():
     # any turn: within the limit the miter vertex lies at w/2 from both
     # segments' lines (the meeting point of the two offset lines)
@@ -258,6 +355,8 @@ TINY = [
     (W.KIND_K, [(0, 0), (5, 5), (10, -1)], 0.3),                # internal ellipse
     (W.KIND_K, [(0, 0), (5, 5), (10, -1)], 3.0),                # internal hyperbola
     (W.KIND_K, [(0, 0), (0, 7), (7, 7)], 1.0),                  # parabola as conic
+    (W.KIND_K, [(0, 0), (5, 5), (10, -1)], -0.3),               # external ellipse
+    (W.KIND_K, [(0, 0), (0, 7), (7, 7)], -0.85),                # external ellipse, long
 ]
 
 
