@@ -54,6 +54,12 @@ def _load():
                                     P, P, P, P, ctypes.c_int64, ctypes.c_int64, P]
         lib.oracle_dash.restype = ctypes.c_int64
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_coverage.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        lib.oracle_coverage.restype = None
+        lib.oracle_coverage_at.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int]
+        lib.oracle_coverage_at.restype = None
         _lib = lib
     return _lib
 
@@ -114,6 +120,33 @@ def facet_stats(b, off: np.ndarray, vx: np.ndarray, vy: np.ndarray) -> dict:
     st = np.zeros(4)
     _load().oracle_facet_stats(b.n_paths, _p(b.seg_begin), _p(off), _p(vx), _p(vy), _p(st))
     return stats_from_sums(st)
+
+
+COVER_QUAD, COVER_TRIANGLES = 0, 1
+
+
+def coverage(b, off: np.ndarray, vx: np.ndarray, vy: np.ndarray, x0: float, y0: float, W: int, H: int,
+             mode: int = COVER_QUAD) -> np.ndarray:
+    """Topmost covering path per sample of a W x H canvas ([H, W] int32, -1 where
+    no quad covers), from an FP32 rib stream (vx, vy: [2R])."""
+    vx = np.ascontiguousarray(vx, np.float32); vy = np.ascontiguousarray(vy, np.float32)
+    off = np.ascontiguousarray(off, np.int64)
+    top = np.empty((H, W), np.int32)
+    _load().oracle_coverage(b.n_paths, _p(b.seg_begin), _p(off), _p(vx), _p(vy), ctypes.c_double(x0),
+                            ctypes.c_double(y0), W, H, mode, _p(top))
+    return top
+
+
+def coverage_at(b, off: np.ndarray, vx: np.ndarray, vy: np.ndarray, x0: float, y0: float, pi, pj,
+                mode: int = COVER_QUAD, nthreads: int = 0) -> np.ndarray:
+    """The same value at single pixels (pi[k], pj[k]), each from every quad."""
+    vx = np.ascontiguousarray(vx, np.float32); vy = np.ascontiguousarray(vy, np.float32)
+    off = np.ascontiguousarray(off, np.int64)
+    pi = np.ascontiguousarray(pi, np.int32); pj = np.ascontiguousarray(pj, np.int32)
+    out = np.empty(pi.size, np.int32)
+    _load().oracle_coverage_at(b.n_paths, _p(b.seg_begin), _p(off), _p(vx), _p(vy), ctypes.c_double(x0),
+                               ctypes.c_double(y0), mode, pi.size, _p(pi), _p(pj), _p(out), nthreads)
+    return out
 
 
 def stats_from_sums(st) -> dict:

@@ -667,6 +667,81 @@ void parallel_paths(int n_paths, int nthreads, F fn) {
 }
 
 
+// ---------------------------------------------------------------------------
+// Coverage of the quad strip (Sec. "Stroked Paths Tessellated to Quad
+// Strips"; the support predicate, Eq. polar-stroking-predicate, taken over the
+// tessellation).  A path covers a sample when any of its quads does, and a
+// quad covers it when its winding number is nonzero, so both lobes of a
+// bow-tie quad count and nothing between them (the quad rasterized as such,
+// not as two overlapping triangles).
+// ---------------------------------------------------------------------------
+enum { COVER_QUAD = 0, COVER_TRIANGLES = 1 };
+
+// Winding number of the closed polygon (x[k], y[k]), k < n, about (px, py):
+// an edge going up with the point strictly to its left counts +1, an edge
+// going down with the point strictly to its right counts -1; an edge counts as
+// going up when it starts at or below py and ends above it (half-open).
+int winding_number(const double* x, const double* y, int n, double px, double py) {
+  int wn = 0;
+  for (int k = 0; k < n; ++k) {
+    double ux = x[k], uy = y[k], vx = x[(k + 1) % n], vy = y[(k + 1) % n];
+    double side = (vx - ux) * (py - uy) - (px - ux) * (vy - uy);
+    if (uy <= py) {
+      if (vy > py && side > 0) ++wn;
+    } else {
+      if (vy <= py && side < 0) --wn;
+    }
+  }
+  return wn;
+}
+
+// The quad between ribs r and r+1: a = N_r, b = P_r, c = P_{r+1}, d = N_{r+1}.
+// COVER_TRIANGLES takes the two triangles (a, b, c) and (a, c, d) that a
+// triangle rasterizer would draw instead.
+bool quad_covers(const double* x, const double* y, int mode, double px, double py) {
+  if (mode == COVER_QUAD) return winding_number(x, y, 4, px, py) != 0;
+  double tx[3] = {x[0], x[2], x[3]}, ty[3] = {y[0], y[2], y[3]};
+  return winding_number(x, y, 3, px, py) != 0 || winding_number(tx, ty, 3, px, py) != 0;
+}
+
+// Calls fn(r, p) for every quad (ribs r, r+1) of path p: consecutive ribs of
+// one link, and the quad from a link's last rib to the next link's first rib
+// unless both links are segments (two segments meet with no join ribs between
+// them; the quad would draw a bevel where the join style asks for none).  A
+// link's role follows from its slot: the start cap first, then segment, join,
+// segment, ..., join or end cap.
+template <class F>
+void for_each_quad(const int32_t* seg_begin, const int64_t* offsets, int p, F fn) {
+  int64_t first = 2 * (int64_t)seg_begin[p] + p, last = 2 * (int64_t)seg_begin[p + 1] + p;
+  int64_t prev_rib = -1, prev_slot = -1;
+  for (int64_t l = first; l <= last; ++l) {
+    bool seg = ((l - first) & 1) == 1;
+    for (int64_t r = offsets[l]; r < offsets[l + 1]; ++r) {
+      if (prev_rib >= 0) {
+        bool prev_seg = ((prev_slot - first) & 1) == 1;
+        if (prev_slot == l || !(prev_seg && seg)) fn(prev_rib, p);
+      }
+      prev_rib = r; prev_slot = l;
+    }
+  }
+}
+
+void quad_corners(const float* vx, const float* vy, int64_t r, double* x, double* y) {
+  x[0] = vx[2 * r];           y[0] = vy[2 * r];            // N_r
+  x[1] = vx[2 * r + 1];       y[1] = vy[2 * r + 1];        // P_r
+  x[2] = vx[2 * (r + 1) + 1]; y[2] = vy[2 * (r + 1) + 1];  // P_{r+1}
+  x[3] = vx[2 * (r + 1)];     y[3] = vy[2 * (r + 1)];      // N_{r+1}
+}
+
+// Range of sample indices k (sample at o + k + 1/2, k in [0, n)) whose sample
+// lies in [lo, hi]; empty when k0 > k1.
+void sample_range(double lo, double hi, double o, int n, int64_t* k0, int64_t* k1) {
+  double a = std::ceil(lo - o - 0.5), b = std::floor(hi - o - 0.5);
+  *k0 = (int64_t)std::max(a, 0.0);
+  *k1 = (int64_t)std::min(b, (double)n - 1);
+}
+
+
 // A conic with w_B <= -1 has a root of its denominator in [0, 1] (at
 // t = 1/2 +- sqrt((-1 - w_B) / (1 - w_B)) / 2): the curve runs through a point
 // at infinity and its stroke is unbounded, so no batch may hold one.
@@ -852,6 +927,60 @@ int64_t oracle_dash(int n_paths, const int64_t* path_rib_begin, const float* vx,
   }
   *n_dashes = nd;
   return overflow ? -out : out;
+}
+
+// Topmost covering path per sample of a W x H canvas (sample of pixel (i, j)
+// at (x0 + i + 1/2, y0 + j + 1/2)): top[j*W + i] = the largest path index
+// whose quads cover the sample, -1 where none does (a renderer drawing opaque
+// strokes in path order shows that path there).
+void oracle_coverage(int n_paths, const int32_t* seg_begin, const int64_t* offsets,
+                     const float* vx, const float* vy, double x0, double y0, int W, int H,
+                     int mode, int32_t* top) {
+  for (int64_t k = 0; k < (int64_t)W * H; ++k) top[k] = -1;
+  for (int p = 0; p < n_paths; ++p) {
+    for_each_quad(seg_begin, offsets, p, [&](int64_t r, int pp) {
+      double x[4], y[4];
+      quad_corners(vx, vy, r, x, y);
+      double xl = std::min(std::min(x[0], x[1]), std::min(x[2], x[3]));
+      double xh = std::max(std::max(x[0], x[1]), std::max(x[2], x[3]));
+      double yl = std::min(std::min(y[0], y[1]), std::min(y[2], y[3]));
+      double yh = std::max(std::max(y[0], y[1]), std::max(y[2], y[3]));
+      int64_t i0, i1, j0, j1;
+      sample_range(xl, xh, x0, W, &i0, &i1);
+      sample_range(yl, yh, y0, H, &j0, &j1);
+      for (int64_t j = j0; j <= j1; ++j)
+        for (int64_t i = i0; i <= i1; ++i)
+          if (quad_covers(x, y, mode, x0 + i + 0.5, y0 + j + 0.5))
+            top[j * W + i] = std::max(top[j * W + i], (int32_t)pp);
+    });
+  }
+}
+
+// The same value for single samples (pixel (pi[k], pj[k]) of the same canvas),
+// each from every quad of every path: for checking a large canvas at a few
+// points.
+void oracle_coverage_at(int n_paths, const int32_t* seg_begin, const int64_t* offsets,
+                        const float* vx, const float* vy, double x0, double y0, int mode,
+                        int n_pts, const int32_t* pi, const int32_t* pj, int32_t* out,
+                        int nthreads) {
+  parallel_paths(n_pts, nthreads, [&](int k) {
+    double px = x0 + pi[k] + 0.5, py = y0 + pj[k] + 0.5;
+    int32_t best = -1;
+    for (int p = n_paths - 1; p >= 0 && best < 0; --p) {
+      for_each_quad(seg_begin, offsets, p, [&](int64_t r, int pp) {
+        if (best >= pp) return;
+        double x[4], y[4];
+        quad_corners(vx, vy, r, x, y);
+        if (px < std::min(std::min(x[0], x[1]), std::min(x[2], x[3])) ||
+            px > std::max(std::max(x[0], x[1]), std::max(x[2], x[3])) ||
+            py < std::min(std::min(y[0], y[1]), std::min(y[2], y[3])) ||
+            py > std::max(std::max(y[0], y[1]), std::max(y[2], y[3])))
+          return;
+        if (quad_covers(x, y, mode, px, py)) best = pp;
+      });
+    }
+    out[k] = best;
+  });
 }
 
 }  // extern "C"

@@ -625,3 +625,120 @@ def test_uniform_ribs_sit_at_uniform_parameters(case):
     ok = speed > 1e-3 * speed.max()          # away from a cusp the normal is defined
     cross = (d[:, 0] * ny - d[:, 1] * nx) / 3.0          # |n| = width, so cross = +1
     np.testing.assert_allclose(cross[ok], 1.0, atol=1e-5)
+
+
+# ------------------------------------------------------------------ coverage
+def _samples(W_, H_, x0=0.0, y0=0.0):
+    i, j = np.meshgrid(np.arange(W_), np.arange(H_))
+    return x0 + i + 0.5, y0 + j + 0.5
+
+
+@pytest.mark.parametrize("join,extra", [(W.JOIN_NONE, 0), (W.JOIN_BEVEL, 6)])
+def test_coverage_of_a_corner(join, extra):
+    # two butt-capped lines meeting at a left turn, width 6, placed so that no
+    # sample centre falls on an edge: the union of the two rectangles (16 x 6
+    # and 6 x 16 samples, 3 x 3 shared = 183), plus for a bevel the 6 samples
+    # of the triangle (20.25, 10.125), (20.25, 7.125), (23.25, 10.125); with no
+    # join nothing bridges the two segments
+    b = W.path([(W.KIND_L, [(4.25, 10.125), (20.25, 10.125)], 1.0),
+                (W.KIND_L, [(20.25, 10.125), (20.25, 26.125)], 1.0)], width=6.0, join=join, cap=W.CAP_BUTT)
+    o = oracle.stroke(b)
+    top = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, 32, 32)
+    x, y = _samples(32, 32)
+    r1 = (x > 4.25) & (x < 20.25) & (y > 7.125) & (y < 13.125)
+    r2 = (x > 17.25) & (x < 23.25) & (y > 10.125) & (y < 26.125)
+    bevel = (x > 20.25) & (y < 10.125) & (x - y < 13.125)
+    want = r1 | r2 | (bevel if extra else False)
+    assert int(want.sum()) == 183 + extra
+    np.testing.assert_array_equal(top == 0, want)
+    assert np.all(top[~want] == -1)
+
+
+def _one_quad_path(N0, P0, P1, N1):
+    # a butt-capped line whose two ribs are replaced by the given ones
+    b = W.path([(W.KIND_L, [(0, 0), (1, 0)], 1.0)], width=2.0, cap=W.CAP_BUTT)
+    off = np.array([0, 0, 2, 2], np.int64)
+    vx = np.array([N0[0], P0[0], N1[0], P1[0]], np.float32)
+    vy = np.array([N0[1], P0[1], N1[1], P1[1]], np.float32)
+    return b, off, vx, vy
+
+
+def test_coverage_of_a_bow_tie_quad():
+    # ribs N0 P0 and N1 P1 that cross: the edges N0 P0 and P1 N1 meet at
+    # X = (4.25, 4.125); the quad covers the two lobes (N1, N0, X) and
+    # (P0, P1, X) -- 20 + 12 samples, counted by hand -- and the triangle
+    # split (N0, P0, P1) + (N0, P1, N1) covers more
+    a, bq, c, d = (0.25, 0.125), (8.25, 8.125), (8.25, 0.125), (0.25, 8.125)
+    b, off, vx, vy = _one_quad_path(a, bq, c, d)
+    x, y = _samples(12, 12)
+    left = (x > 0.25) & (y > x - 0.125) & (y < 8.375 - x)
+    right = (x < 8.25) & (y < x - 0.125) & (y > 8.375 - x)
+    assert int(left.sum()) == 20 and int(right.sum()) == 12
+    top = oracle.coverage(b, off, vx, vy, 0.0, 0.0, 12, 12, oracle.COVER_QUAD)
+    np.testing.assert_array_equal(top == 0, left | right)
+    t1 = (y > 0.125) & (y < x - 0.125) & (x < 8.25)
+    t2 = (x > 0.25) & (y > 0.125) & (x + y < 8.375)
+    top = oracle.coverage(b, off, vx, vy, 0.0, 0.0, 12, 12, oracle.COVER_TRIANGLES)
+    np.testing.assert_array_equal(top == 0, t1 | t2)
+    assert int((t1 | t2).sum()) > int((left | right).sum())
+
+
+def test_coverage_of_a_ring_is_between_two_regular_polygons():
+    # a closed circle of four conic quarters (radius 40 around (64, 64), width
+    # 12, q = 5.625 deg: 16 steps a quarter) covers exactly the samples inside
+    # the regular 64-gon of circumradius 46 and outside that of circumradius 34
+    # (vertices at multiples of 5.625 deg)
+    C, R, r = 64.0, 40.0, 6.0
+    k = math.cos(math.pi / 4)
+    quarter = [[(C + R, C), (C + R, C + R), (C, C + R)], [(C, C + R), (C - R, C + R), (C - R, C)],
+               [(C - R, C), (C - R, C - R), (C, C - R)], [(C, C - R), (C + R, C - R), (C + R, C)]]
+    b = W.path([(W.KIND_K, pts, k) for pts in quarter], width=2 * r, q=math.pi / 32,
+               join=W.JOIN_ROUND, cap=W.CAP_ROUND, closed=True)
+    o = oracle.stroke(b)
+    top = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, 128, 128)
+    x, y = _samples(128, 128)
+    d, phi = np.hypot(x - C, y - C), np.arctan2(y - C, x - C) % (2 * math.pi)
+    step = math.pi / 32
+    mid = (np.floor(phi / step) + 0.5) * step
+    h = d * np.cos(phi - mid)                       # distance towards the sector's edge
+    outer, inner = (R + r) * math.cos(step / 2), (R - r) * math.cos(step / 2)
+    clear = (np.abs(h - outer) > 1e-4) & (np.abs(h - inner) > 1e-4)
+    want = (h < outer) & (h > inner)
+    assert clear.sum() > 128 * 128 - 50
+    np.testing.assert_array_equal((top == 0)[clear], want[clear])
+
+
+def test_coverage_converges_to_the_support_predicate():
+    # round caps: the stroked region is every point within w/2 of the curve;
+    # the samples on which the tessellated coverage disagrees with it shrink
+    # as q does
+    from scipy.spatial import cKDTree
+    for kind, pts, w in TINY[:3] + TINY[7:8] + TINY[-2:-1]:
+        P = np.asarray(pts, np.float64) * 12 + 20
+        dense = G.point(kind, P, np.linspace(0, 1, 200_001), w)
+        x, y = _samples(160, 160)
+        # distances beyond 8 come back as inf (outside either way)
+        dist = cKDTree(dense).query(np.column_stack([x.ravel(), y.ravel()]),
+                                    distance_upper_bound=8.0)[0].reshape(x.shape)
+        wrong = []
+        for q in (math.pi / 8, math.pi / 32, math.pi / 128):
+            b = W.single(kind, [tuple(p) for p in P], w=w, width=10.0, q=q, cap=W.CAP_ROUND)
+            o = oracle.stroke(b)
+            top = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, 160, 160)
+            sure = np.abs(dist - 5.0) > 2e-3
+            wrong.append(int(((top == 0) != (dist < 5.0))[sure].sum()))
+        inside = int((dist < 5.0).sum())
+        assert wrong[2] <= wrong[1] <= wrong[0], (kind, wrong)
+        assert wrong[2] <= 0.002 * inside + 2, (kind, wrong, inside)
+
+
+def test_coverage_at_agrees_with_the_canvas():
+    b = W.random_mixed(11, n_paths=12, max_segs=6, extent=96.0)
+    o = oracle.stroke(b)
+    vx, vy = o["vx"].astype(np.float32), o["vy"].astype(np.float32)
+    for mode in (oracle.COVER_QUAD, oracle.COVER_TRIANGLES):
+        top = oracle.coverage(b, o["offsets"], vx, vy, -8.0, -4.0, 120, 110, mode)
+        rng = np.random.default_rng(3)
+        pi, pj = rng.integers(0, 120, 400), rng.integers(0, 110, 400)
+        got = oracle.coverage_at(b, o["offsets"], vx, vy, -8.0, -4.0, pi, pj, mode)
+        np.testing.assert_array_equal(got, top[pj, pi])
