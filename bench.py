@@ -78,7 +78,7 @@ def main() -> int:
                          "instead of the plan's autotuning, e.g. for profiles of one mapping")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit", "c1", "facets"], default=None,
+    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit", "c1", "facets", "coverage"], default=None,
                     help="secondary measurements: the near-degenerate precision study, the long "
                          "dashed path, or the stress configuration at q in {pi/16, pi/64, pi/256}")
     args = ap.parse_args()
@@ -499,8 +499,58 @@ def study_facets(args, torch, ps, W, dev):
     return 0
 
 
+def study_coverage(args, torch, ps, W, dev):
+    """Coverage of the 4096-path batch's quad strip on a 4096 x 4096 canvas
+    (one sample per pixel centre), quads as quads (winding number, bow-ties as
+    two lobes) and as the triangle pairs a triangle rasterizer draws: time per
+    pass, covered samples, and the algorithmic work -- the summed area of the
+    quads in px^2, about one winding test per covered (quad, sample) pair."""
+    b = W.config2()
+    db = ps.DeviceBatch(b, device=dev)
+    out = ps.stroke(db, b.q)
+    R = out["total_ribs"]
+    vx, vy, off = out["vx"][:2 * R], out["vy"][:2 * R], out["offsets"]
+    # area of the quads between ribs of one link (bridges between links are
+    # zero-area), by the shoelace formula on the N_r P_r P_{r+1} N_{r+1} loop
+    link = torch.searchsorted(off, torch.arange(R, device=dev), right=True) - 1
+    same = link[:-1] == link[1:]
+    ax, ay, bx, by = vx[0::2].double(), vy[0::2].double(), vx[1::2].double(), vy[1::2].double()
+    sh = (ax[:-1] * by[:-1] - bx[:-1] * ay[:-1]) + (bx[:-1] * by[1:] - bx[1:] * by[:-1]) \
+        + (bx[1:] * ay[1:] - ax[1:] * by[1:]) + (ax[1:] * ay[:-1] - ax[:-1] * ay[1:])
+    area = float((0.5 * sh.abs() * same).sum())
+    del link, same, ax, ay, bx, by, sh
+    top = torch.empty((4096, 4096), dtype=torch.int32, device=dev)
+    rows = []
+    covered = {}
+    for mode, name in ((ps.PS_COVER_QUAD, "quads"), (ps.PS_COVER_TRIANGLES, "triangles")):
+        for _ in range(2):
+            ps.ps_coverage(db, off, vx, vy, R, top, 0.0, 0.0, mode)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ps.ps_coverage(db, off, vx, vy, R, top, 0.0, 0.0, mode)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        covered[name] = top >= 0
+        # 4 edges x 7 FP64 operations per winding test (3 edges twice for triangles)
+        ops = area * (28 if mode == ps.PS_COVER_QUAD else 42)
+        row = {"mode": name, "ms": ms, "covered_samples": int(covered[name].sum()),
+               "quad_area_px2": area, "samples_per_s": area / (ms * 1e-3),
+               "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": 78.6,
+                            "unit": "TFLOP/s (fp64)", "frac": ops / (ms * 1e-3) / 1e12 / 78.6}}
+        rows.append(row)
+        log(str(row))
+    excess = int((covered["triangles"] & ~covered["quads"]).sum())
+    print(json.dumps({"study": "coverage", "workload": "4096-path batch, 4096 x 4096 canvas, 1 sample/px",
+                      "ribs": R, "rows": rows, "triangle_excess_samples": excess}), flush=True)
+    return 0
+
+
 STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5, "emit": study_emit, "c1": study_c1,
-           "facets": study_facets}
+           "facets": study_facets, "coverage": study_coverage}
 
 
 if __name__ == "__main__":

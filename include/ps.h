@@ -233,6 +233,39 @@ int ps_emit_uniform(const ps_batch* batch, const ps_params* params, const int64_
 int ps_facet_stats(const ps_batch* batch, const int64_t* offsets, const float* vx,
                    const float* vy, double* stats, void* stream);
 
+/* Coverage modes of ps_coverage. */
+enum {
+  PS_COVER_QUAD = 0,       /* a quad covers where its winding number is nonzero     */
+  PS_COVER_TRIANGLES = 1   /* the two triangles a triangle rasterizer would draw    */
+};
+
+typedef struct {
+  double x0, y0;           /* world position of the corner of pixel (0, 0)          */
+  int32_t width, height;   /* pixels; pixel (i, j) samples (x0+i+1/2, y0+j+1/2)      */
+  int32_t mode;            /* PS_COVER_*                                             */
+} ps_canvas;
+
+/*
+ * ps_coverage -- which path covers each pixel sample (Sec. "Stroked Paths
+ * Tessellated to Quad Strips"; the support predicate, Eq.
+ * polar-stroking-predicate, evaluated on the tessellation).  The quads of a
+ * path are its consecutive ribs within a link, plus the quad from a link's
+ * last rib to the next link's first rib unless both links are segments (then
+ * no join ribs lie between them and the quad would draw a bevel).  Quad r has
+ * corners N_r, P_r, P_{r+1}, N_{r+1}; in PS_COVER_QUAD it covers a sample
+ * where its winding number is nonzero (edges counted by the half-open
+ * crossing rule, in FP64 on the FP32 vertices), so a bow-tie quad covers its
+ * two lobes; PS_COVER_TRIANGLES covers the union of triangles (N_r, P_r,
+ * P_{r+1}) and (N_r, P_{r+1}, N_{r+1}) instead, which is what splitting the
+ * quad for a triangle rasterizer draws.  top: DEVICE int32 [height * width],
+ * row-major, overwritten with the largest covering path index, or -1 (a
+ * renderer drawing opaque strokes in path order shows that path there).
+ * vx, vy [2 * n_ribs] and offsets as written by ps_emit or ps_emit_uniform;
+ * ribs beyond offsets[n_links] are ignored.  Needs no workspace.
+ */
+int ps_coverage(const ps_batch* batch, const int64_t* offsets, const float* vx, const float* vy,
+                int64_t n_ribs, const ps_canvas* canvas, int32_t* top, void* stream);
+
 /*
  * ps_dash -- dashing by arc length (Sec. "Dashing").  Reads the rib stream of
  * ps_emit (vx, vy, vs of vertex_capacity entries, the capacity the workspace

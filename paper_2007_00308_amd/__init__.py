@@ -39,6 +39,14 @@ class ps_params(ctypes.Structure):
                 ("dash", _vp), ("dash_phase", ctypes.c_double), ("miter_limit", ctypes.c_double)]
 
 
+PS_COVER_QUAD, PS_COVER_TRIANGLES = 0, 1
+
+
+class ps_canvas(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
 class ps_status(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("total_ribs", ctypes.c_int64), ("fixups", ctypes.c_int64),
@@ -87,6 +95,7 @@ def load(path: str = LIB_PATH):
         "ps_emit_uniform": (ctypes.c_int, [P(ps_batch), P(ps_params), _vp, _vp, _vp, ctypes.c_int64, _vp,
                                            ctypes.c_size_t, _vp]),
         "ps_facet_stats": (ctypes.c_int, [P(ps_batch), _vp, _vp, _vp, _vp, _vp]),
+        "ps_coverage": (ctypes.c_int, [P(ps_batch), _vp, _vp, _vp, ctypes.c_int64, P(ps_canvas), _vp, _vp]),
         "ps_last_error": (ctypes.c_char_p, []),
         "ps_version": (ctypes.c_char_p, []),
     }
@@ -194,6 +203,15 @@ def ps_emit_uniform(db, params, offsets, vx, vy, vertex_capacity, ws, stream=Non
 def ps_facet_stats(db, offsets, vx, vy, stats, stream=None):
     _check(load().ps_facet_stats(ctypes.byref(db.struct), _ptr(offsets), _ptr(vx), _ptr(vy), _ptr(stats),
                                  _stream(stream)), "ps_facet_stats")
+
+
+def ps_coverage(db, offsets, vx, vy, n_ribs, top, x0=0.0, y0=0.0, mode=PS_COVER_QUAD, stream=None):
+    """top: int32 device tensor [height, width], overwritten with the topmost
+    covering path index per pixel sample (-1 for none)."""
+    H, W = top.shape
+    cv = ps_canvas(float(x0), float(y0), int(W), int(H), int(mode))
+    _check(load().ps_coverage(ctypes.byref(db.struct), _ptr(offsets), _ptr(vx), _ptr(vy), int(n_ribs),
+                              ctypes.byref(cv), _ptr(top), _stream(stream)), "ps_coverage")
 
 
 def ps_arclen(db, params, offsets, vs, vertex_capacity, ws, stream=None):

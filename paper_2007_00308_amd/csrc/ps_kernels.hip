@@ -1449,6 +1449,190 @@ __global__ void __launch_bounds__(256) facet_stats_kernel(const int32_t* seg_beg
 }
 
 // ===========================================================================
+// Coverage of the quad strip (Sec. "Stroked Paths Tessellated to Quad Strips")
+// ===========================================================================
+struct CovArgs {
+  const int64_t* off;        // link offsets [n_links+1]
+  int64_t n_links;
+  const int32_t* seg_begin;
+  int n_paths;
+  const float* vx;           // [2 * n_ribs], N then P per rib
+  const float* vy;
+  int64_t n_ribs;
+  double x0, y0;             // corner of pixel (0,0); its sample at (x0+1/2, y0+1/2)
+  int W, H;
+  int32_t* top;              // [H*W] topmost covering path, -1 for none
+};
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// The link holding rib r: the largest l with off[l] <= r (empty links share
+// their offset with the next link, so this is the one that has ribs).
+__device__ int64_t link_of_rib(const int64_t* off, int64_t n_links, int64_t r) {
+  int64_t a = 0, b = n_links - 1;
+  while (a < b) {
+    const int64_t m = (a + b + 1) >> 1;
+    if (off[m] <= r) a = m; else b = m - 1;
+  }
+  return a;
+}
+
+// The path owning link slot l: the largest p with 2*seg_begin[p] + p <= l.
+__device__ int path_of_link(const int32_t* seg_begin, int n_paths, int64_t l) {
+  int a = 0, b = n_paths - 1;
+  while (a < b) {
+    const int m = (a + b + 1) >> 1;
+    if (2 * (int64_t)seg_begin[m] + m <= l) a = m; else b = m - 1;
+  }
+  return a;
+}
+
+// Sample index range [k0, k1] (sample k at o + k + 1/2, 0 <= k < n) of the
+// samples in [lo - 1, hi + 1]; empty (k1 < k0) unless lo and hi are finite.
+__device__ __forceinline__ void cov_range(double lo, double hi, double o, int n, int& k0, int& k1) {
+  k0 = 0; k1 = -1;
+  if (!(lo <= hi) || !isfinite(lo) || !isfinite(hi)) return;
+  const double a = fmax(ceil(lo - o - 0.5) - 1.0, 0.0);
+  const double b = fmin(floor(hi - o - 0.5) + 1.0, (double)n - 1.0);
+  if (a <= b) { k0 = (int)a; k1 = (int)b; }
+}
+
+#pragma clang fp contract(off)
+// Winding-number contribution of edge u -> v about (px, py): +1 going up with
+// the point strictly left of it, -1 going down with the point strictly right;
+// an edge goes up when it starts at or below py and ends above it.
+__device__ __forceinline__ int cov_edge(double ux, double uy, double vx, double vy, double px, double py) {
+  const double side = (vx - ux) * (py - uy) - (px - ux) * (vy - uy);
+  if (uy <= py) return (vy > py && side > 0) ? 1 : 0;
+  return (vy <= py && side < 0) ? -1 : 0;
+}
+
+// Quad a = N_r, b = P_r, c = P_{r+1}, d = N_{r+1}: MODE 0 covers where its
+// winding number is nonzero (a bow-tie as its two lobes); MODE 1 where either
+// triangle (a, b, c) or (a, c, d) does, as a triangle rasterizer would.
+template <int MODE>
+__device__ __forceinline__ bool cov_test(const double* x, const double* y, double px, double py) {
+  if (MODE == 0) {
+    const int wn = cov_edge(x[0], y[0], x[1], y[1], px, py) + cov_edge(x[1], y[1], x[2], y[2], px, py) +
+                   cov_edge(x[2], y[2], x[3], y[3], px, py) + cov_edge(x[3], y[3], x[0], y[0], px, py);
+    return wn != 0;
+  }
+  const int w1 = cov_edge(x[0], y[0], x[1], y[1], px, py) + cov_edge(x[1], y[1], x[2], y[2], px, py) +
+                 cov_edge(x[2], y[2], x[0], y[0], px, py);
+  const int w2 = cov_edge(x[0], y[0], x[2], y[2], px, py) + cov_edge(x[2], y[2], x[3], y[3], px, py) +
+                 cov_edge(x[3], y[3], x[0], y[0], px, py);
+  return w1 != 0 || w2 != 0;
+}
+
+// x where edge u -> v crosses the horizontal line at yc (when it does, by the
+// half-open rule) widens [lo, hi].
+__device__ __forceinline__ void cov_cross(double ux, double uy, double vx, double vy, double yc,
+                                          double& lo, double& hi) {
+  if ((uy <= yc) != (vy <= yc)) {
+    const double xc = ux + (yc - uy) * (vx - ux) / (vy - uy);
+    lo = fmin(lo, xc); hi = fmax(hi, xc);
+  }
+}
+#pragma clang fp contract(on)
+
+// Smallest lane whose inclusive prefix exceeds k (every lane's prefix is in v).
+__device__ __forceinline__ int cov_owner(int v, int k) {
+  int a = 0, b = 63;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int m = (a + b) >> 1;
+    if (__shfl(v, m, 64) > k) b = m; else a = m + 1;
+  }
+  return a;
+}
+
+// One wavefront per 64 consecutive quads, taken from the end of the rib
+// stream so that later paths land first and most samples need no atomic.
+// Rows of the 64 quads are spread over the lanes by a prefix sum, then the
+// samples of 64 rows the same way; each sample takes the exact winding test,
+// so covered samples match a per-sample evaluation bit for bit.
+template <int MODE>
+__global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t R = min(A.n_ribs, A.off[A.n_links]);
+  const int64_t Q = R - 1;                      // quads r = 0 .. R-2
+  const int64_t waves = (Q + 63) / 64;
+  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < waves; w += wstride) {
+    const int64_t r = Q - 1 - (w * 64 + lane);
+    double x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
+    int p = -1, j0 = 0, nrows = 0;
+    if (r >= 0) {
+      const int64_t l = link_of_rib(A.off, A.n_links, r), l2 = link_of_rib(A.off, A.n_links, r + 1);
+      const int pa = path_of_link(A.seg_begin, A.n_paths, l), pb = path_of_link(A.seg_begin, A.n_paths, l2);
+      const int64_t f = 2 * (int64_t)A.seg_begin[pa] + pa;
+      const bool seg_a = ((l - f) & 1) == 1, seg_b = ((l2 - f) & 1) == 1;
+      if (pa == pb && (l == l2 || !(seg_a && seg_b))) {
+        const float2 ax = *reinterpret_cast<const float2*>(A.vx + 2 * r);
+        const float2 ay = *reinterpret_cast<const float2*>(A.vy + 2 * r);
+        const float2 bx = *reinterpret_cast<const float2*>(A.vx + 2 * r + 2);
+        const float2 by = *reinterpret_cast<const float2*>(A.vy + 2 * r + 2);
+        x[0] = ax.x; y[0] = ay.x; x[1] = ax.y; y[1] = ay.y;   // N_r, P_r
+        x[2] = bx.y; y[2] = by.y; x[3] = bx.x; y[3] = by.x;   // P_{r+1}, N_{r+1}
+        const double yl = fmin(fmin(y[0], y[1]), fmin(y[2], y[3]));
+        const double yh = fmax(fmax(y[0], y[1]), fmax(y[2], y[3]));
+        const double xl = fmin(fmin(x[0], x[1]), fmin(x[2], x[3]));
+        const double xh = fmax(fmax(x[0], x[1]), fmax(x[2], x[3]));
+        int i0, i1, j1;
+        cov_range(xl, xh, A.x0, A.W, i0, i1);
+        cov_range(yl, yh, A.y0, A.H, j0, j1);
+        if (i1 >= i0 && j1 >= j0) { p = pa; nrows = j1 - j0 + 1; }
+      }
+    }
+    const int incl = wave_incl_scan(nrows);
+    const int total = __shfl(incl, 63, 64);
+    for (int base = 0; base < total; base += 64) {
+      // this lane's row: row k of the wave's rows
+      const int k = base + lane;
+      const int o = cov_owner(incl, k);
+      double qx[4], qy[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { qx[c] = __shfl(x[c], o, 64); qy[c] = __shfl(y[c], o, 64); }
+      const int qp = __shfl(p, o, 64);
+      const int j = __shfl(j0, o, 64) + (k - (__shfl(incl, o, 64) - __shfl(nrows, o, 64)));
+      int i0 = 0, ns = 0;
+      if (k < total) {
+        const double yc = A.y0 + j + 0.5;
+        double lo = INFINITY, hi = -INFINITY;
+        cov_cross(qx[0], qy[0], qx[1], qy[1], yc, lo, hi);
+        cov_cross(qx[1], qy[1], qx[2], qy[2], yc, lo, hi);
+        cov_cross(qx[2], qy[2], qx[3], qy[3], yc, lo, hi);
+        cov_cross(qx[3], qy[3], qx[0], qy[0], yc, lo, hi);
+        cov_cross(qx[0], qy[0], qx[2], qy[2], yc, lo, hi);   // the triangles' shared diagonal
+        int i1;
+        cov_range(lo, hi, A.x0, A.W, i0, i1);
+        ns = i1 >= i0 ? i1 - i0 + 1 : 0;
+      }
+      const int incl2 = wave_incl_scan(ns);
+      const int total2 = __shfl(incl2, 63, 64);
+      for (int base2 = 0; base2 < total2; base2 += 64) {
+        const int k2 = base2 + lane;
+        const int o2 = cov_owner(incl2, k2);
+        double sx[4], sy[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { sx[c] = __shfl(qx[c], o2, 64); sy[c] = __shfl(qy[c], o2, 64); }
+        const int sp = __shfl(qp, o2, 64), sj = __shfl(j, o2, 64);
+        const int si = __shfl(i0, o2, 64) + (k2 - (__shfl(incl2, o2, 64) - __shfl(ns, o2, 64)));
+        if (k2 < total2 && cov_test<MODE>(sx, sy, A.x0 + si + 0.5, A.y0 + sj + 0.5)) {
+          int32_t* t = A.top + (int64_t)sj * A.W + si;
+          // values only grow, so a stale read costs at most a redundant atomic
+          if (*t < sp) atomicMax(t, sp);
+        }
+      }
+    }
+  }
+}
+
+// ===========================================================================
 // Dash (Sec. "Dashing")
 // ===========================================================================
 struct DashArgs {
@@ -2067,6 +2251,34 @@ int ps_facet_stats(const ps_batch* b, const int64_t* offsets, const float* vx, c
   if (b->n_segs > 0)
     hipLaunchKernelGGL(facet_stats_kernel, dim3(grid_for(b->n_segs, 256)), dim3(256), 0, s,
                        b->seg_begin, b->n_paths, b->n_segs, offsets, vx, vy, stats);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
+int ps_coverage(const ps_batch* b, const int64_t* offsets, const float* vx, const float* vy,
+                int64_t n_ribs, const ps_canvas* cv, int32_t* top, void* stream) {
+  int rc;
+  if ((rc = check_batch(b))) return rc;
+  if (!cv) return fail(PS_E_ARG, "canvas is NULL");
+  if (cv->width < 0 || cv->height < 0) return fail(PS_E_ARG, "negative canvas size");
+  if (!std::isfinite(cv->x0) || !std::isfinite(cv->y0)) return fail(PS_E_ARG, "canvas origin not finite");
+  if (cv->mode != PS_COVER_QUAD && cv->mode != PS_COVER_TRIANGLES)
+    return fail(PS_E_ARG, "unknown coverage mode %d", cv->mode);
+  if (n_ribs < 0) return fail(PS_E_ARG, "negative rib count");
+  const int64_t npix = (int64_t)cv->width * cv->height;
+  if (npix == 0) return PS_OK;
+  if (!offsets || !top || (n_ribs > 0 && (!vx || !vy))) return fail(PS_E_ARG, "NULL array");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(npix, 256)), dim3(256), 0, s, top, npix, -1);
+  if (n_ribs > 1 && n_links_of(b) > 0) {
+    CovArgs a{offsets, n_links_of(b), b->seg_begin, b->n_paths, vx, vy, n_ribs, cv->x0, cv->y0,
+              cv->width, cv->height, top};
+    const int blocks = grid_for((n_ribs - 1 + 63) / 64, 4);
+    if (cv->mode == PS_COVER_QUAD)
+      hipLaunchKernelGGL(coverage_kernel<0>, dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(coverage_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
+  }
   PS_HIP(hipGetLastError());
   return PS_OK;
 }

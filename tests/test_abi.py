@@ -115,3 +115,25 @@ def test_plan_rejects_null_buffers():
     assert rc == ps.PS_E_ARG and not h.value
     assert lib.ps_plan_launch(None, None) == ps.PS_E_ARG
     assert lib.ps_plan_destroy(None) == ps.PS_OK
+
+
+@pytest.mark.parametrize("canvas,what", [(None, b"canvas is NULL"),
+                                         ((0.0, 0.0, -1, 4, 0), b"negative canvas"),
+                                         ((float("nan"), 0.0, 4, 4, 0), b"origin"),
+                                         ((0.0, 0.0, 4, 4, 2), b"mode")])
+def test_coverage_rejects_bad_canvas(canvas, what):
+    lib = ps.load()
+    b = _batch()
+    cv = None if canvas is None else ctypes.byref(ps.ps_canvas(*canvas))
+    rc = lib.ps_coverage(ctypes.byref(b), 0x1000, 0x1000, 0x1000, 4, cv, 0x1000, None)
+    assert rc == ps.PS_E_ARG
+    assert what in lib.ps_last_error()
+
+
+def test_coverage_of_an_empty_canvas_is_a_no_op():
+    # nothing to write, so no device call is made
+    lib = ps.load()
+    b = _batch()
+    for w, h in ((0, 5), (5, 0)):
+        assert lib.ps_coverage(ctypes.byref(b), None, None, None, 0,
+                               ctypes.byref(ps.ps_canvas(0.0, 0.0, w, h, 0)), None, None) == ps.PS_OK

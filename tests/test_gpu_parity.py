@@ -388,3 +388,92 @@ def test_facet_stats_match_oracle():
     ps.ps_facet_stats(db, out["offsets"], out["vx"], out["vy"], stats)
     torch.cuda.synchronize()
     assert oracle.stats_from_sums(_np(stats))["max_deg"] < 2 * 4.0 + 0.05
+
+
+# ------------------------------------------------------------------ coverage
+def _cover_gpu(b, o, x0, y0, Wd, Hd, mode):
+    """ps_coverage on the oracle's own rib stream (uploaded as FP32)."""
+    import torch
+    db = ps.DeviceBatch(b)
+    vx = torch.from_numpy(o["vx"].astype(np.float32)).cuda()
+    vy = torch.from_numpy(o["vy"].astype(np.float32)).cuda()
+    off = torch.from_numpy(np.ascontiguousarray(o["offsets"], np.int64)).cuda()
+    top = torch.empty((Hd, Wd), dtype=torch.int32, device="cuda")
+    ps.ps_coverage(db, off, vx, vy, vx.numel() // 2, top, x0, y0, mode)
+    torch.cuda.synchronize()
+    return _np(top)
+
+
+def _tight_turns(seed, n=40, q=math.pi / 8, cap=W.CAP_BUTT):
+    # small cubics stroked 30-60 wide, bending tighter than the half width:
+    # bow-tie quads (butt caps leave the triangle split's excess visible)
+    rng = np.random.default_rng(seed)
+    segs = []
+    for _ in range(n):
+        c = rng.uniform(30, 220, 2)
+        pts = [tuple(np.round((c + rng.uniform(-12, 12, 2)) * 64) / 64) for _ in range(4)]
+        segs.append([(W.KIND_C, pts, 1.0)])
+    return W.paths(segs, widths=list(rng.uniform(30, 60, n)), q=q, caps=[cap] * n, joins=[W.JOIN_ROUND] * n)
+
+
+@pytest.mark.parametrize("mode", [ps.PS_COVER_QUAD, ps.PS_COVER_TRIANGLES])
+@pytest.mark.parametrize("case", ["mixed", "styles", "config1", "tight", "closed"])
+def test_coverage_matches_oracle(case, mode):
+    if case == "mixed":
+        b, frame = W.random_mixed(61, n_paths=40, max_segs=10, extent=300.0), (-20.0, -10.0, 333, 301)
+    elif case == "styles":
+        b = W.random_mixed(62, n_paths=30, max_segs=8, extent=256.0, join=W.JOIN_NONE, cap=W.CAP_SQUARE)
+        frame = (0.0, 0.0, 256, 200)
+    elif case == "config1":
+        b, frame = W.config1(), (-16.5, -16.25, 97, 83)
+    elif case == "tight":
+        b, frame = _tight_turns(63), (0.0, 0.0, 257, 255)
+    else:
+        b = W.random_mixed(64, n_paths=30, max_segs=7, extent=200.0, join=W.JOIN_MITER, cap=W.CAP_ROUND)
+        closed = np.ones(b.n_paths, np.uint8)
+        for p in range(b.n_paths):
+            s0, s1 = int(b.seg_begin[p]), int(b.seg_begin[p + 1]) - 1
+            n = W.NPTS[int(b.kind[s1])]
+            b.cx[n - 1, s1], b.cy[n - 1, s1] = b.cx[0, s0], b.cy[0, s0]
+        b.closed = closed
+        frame = (-5.0, -5.0, 215, 215)
+    o = oracle.stroke(b)
+    ref = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], *frame, mode)
+    got = _cover_gpu(b, o, *frame, mode)
+    assert (ref >= 0).sum() > 500
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_coverage_bow_ties_differ_from_triangles():
+    b = _tight_turns(65)
+    o = oracle.stroke(b)
+    quad = _cover_gpu(b, o, 0.0, 0.0, 256, 256, ps.PS_COVER_QUAD)
+    tri = _cover_gpu(b, o, 0.0, 0.0, 256, 256, ps.PS_COVER_TRIANGLES)
+    assert np.array_equal(quad, oracle.coverage(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, 256, 256))
+    # the triangle split covers where the bow-ties leave gaps
+    assert (tri >= 0).sum() > (quad >= 0).sum()
+
+
+def test_coverage_edge_cases():
+    b = W.random_mixed(66, n_paths=5, max_segs=4, extent=100.0)
+    o = oracle.stroke(b)
+    # a canvas away from every stroke, a one-pixel canvas, a one-row canvas
+    for frame in ((5000.0, 5000.0, 40, 30), (50.25, 50.25, 1, 1), (0.0, 49.0, 150, 1)):
+        got = _cover_gpu(b, o, *frame, ps.PS_COVER_QUAD)
+        np.testing.assert_array_equal(got, oracle.coverage(b, o["offsets"], o["vx"], o["vy"], *frame))
+    # an empty batch: nothing covered
+    e = W.paths([], widths=[])
+    oe = dict(vx=np.zeros(0), vy=np.zeros(0), offsets=np.zeros(1, np.int64))
+    assert np.all(_cover_gpu(e, oe, 0.0, 0.0, 16, 8, ps.PS_COVER_QUAD) == -1)
+
+
+def test_coverage_full_batch_sampled():
+    # the 4096-path batch on a 4096 x 4096 canvas, checked at sampled pixels
+    b = W.config2()
+    o = oracle.stroke(b)
+    got = _cover_gpu(b, o, 0.0, 0.0, 4096, 4096, ps.PS_COVER_QUAD)
+    rng = np.random.default_rng(7)
+    pi, pj = rng.integers(0, 4096, 384), rng.integers(0, 4096, 384)
+    ref = oracle.coverage_at(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, pi, pj)
+    np.testing.assert_array_equal(got[pj, pi], ref)
+    assert (ref >= 0).mean() > 0.5

@@ -742,3 +742,24 @@ def test_coverage_at_agrees_with_the_canvas():
         pi, pj = rng.integers(0, 120, 400), rng.integers(0, 110, 400)
         got = oracle.coverage_at(b, o["offsets"], vx, vy, -8.0, -4.0, pi, pj, mode)
         np.testing.assert_array_equal(got, top[pj, pi])
+
+
+def test_triangle_split_excess_shrinks_with_q():
+    # a quad's winding number is the sum of its two triangles', so the split
+    # covers every sample the quad does; what it adds at bow-ties shrinks as q
+    # does (Sec. "Limitations"), on small cubics stroked wider than they bend
+    rng = np.random.default_rng(65)
+    segs, widths = [], []
+    for _ in range(30):
+        c = rng.uniform(30, 220, 2)
+        segs.append([(W.KIND_C, [tuple(np.round((c + rng.uniform(-12, 12, 2)) * 64) / 64) for _ in range(4)], 1.0)])
+        widths.append(float(rng.uniform(30, 60)))
+    excess = []
+    for q in (math.pi / 4, math.pi / 16, math.pi / 64):
+        b = W.paths(segs, widths=widths, q=q, caps=[W.CAP_BUTT] * 30, joins=[W.JOIN_ROUND] * 30)
+        o = oracle.stroke(b)
+        quad = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, 256, 256, oracle.COVER_QUAD)
+        tri = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, 256, 256, oracle.COVER_TRIANGLES)
+        assert not np.any((quad >= 0) & (tri < 0))
+        excess.append(int(((tri >= 0) & (quad < 0)).sum()))
+    assert excess[0] > excess[1] > excess[2] and excess[0] > 100, excess
