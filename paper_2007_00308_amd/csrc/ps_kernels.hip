@@ -1502,42 +1502,106 @@ __device__ __forceinline__ void cov_range(double lo, double hi, double o, int n,
 }
 
 #pragma clang fp contract(off)
-// Winding-number contribution of edge u -> v about (px, py): +1 going up with
-// the point strictly left of it, -1 going down with the point strictly right;
-// an edge goes up when it starts at or below py and ends above it.
-__device__ __forceinline__ int cov_edge(double ux, double uy, double vx, double vy, double px, double py) {
-  const double side = (vx - ux) * (py - uy) - (px - ux) * (vy - uy);
-  if (uy <= py) return (vy > py && side > 0) ? 1 : 0;
-  return (vy <= py && side < 0) ? -1 : 0;
+// One edge u -> v of a quad, seen from the sample row at height py.  It counts
+// in the winding number when it crosses the row by the half-open rule (starts
+// at or below py and ends above it, or the reverse); then its contribution at
+// a sample px is dir (+1 going up, -1 going down) when
+//   side = (vx - ux) * (py - uy) - (px - ux) * (vy - uy)
+// is > 0 (up) or < 0 (down).  side is monotone in px with the sign of -dir,
+// also in rounded FP64, so along the row the edge contributes for the samples
+// below one flip index and not from it on.
+struct CovEdge {
+  double ux, dx, dy, t1;  // t1 = (vx - ux) * (py - uy)
+  float xc;               // where it crosses the row (FP32 estimate)
+  int dir;                // 0: does not cross the row
+};
+
+__device__ __forceinline__ CovEdge cov_edge(float ux, float uy, float vx, float vy, double py) {
+  CovEdge e;
+  e.ux = ux; e.dx = (double)vx - (double)ux; e.dy = (double)vy - (double)uy;
+  e.t1 = e.dx * (py - (double)uy);
+  e.dir = ((double)uy <= py) == ((double)vy <= py) ? 0 : ((double)uy <= py ? 1 : -1);
+  e.xc = ux + ((float)py - uy) * ((vx - ux) / (vy - uy));
+  return e;
 }
 
-// Quad a = N_r, b = P_r, c = P_{r+1}, d = N_{r+1}: MODE 0 covers where its
-// winding number is nonzero (a bow-tie as its two lobes); MODE 1 where either
-// triangle (a, b, c) or (a, c, d) does, as a triangle rasterizer would.
-template <int MODE>
-__device__ __forceinline__ bool cov_test(const double* x, const double* y, double px, double py) {
-  if (MODE == 0) {
-    const int wn = cov_edge(x[0], y[0], x[1], y[1], px, py) + cov_edge(x[1], y[1], x[2], y[2], px, py) +
-                   cov_edge(x[2], y[2], x[3], y[3], px, py) + cov_edge(x[3], y[3], x[0], y[0], px, py);
-    return wn != 0;
-  }
-  const int w1 = cov_edge(x[0], y[0], x[1], y[1], px, py) + cov_edge(x[1], y[1], x[2], y[2], px, py) +
-                 cov_edge(x[2], y[2], x[0], y[0], px, py);
-  const int w2 = cov_edge(x[0], y[0], x[2], y[2], px, py) + cov_edge(x[2], y[2], x[3], y[3], px, py) +
-                 cov_edge(x[3], y[3], x[0], y[0], px, py);
-  return w1 != 0 || w2 != 0;
+__device__ __forceinline__ bool cov_contrib(const CovEdge& e, double px) {
+  const double side = e.t1 - (px - e.ux) * e.dy;
+  return e.dir > 0 ? side > 0 : side < 0;
 }
 
-// x where edge u -> v crosses the horizontal line at yc (when it does, by the
-// half-open rule) widens [lo, hi].
-__device__ __forceinline__ void cov_cross(double ux, double uy, double vx, double vy, double yc,
-                                          double& lo, double& hi) {
-  if ((uy <= yc) != (vy <= yc)) {
-    const double xc = ux + (yc - uy) * (vx - ux) / (vy - uy);
-    lo = fmin(lo, xc); hi = fmax(hi, xc);
+// The flip index of a crossing edge on a row of W samples (sample k at
+// x0 + k + 1/2): the smallest k in [0, W] from which the edge no longer
+// contributes.  The crossing estimate is corrected by exact tests, with a
+// bisection when it is further off than a few samples.
+__device__ int cov_flip(const CovEdge& e, double x0, int W) {
+  const double g = ceil((double)e.xc - x0 - 0.5);
+  int k = isfinite(g) ? (int)fmin(fmax(g, 0.0), (double)W) : 0;
+  int steps = 0;
+  if (k > 0 && !cov_contrib(e, x0 + (k - 1) + 0.5)) {
+    do { --k; ++steps; } while (k > 0 && steps < 8 && !cov_contrib(e, x0 + (k - 1) + 0.5));
+    if (k > 0 && !cov_contrib(e, x0 + (k - 1) + 0.5)) steps = 99;
+  } else if (k < W && cov_contrib(e, x0 + k + 0.5)) {
+    do { ++k; ++steps; } while (k < W && steps < 8 && cov_contrib(e, x0 + k + 0.5));
+    if (k < W && cov_contrib(e, x0 + k + 0.5)) steps = 99;
   }
+  if (steps == 99 || !isfinite(g)) {
+    int lo = 0, hi = W;
+    while (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (cov_contrib(e, x0 + m + 0.5)) lo = m + 1; else hi = m;
+    }
+    k = lo;
+  }
+  return k;
 }
 #pragma clang fp contract(on)
+
+// Covered sample intervals of one row: the winding number at sample k is the
+// sum of dir over the crossing edges whose flip index exceeds k, constant
+// between sorted flip indices; a quad has 0, 2 or 4 crossing edges, so at most
+// two maximal runs of nonzero winding.  Written as [a1, a1+n1) and [a2, a2+n2).
+__device__ __forceinline__ void cov_add_run(int a, int b, int& a1, int& n1, int& a2, int& n2) {
+  if (b <= a) return;
+  if (n1 == 0) { a1 = a; n1 = b - a; return; }
+  if (a <= a1 + n1 && b >= a1) {              // touches or overlaps the first run
+    const int lo = min(a, a1), hi = max(b, a1 + n1);
+    a1 = lo; n1 = hi - lo;
+    if (n2 > 0 && a2 <= a1 + n1) {            // may now reach the second one
+      const int h2 = max(a1 + n1, a2 + n2);
+      n1 = h2 - a1; n2 = 0;
+    }
+    return;
+  }
+  if (n2 == 0) { a2 = a; n2 = b - a; }
+  else { const int lo = min(a, a2), hi = max(b, a2 + n2); a2 = lo; n2 = hi - lo; }
+  if (a2 < a1) { const int t = a1, u = n1; a1 = a2; n1 = n2; a2 = t; n2 = u; }
+}
+
+template <int N>
+__device__ __forceinline__ void cov_runs(const CovEdge* e, double x0, int W, int& a1, int& n1, int& a2,
+                                         int& n2) {
+  int k[N], d[N], m = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    k[i] = 0; d[i] = 0;
+    if (e[i].dir != 0) { k[i] = cov_flip(e[i], x0, W); d[i] = e[i].dir; ++m; }
+  }
+  // winding just below each flip index: runs between consecutive indices
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (d[i] == 0) continue;
+    int w = 0, nxt = W + 1;
+#pragma unroll
+    for (int t = 0; t < N; ++t)
+      if (d[t] != 0) {
+        if (k[t] > k[i] || (k[t] == k[i] && t > i)) { if (k[t] < nxt) nxt = k[t]; }
+        if (k[t] > k[i]) w += d[t];
+      }
+    if (w != 0 && nxt <= W) cov_add_run(k[i], nxt, a1, n1, a2, n2);
+  }
+  (void)m;
+}
 
 // Smallest lane whose inclusive prefix exceeds k (every lane's prefix is in v).
 __device__ __forceinline__ int cov_owner(int v, int k) {
@@ -1550,21 +1614,44 @@ __device__ __forceinline__ int cov_owner(int v, int k) {
   return a;
 }
 
+// Inclusive sum and max over the wavefront on the DPP paths (rows of 16 lanes,
+// then row broadcasts); lanes outside a step's source read 0, the identity of
+// both (the values here are >= 0).
+__device__ __forceinline__ int dpp_incl_sum(int v) {
+  v += dpp_i32<0x111, 0xf>(v); v += dpp_i32<0x112, 0xf>(v);
+  v += dpp_i32<0x114, 0xf>(v); v += dpp_i32<0x118, 0xf>(v);
+  v += dpp_i32<0x142, 0xa>(v); v += dpp_i32<0x143, 0xc>(v);
+  return v;
+}
+__device__ __forceinline__ int dpp_incl_max(int v) {
+  v = max(v, dpp_i32<0x111, 0xf>(v)); v = max(v, dpp_i32<0x112, 0xf>(v));
+  v = max(v, dpp_i32<0x114, 0xf>(v)); v = max(v, dpp_i32<0x118, 0xf>(v));
+  v = max(v, dpp_i32<0x142, 0xa>(v)); v = max(v, dpp_i32<0x143, 0xc>(v));
+  return v;
+}
+
+constexpr int kCovWaves = 4;   // wavefronts per workgroup
+
 // One wavefront per 64 consecutive quads, taken from the end of the rib
 // stream so that later paths land first and most samples need no atomic.
-// Rows of the 64 quads are spread over the lanes by a prefix sum, then the
-// samples of 64 rows the same way; each sample takes the exact winding test,
-// so covered samples match a per-sample evaluation bit for bit.
+// The rows of the 64 quads are spread over the lanes by a prefix sum; each
+// row lane finds the row's covered samples exactly (the flip index of every
+// crossing edge, by the same FP64 side test a per-sample evaluation makes)
+// as at most two runs.  The samples of 64 rows are then laid end to end and
+// taken 64 at a time: every row marks where its samples start in a per-wave
+// LDS slot array, a max-scan over the marks gives each lane its row, and the
+// lane reads, compares and raises one canvas word.
 template <int MODE>
 __global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
-  const int lane = threadIdx.x & 63;
+  __shared__ int mark[kCovWaves][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t R = min(A.n_ribs, A.off[A.n_links]);
   const int64_t Q = R - 1;                      // quads r = 0 .. R-2
   const int64_t waves = (Q + 63) / 64;
-  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < waves; w += wstride) {
+  const int64_t wstride = (int64_t)gridDim.x * kCovWaves;
+  for (int64_t w = (int64_t)blockIdx.x * kCovWaves + wv; w < waves; w += wstride) {
     const int64_t r = Q - 1 - (w * 64 + lane);
-    double x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
+    float x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
     int p = -1, j0 = 0, nrows = 0;
     if (r >= 0) {
       const int64_t l = link_of_rib(A.off, A.n_links, r), l2 = link_of_rib(A.off, A.n_links, r + 1);
@@ -1588,45 +1675,61 @@ __global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
         if (i1 >= i0 && j1 >= j0) { p = pa; nrows = j1 - j0 + 1; }
       }
     }
-    const int incl = wave_incl_scan(nrows);
+    const int incl = dpp_incl_sum(nrows);
     const int total = __shfl(incl, 63, 64);
     for (int base = 0; base < total; base += 64) {
       // this lane's row: row k of the wave's rows
       const int k = base + lane;
       const int o = cov_owner(incl, k);
-      double qx[4], qy[4];
+      float qx[4], qy[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) { qx[c] = __shfl(x[c], o, 64); qy[c] = __shfl(y[c], o, 64); }
       const int qp = __shfl(p, o, 64);
       const int j = __shfl(j0, o, 64) + (k - (__shfl(incl, o, 64) - __shfl(nrows, o, 64)));
-      int i0 = 0, ns = 0;
+      int a1 = 0, n1 = 0, a2 = 0, n2 = 0;
       if (k < total) {
-        const double yc = A.y0 + j + 0.5;
-        double lo = INFINITY, hi = -INFINITY;
-        cov_cross(qx[0], qy[0], qx[1], qy[1], yc, lo, hi);
-        cov_cross(qx[1], qy[1], qx[2], qy[2], yc, lo, hi);
-        cov_cross(qx[2], qy[2], qx[3], qy[3], yc, lo, hi);
-        cov_cross(qx[3], qy[3], qx[0], qy[0], yc, lo, hi);
-        cov_cross(qx[0], qy[0], qx[2], qy[2], yc, lo, hi);   // the triangles' shared diagonal
-        int i1;
-        cov_range(lo, hi, A.x0, A.W, i0, i1);
-        ns = i1 >= i0 ? i1 - i0 + 1 : 0;
-      }
-      const int incl2 = wave_incl_scan(ns);
-      const int total2 = __shfl(incl2, 63, 64);
-      for (int base2 = 0; base2 < total2; base2 += 64) {
-        const int k2 = base2 + lane;
-        const int o2 = cov_owner(incl2, k2);
-        double sx[4], sy[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) { sx[c] = __shfl(qx[c], o2, 64); sy[c] = __shfl(qy[c], o2, 64); }
-        const int sp = __shfl(qp, o2, 64), sj = __shfl(j, o2, 64);
-        const int si = __shfl(i0, o2, 64) + (k2 - (__shfl(incl2, o2, 64) - __shfl(ns, o2, 64)));
-        if (k2 < total2 && cov_test<MODE>(sx, sy, A.x0 + si + 0.5, A.y0 + sj + 0.5)) {
-          int32_t* t = A.top + (int64_t)sj * A.W + si;
-          // values only grow, so a stale read costs at most a redundant atomic
-          if (*t < sp) atomicMax(t, sp);
+        const double py = A.y0 + j + 0.5;
+        if (MODE == 0) {
+          CovEdge e[4] = {cov_edge(qx[0], qy[0], qx[1], qy[1], py), cov_edge(qx[1], qy[1], qx[2], qy[2], py),
+                          cov_edge(qx[2], qy[2], qx[3], qy[3], py), cov_edge(qx[3], qy[3], qx[0], qy[0], py)};
+          cov_runs<4>(e, A.x0, A.W, a1, n1, a2, n2);
+        } else {
+          CovEdge t1[3] = {cov_edge(qx[0], qy[0], qx[1], qy[1], py), cov_edge(qx[1], qy[1], qx[2], qy[2], py),
+                           cov_edge(qx[2], qy[2], qx[0], qy[0], py)};
+          CovEdge t2[3] = {cov_edge(qx[0], qy[0], qx[2], qy[2], py), cov_edge(qx[2], qy[2], qx[3], qy[3], py),
+                           cov_edge(qx[3], qy[3], qx[0], qy[0], py)};
+          cov_runs<3>(t1, A.x0, A.W, a1, n1, a2, n2);
+          cov_runs<3>(t2, A.x0, A.W, a1, n1, a2, n2);
         }
+      }
+      // this row's samples occupy [st, st + ns) of the wave's laid-out samples;
+      // sample at position g is canvas word (g < bnd ? c1 : c2) + g
+      const int ns = n1 + n2;
+      const int incl2 = dpp_incl_sum(ns);
+      const int total2 = __shfl(incl2, 63, 64);
+      const int st = incl2 - ns, bnd = st + n1;
+      const int c1 = j * A.W + a1 - st, c2 = j * A.W + a2 - bnd;
+      int carry = 0;
+      for (int base2 = 0; base2 < total2; base2 += 64) {
+        mark[wv][lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (ns > 0 && st >= base2 && st < base2 + 64) mark[wv][st - base2] = lane + 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int m = dpp_incl_max(mark[wv][lane]);
+        const int o2 = m > 0 ? m - 1 : carry;
+        carry = __shfl(o2, 63, 64);
+        const int g = base2 + lane;
+        const int sb = __shfl(bnd, o2, 64), s1 = __shfl(c1, o2, 64), s2 = __shfl(c2, o2, 64);
+        const int sp = __shfl(qp, o2, 64);
+        if (g < total2) {
+          int32_t* tp = A.top + (g < sb ? s1 : s2) + g;
+          // values only grow, so a stale read costs at most a redundant atomic
+          if (*tp < sp) atomicMax(tp, sp);
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
   }
@@ -2266,6 +2369,7 @@ int ps_coverage(const ps_batch* b, const int64_t* offsets, const float* vx, cons
     return fail(PS_E_ARG, "unknown coverage mode %d", cv->mode);
   if (n_ribs < 0) return fail(PS_E_ARG, "negative rib count");
   const int64_t npix = (int64_t)cv->width * cv->height;
+  if (npix >= (int64_t)INT32_MAX) return fail(PS_E_ARG, "canvas must hold fewer than 2^31 pixels");
   if (npix == 0) return PS_OK;
   if (!offsets || !top || (n_ribs > 0 && (!vx || !vy))) return fail(PS_E_ARG, "NULL array");
   hipStream_t s = (hipStream_t)stream;
@@ -2273,7 +2377,7 @@ int ps_coverage(const ps_batch* b, const int64_t* offsets, const float* vx, cons
   if (n_ribs > 1 && n_links_of(b) > 0) {
     CovArgs a{offsets, n_links_of(b), b->seg_begin, b->n_paths, vx, vy, n_ribs, cv->x0, cv->y0,
               cv->width, cv->height, top};
-    const int blocks = grid_for((n_ribs - 1 + 63) / 64, 4);
+    const int blocks = grid_for((n_ribs - 1 + 63) / 64, kCovWaves);
     if (cv->mode == PS_COVER_QUAD)
       hipLaunchKernelGGL(coverage_kernel<0>, dim3(blocks), dim3(256), 0, s, a);
     else

@@ -444,6 +444,22 @@ def test_coverage_matches_oracle(case, mode):
     np.testing.assert_array_equal(got, ref)
 
 
+@pytest.mark.parametrize("shift", [1e5, 1e9])
+def test_coverage_far_from_the_origin(shift):
+    # at 1e5 the FP32 crossing estimate is a sample or so off and exact tests
+    # correct it; at 1e9 (FP32 spacing 64 px) the kernel falls back to a
+    # bisection with the exact test; both must still match sample for sample
+    b = W.random_mixed(13, n_paths=10, max_segs=5, extent=96.0)
+    b.cx[:] = (b.cx.astype(np.float64) + shift).astype(np.float32)
+    b.cy[:] = (b.cy.astype(np.float64) + shift).astype(np.float32)
+    o = oracle.stroke(b)
+    for mode in (ps.PS_COVER_QUAD, ps.PS_COVER_TRIANGLES):
+        frame = (shift - 8.0, shift - 4.0, 300, 200)
+        ref = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], *frame, mode)
+        assert (ref >= 0).sum() > 1000
+        np.testing.assert_array_equal(_cover_gpu(b, o, *frame, mode), ref)
+
+
 def test_coverage_bow_ties_differ_from_triangles():
     b = _tight_turns(65)
     o = oracle.stroke(b)
