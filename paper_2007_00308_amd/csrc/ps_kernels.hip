@@ -1076,6 +1076,8 @@ struct SplitLDS {
   int segpos[kWin + 1];       // exclusive positions of the slots' segment ribs
   int pivpos[kWin + 1];       // ... and of their pivot ribs
   int first[kWin];            // first rib of the slot in this tile, minus (r0 - 1)
+  int jfirst[kWin];           // ... as a rib index within its link
+  int endrel[kWin];           // the slot's last rib minus r0 (INT_MAX when past the tile)
 };
 
 // two buffers of per-rib partial sums: a tile whose predecessors have not all
@@ -1141,7 +1143,10 @@ __device__ __forceinline__ bool finish_tile(const EmitArgs& A, const TileState& 
 }
 
 template <int K, int PREC, bool WXY, bool WS>
-__global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
+// 3 wavefronts per SIMD (up to 168 VGPRs): a cap of 128 makes the FP64 solve
+// spill 160 bytes per lane to scratch, which costs more than it hides.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+emit_split_kernel(EmitArgs A) {
   extern __shared__ unsigned char smem_raw[];
   unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_split_lds_per_wave(K, WS);
   SplitLDS& w = *reinterpret_cast<SplitLDS*>(wave_lds);
@@ -1172,6 +1177,9 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
       long long* const srel = srel_base + (size_t)buf * (64 * K);
       const int64_t r0 = tile * TS;
       const int64_t r1 = (r0 + TS < R) ? r0 + TS : R;
+      // ribs of the tile are addressed by 32-bit offsets from r0
+      float* const vxt = A.vx + 2 * r0;
+      float* const vyt = A.vy + 2 * r0;
       int64_t base = A.tile_link[tile];
       long long run = 0;                 // segment chord sum since the tile start or its last path start
       bool seen_start = false;
@@ -1192,7 +1200,7 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
         }
         // ---- each slot's ribs inside the tile; the link holding r0 also
         // gives rib r0 - 1 when it is a segment begun earlier (first chord)
-        int ns = 0, np = 0, fr = 0;
+        int ns = 0, np = 0, fr = 0, jf = 0, er = INT_MAX;
         if (lane < kWin && idx < L) {
           const bool segl = w.rec[lane].role == ROLE_SEG;
           long long a = o_i > r0 ? o_i : r0;
@@ -1202,6 +1210,9 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
           ns = segl ? n : 0;
           np = segl ? 0 : n;
           fr = (int)(a - (r0 - 1));
+          jf = (int)(a - o_i);
+          const long long e = o_n - 1 - r0;
+          er = e < (long long)INT_MAX ? (int)e : INT_MAX;
         }
         const int ns_in = wave_incl_scan(ns), np_in = wave_incl_scan(np);
         const int NS = __builtin_amdgcn_readlane(ns_in, 63), NP = __builtin_amdgcn_readlane(np_in, 63);
@@ -1210,29 +1221,30 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
           w.pivpos[lane] = np_in - np;
           if (WS) w.ends[lane] = (lane == 0) ? (long long)carry_end : (long long)kNeed;
         }
-        if (lane < kWin) w.first[lane] = fr;
+        if (lane < kWin) { w.first[lane] = fr; w.jfirst[lane] = jf; w.endrel[lane] = er; }
         // ---- sweep A: segment ribs
         for (int q0 = 0; q0 < NS; q0 += 64) {
           const int q = q0 + lane;
           RibOut o;
           o.gx = o.gy = o.t = 0; o.chord_ok = false; o.seg_path_start = false; o.fixed = false;
-          int64_t r = -1;
+          int rel = -1;   // rib - r0
           int i = 0;
           if (q < NS) {
             // largest i with segpos[i] <= q (it holds segment ribs); the
             // positions do not decrease, so i counts the slots at or below q
 #pragma unroll
             for (int m = 1; m < kWin; ++m) i += (w.segpos[m] <= q) ? 1 : 0;
-            r = (r0 - 1) + w.first[i] + (q - w.segpos[i]);
-            compute_rib<PREC, kSegOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, A.miter_limit, o);
-            if (WXY && r >= r0) {
-              *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
-              *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
+            const int d = q - w.segpos[i];
+            rel = w.first[i] - 1 + d;
+            compute_rib<PREC, kSegOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, o);
+            if (WXY && rel >= 0) {
+              *reinterpret_cast<float2*>(vxt + 2 * rel) = make_float2(o.Nx, o.Px);
+              *reinterpret_cast<float2*>(vyt + 2 * rel) = make_float2(o.Ny, o.Py);
             }
             fixups += o.fixed ? 1 : 0;
           }
           if (WS) {
-            const bool mine = q < NS && r >= r0;
+            const bool mine = q < NS && rel >= 0;
             double pgx = wave_shr1(o.gx), pgy = wave_shr1(o.gy), pt = wave_shr1(o.t);
             if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
             long long c = 0;
@@ -1262,8 +1274,8 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
             const unsigned long long v =
                 (unsigned long long)(f ? c : run + c) | (need ? kNeed : 0ull);
             if (mine) {
-              srel[r - r0] = (long long)v;
-              if (r == w.off[i + 1] - 1) w.ends[i + 1] = (long long)v;   // the segment's last rib
+              srel[rel] = (long long)v;
+              if (rel == w.endrel[i]) w.ends[i + 1] = (long long)v;   // the segment's last rib
             }
             any_need = any_need || (__ballot(mine && need) != 0ull);
             const long long c63 = readlane_i64(c, 63);
@@ -1282,17 +1294,18 @@ __global__ void __launch_bounds__(256) emit_split_kernel(EmitArgs A) {
             int i = 0;
 #pragma unroll
             for (int m = 1; m < kWin; ++m) i += (w.pivpos[m] <= pq) ? 1 : 0;
-            const int64_t r = (r0 - 1) + w.first[i] + (pq - w.pivpos[i]);
+            const int d = pq - w.pivpos[i];
+            const int rel = w.first[i] - 1 + d;   // >= 0: pivots never reach back before r0
             RibOut o;
-            compute_rib<PREC, kPivotOnly>(w.rec[i], (int)(r - w.off[i]), A.fix_tol, A.miter_limit, o);
+            compute_rib<PREC, kPivotOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, o);
             if (WXY) {
-              *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
-              *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
+              *reinterpret_cast<float2*>(vxt + 2 * rel) = make_float2(o.Nx, o.Px);
+              *reinterpret_cast<float2*>(vyt + 2 * rel) = make_float2(o.Ny, o.Py);
             }
             if (WS) {
               // a join or end cap takes its segment's end value (slot i - 1)
               const long long v = (w.rec[i].role == ROLE_SCAP) ? 0ll : w.ends[i];
-              srel[r - r0] = v;
+              srel[rel] = v;
               any_need = any_need || ((unsigned long long)v & kNeed);
             }
           }
