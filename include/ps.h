@@ -261,7 +261,8 @@ typedef struct {
  * row-major, overwritten with the largest covering path index, or -1 (a
  * renderer drawing opaque strokes in path order shows that path there).
  * vx, vy [2 * n_ribs] and offsets as written by ps_emit or ps_emit_uniform;
- * ribs beyond offsets[n_links] are ignored.  Needs no workspace.
+ * ribs beyond offsets[n_links] are ignored.  The canvas must hold fewer than
+ * 2^31 pixels (PS_E_ARG otherwise).  Needs no workspace.
  */
 int ps_coverage(const ps_batch* batch, const int64_t* offsets, const float* vx, const float* vy,
                 int64_t n_ribs, const ps_canvas* canvas, int32_t* top, void* stream);

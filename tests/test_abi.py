@@ -137,3 +137,12 @@ def test_coverage_of_an_empty_canvas_is_a_no_op():
     for w, h in ((0, 5), (5, 0)):
         assert lib.ps_coverage(ctypes.byref(b), None, None, None, 0,
                                ctypes.byref(ps.ps_canvas(0.0, 0.0, w, h, 0)), None, None) == ps.PS_OK
+
+
+def test_coverage_rejects_a_canvas_of_2_31_pixels():
+    # pixel indices are 32-bit inside the kernel
+    lib = ps.load()
+    b = _batch()
+    cv = ps.ps_canvas(0.0, 0.0, 65536, 32768, 0)
+    assert lib.ps_coverage(ctypes.byref(b), 0x1000, 0x1000, 0x1000, 4, ctypes.byref(cv), 0x1000, None) == ps.PS_E_ARG
+    assert b"2^31" in lib.ps_last_error()
