@@ -734,8 +734,10 @@ void quad_corners(const float* vx, const float* vy, int64_t r, double* x, double
 }
 
 // Range of sample indices k (sample at o + k + 1/2, k in [0, n)) whose sample
-// lies in [lo, hi]; empty when k0 > k1.
+// lies in [lo, hi]; empty when k0 > k1, and for non-finite bounds (a quad with
+// a non-finite corner covers nothing).
 void sample_range(double lo, double hi, double o, int n, int64_t* k0, int64_t* k1) {
+  if (!std::isfinite(lo) || !std::isfinite(hi)) { *k0 = 0; *k1 = -1; return; }
   double a = std::ceil(lo - o - 0.5), b = std::floor(hi - o - 0.5);
   *k0 = (int64_t)std::max(a, 0.0);
   *k1 = (int64_t)std::min(b, (double)n - 1);

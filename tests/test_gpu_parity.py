@@ -477,6 +477,13 @@ def test_coverage_edge_cases():
     for frame in ((5000.0, 5000.0, 40, 30), (50.25, 50.25, 1, 1), (0.0, 49.0, 150, 1)):
         got = _cover_gpu(b, o, *frame, ps.PS_COVER_QUAD)
         np.testing.assert_array_equal(got, oracle.coverage(b, o["offsets"], o["vx"], o["vy"], *frame))
+    # a quad with a non-finite corner covers nothing
+    q = W.path([(W.KIND_L, [(0, 0), (1, 0)], 1.0)], width=2.0, cap=W.CAP_BUTT)
+    oq = dict(offsets=np.array([0, 0, 2, 2], np.int64),
+              vx=np.array([0.25, 8.25, 0.25, 8.25], np.float32), vy=np.array([0.125, 0.125, 8.125, 8.125], np.float32))
+    assert (_cover_gpu(q, oq, 0.0, 0.0, 12, 12, ps.PS_COVER_QUAD) == 0).sum() == 64
+    oq["vx"][1] = np.nan
+    assert np.all(_cover_gpu(q, oq, 0.0, 0.0, 12, 12, ps.PS_COVER_QUAD) == -1)
     # an empty batch: nothing covered
     e = W.paths([], widths=[])
     oe = dict(vx=np.zeros(0), vy=np.zeros(0), offsets=np.zeros(1, np.int64))

@@ -763,3 +763,13 @@ def test_triangle_split_excess_shrinks_with_q():
         assert not np.any((quad >= 0) & (tri < 0))
         excess.append(int(((tri >= 0) & (quad < 0)).sum()))
     assert excess[0] > excess[1] > excess[2] and excess[0] > 100, excess
+
+
+def test_coverage_skips_non_finite_quads():
+    # a quad with a non-finite corner covers nothing (the others still do)
+    b, off, vx, vy = _one_quad_path((0.25, 0.125), (8.25, 0.125), (8.25, 8.125), (0.25, 8.125))
+    top = oracle.coverage(b, off, vx, vy, 0.0, 0.0, 12, 12)
+    assert (top == 0).sum() == 64
+    vx[1] = np.nan
+    assert np.all(oracle.coverage(b, off, vx, vy, 0.0, 0.0, 12, 12) == -1)
+    assert oracle.coverage_at(b, off, vx, vy, 0.0, 0.0, [3], [3])[0] == -1
