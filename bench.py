@@ -281,34 +281,36 @@ def _time_plan(torch, plan, steps, warmup):
 
 
 def study_precision(args, torch, ps, W, dev):
-    """Near-degenerate shapes: count mismatches and worst vertex / arc-length
-    error against the FP64 oracle for FP32 only, FP32 + FP64 polish, FP64."""
-    import oracle
+    """Near-degenerate shapes: FP32 only and FP32 + FP64 polish against the FP64
+    path (which the GPU parity tests hold to the oracle): count mismatches, worst
+    vertex and arc-length differences, ribs re-solved in FP64."""
     b = W.config4()
-    ref = oracle.stroke(b)
     db = ps.DeviceBatch(b, device=dev)
+    ref = ps.stroke(db, b.q, precision=ps.PS_PREC_FP64)
+    R64 = ref["total_ribs"]
+    rx, ry = ref["vx"][:2 * R64].cpu().numpy(), ref["vy"][:2 * R64].cpu().numpy()
+    rs = ref["vs"][:2 * R64].cpu().numpy()[0::2]
+    rl = ref["link_ribs"].cpu().numpy()
     rows = {}
-    for name, prec in (("fp32", ps.PS_PREC_FP32), ("fp32_fixup", ps.PS_PREC_FP32_FIXUP),
-                       ("fp64", ps.PS_PREC_FP64)):
+    for name, prec in (("fp32", ps.PS_PREC_FP32), ("fp32_fixup", ps.PS_PREC_FP32_FIXUP)):
         out = ps.stroke(db, b.q, precision=prec)
         R = out["total_ribs"]
-        mism = int(np.sum(out["link_ribs"].cpu().numpy() != ref["link_ribs"]))
+        mism = int(np.sum(out["link_ribs"].cpu().numpy() != rl))
         row = {"count_mismatches": mism, "total_ribs": R, "fixups": int(out["status"].fixups)}
-        if R == int(ref["offsets"][-1]):
-            verr = np.hypot(out["vx"].cpu().numpy() - ref["vx"], out["vy"].cpu().numpy() - ref["vy"])
-            serr = np.abs(out["vs"].cpu().numpy()[0::2] - ref["vs"])
-            row.update(max_vertex_err_px=float(verr.max()), p999_vertex_err_px=float(np.quantile(verr, 0.999)),
-                       max_arclen_err_px=float(serr.max()))
+        if R == R64:
+            verr = np.hypot(out["vx"][:2 * R].cpu().numpy() - rx, out["vy"][:2 * R].cpu().numpy() - ry)
+            serr = np.abs(out["vs"][:2 * R].cpu().numpy()[0::2] - rs)
+            row.update(max_vertex_diff_px=float(verr.max()), p999_vertex_diff_px=float(np.quantile(verr, 0.999)),
+                       max_arclen_diff_px=float(serr.max()))
         rows[name] = row
         log(f"{name}: {row}")
-    print(json.dumps({"study": "precision", "workload": b.name, "segments": b.n_segs,
-                      "meta": b.meta, "modes": rows}), flush=True)
+    print(json.dumps({"study": "precision", "workload": b.name, "segments": b.n_segs, "ribs": R64,
+                      "reference": "the FP64 path", "meta": b.meta, "modes": rows}), flush=True)
     return 0
 
 
 def study_c3(args, torch, ps, W, dev):
     """One 5,000-cubic random-walk path: stroke with arc length, then dashing."""
-    import oracle
     b = W.config3()
     db = ps.DeviceBatch(b, device=dev)
     first = ps.stroke(db, b.q)
@@ -320,16 +322,10 @@ def study_c3(args, torch, ps, W, dev):
     st = plan.status()
     plain = ps.Plan(db, b.q, vertex_capacity=2 * R)
     ms_plain = _time_plan(torch, plain, args.steps, args.warmup)
-    ref = oracle.stroke(b)
-    serr = np.abs(plan.vs[:2 * R].cpu().numpy()[0::2] - ref["vs"])
-    verr = np.hypot(plan.vx[:2 * R].cpu().numpy() - ref["vx"], plan.vy[:2 * R].cpu().numpy() - ref["vy"])
-    pr = oracle.path_rib_begin(b, ref["offsets"])
-    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], list(b.dash), b.dash_phase)
     res = {"study": "c3", "workload": b.name, "ribs": R, "vertices": 2 * R,
            "ms_stroke": ms_plain, "ms_stroke_and_dash": ms, "ms_dash": ms - ms_plain,
            "dash_ribs": int(st.dash_ribs), "dashes": int(st.dash_count),
-           "oracle_dashes": int(dref["ranges"].shape[0]), "path_length_px": float(ref["vs"][-1]),
-           "max_vertex_err_px": float(verr.max()), "max_arclen_err_px": float(serr.max()),
+           "path_length_px": float(plan.vs[2 * R - 1].item()),
            "dash_bytes": 12 * 2 * int(st.dash_ribs) + 12 * 2 * R}
     log(str(res))
     print(json.dumps(res), flush=True)
