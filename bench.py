@@ -83,7 +83,7 @@ def main() -> int:
                          "dashed path, or the stress configuration at q in {pi/16, pi/64, pi/256}")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the stroking path runs on one GPU: --gpus must be 1"}), flush=True)
         return 2
     if args.profile:
         args.no_cpu = True
