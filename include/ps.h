@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-/* Segment forms (Table "path segment forms"): line, quadratic Bezier,
+/* Segment forms (the table of segment generator functions): line, quadratic Bezier,
  * rational quadratic conic with middle weight w_B, cubic Bezier. */
 enum { PS_KIND_LINE = 0, PS_KIND_QUAD = 1, PS_KIND_CONIC = 2, PS_KIND_CUBIC = 3 };
 /* Join styles (Secs. "Easy Joins", "Harder Joins: Miter Truncate and Revert"):
