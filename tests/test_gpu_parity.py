@@ -365,6 +365,32 @@ def test_uniform_baseline_matches_oracle():
     assert err.max() <= VERTEX_TOL, err.max()
 
 
+def test_uniform_baseline_with_joins_closed_paths_and_external_conics():
+    # pivots are emitted as in polar stroking; segments at t = j/N with the
+    # normal of g' (a positive multiple of it for negative conic weights too)
+    b = W.random_mixed(71, n_paths=40, max_segs=8, extent=400.0, join=W.JOIN_MITER, cap=W.CAP_SQUARE)
+    k = np.flatnonzero(b.kind == W.KIND_K)
+    b.conic_w[k[::2]] = -np.float32(0.5)
+    b.conic_w[k[1::5]] = 0.0
+    closed = np.zeros(b.n_paths, np.uint8)
+    for p in range(0, b.n_paths, 3):
+        s0, s1 = int(b.seg_begin[p]), int(b.seg_begin[p + 1]) - 1
+        n = W.NPTS[int(b.kind[s1])]
+        b.cx[n - 1, s1], b.cy[n - 1, s1] = b.cx[0, s0], b.cy[0, s0]
+        closed[p] = 1
+    b.closed = closed
+    ref = oracle.stroke(b, uniform=True)
+    db, out = _gpu(b)
+    import torch
+    vx, vy = torch.empty_like(out["vx"]), torch.empty_like(out["vy"])
+    ps.ps_emit_uniform(db, out["params"], out["offsets"], vx, vy, out["capacity"], out["ws"])
+    torch.cuda.synchronize()
+    R = out["total_ribs"]
+    assert R == int(ref["offsets"][-1])
+    err = np.hypot(_np(vx)[:2 * R] - ref["vx"], _np(vy)[:2 * R] - ref["vy"])
+    assert err.max() <= VERTEX_TOL, err.max()
+
+
 def test_facet_stats_match_oracle():
     import torch
     b = _serpentines(6, 64)
