@@ -85,6 +85,9 @@ def main() -> int:
     if args.gpus != 1:
         print(json.dumps({"error": "the stroking path runs on one GPU: --gpus must be 1"}), flush=True)
         return 2
+    if args.steps < 1 or args.warmup < 0:
+        print(json.dumps({"error": "--steps must be >= 1 and --warmup >= 0"}), flush=True)
+        return 2
     if args.profile:
         args.no_cpu = True
         args.no_per_path = True
@@ -124,12 +127,18 @@ def main() -> int:
     log(f"plan: autotuned emit mapping K={K} waves/group={waves} stage={stage}")
     stream = torch.cuda.current_stream()
 
+    # one event pair per timed step around the emit graph, on the stream the
+    # kernels run on (recorded once first so that the events exist)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for a, c in ev:
+        a.record(stream); c.record(stream)
     for _ in range(args.warmup):
         plan.launch()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        plan.launch()
+    for a, c in ev:
+        plan.launch_timed(a, c)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_step = 1e3 * t_total / args.steps
@@ -141,18 +150,9 @@ def main() -> int:
     log(f"batched: {ms_step:.3f} ms/step, {vps / 1e9:.2f} G vertices/s, "
         f"{B_alg / (ms_step * 1e-3) / 1e9:.0f} GB/s; fix-ups {st.fixups}")
 
-    # the emit kernel alone, timed with HIP events on the stream it runs on
-    reps = max(5, args.steps)
+    # the emit (tile table + emit kernel) of every timed step, from its events
+    emit_ms = sum(a.elapsed_time(c) for a, c in ev) / len(ev)
     ps.ps_set_emit_config(K, waves, stage)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(2):
-        ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, cap, plan.ws)
-    ev0.record(stream)
-    for _ in range(reps):
-        ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, cap, plan.ws)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    emit_ms = ev0.elapsed_time(ev1) / reps
     emit_bytes = algorithmic_bytes(V, b.n_segs, b.n_paths)
     emit_gbs = emit_bytes / (emit_ms * 1e-3) / 1e9
     log(f"emit call: {emit_ms:.3f} ms, {emit_gbs:.0f} GB/s algorithmic ({emit_gbs / HBM_PEAK_GBS:.1%} of peak)")

@@ -289,10 +289,14 @@ int ps_read_status(const void* ws, ps_status* out, void* stream);
 /*
  * Batched form: ps_plan_create picks the emit mapping for this batch (it runs
  * the pipeline several times on `stream` and times it), then captures
- * count -> scan -> emit (-> dash when params->n_dash > 0) into one hipGraph
- * bound to these buffers.  ps_plan_launch replays it; ps_plan_destroy frees
- * it.  link_ribs [ps_num_links], offsets [ps_num_links+1]; the dash buffers
- * may be NULL when dashing is off.  The plan keeps all pointers given here.
+ * count -> scan and emit (-> dash when params->n_dash > 0) into two hipGraphs
+ * bound to these buffers.  ps_plan_launch replays both on `stream`, back to
+ * back; ps_plan_launch_timed does the same and records the caller's events
+ * emit_begin and emit_end (hipEvent_t, created with timing) on `stream` just
+ * before and after the emit graph, so their elapsed time is that step's emit.
+ * ps_plan_destroy frees the plan.  link_ribs [ps_num_links], offsets
+ * [ps_num_links+1]; the dash buffers may be NULL when dashing is off.  The
+ * plan keeps all pointers given here.
  */
 typedef struct ps_plan ps_plan;
 int ps_plan_create(const ps_batch* batch, const ps_params* params, int32_t* link_ribs,
@@ -301,6 +305,7 @@ int ps_plan_create(const ps_batch* batch, const ps_params* params, int32_t* link
                    int64_t dash_capacity, void* ws, size_t ws_bytes, void* stream,
                    ps_plan** out);
 int ps_plan_launch(ps_plan* plan, void* stream);
+int ps_plan_launch_timed(ps_plan* plan, void* stream, void* emit_begin, void* emit_end);
 int ps_plan_destroy(ps_plan* plan);
 /* The emit mapping a plan chose: K, waves per workgroup, stage (0, 1 or 2). */
 int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_per_group,

@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
                                           ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_int64,
                                           ctypes.c_int64, _vp, ctypes.c_size_t, _vp, P(_vp)]),
         "ps_plan_launch": (ctypes.c_int, [_vp, _vp]),
+        "ps_plan_launch_timed": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
         "ps_plan_destroy": (ctypes.c_int, [_vp]),
         "ps_plan_config": (ctypes.c_int, [_vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
         "ps_set_emit_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -336,6 +337,13 @@ class Plan:
 
     def launch(self, stream=None):
         _check(load().ps_plan_launch(self.handle, _stream(stream)), "ps_plan_launch")
+
+    def launch_timed(self, emit_begin, emit_end, stream=None):
+        """launch(), recording the torch.cuda.Events emit_begin / emit_end on the
+        launch stream around the emit graph (the events must exist: record
+        each once before)."""
+        _check(load().ps_plan_launch_timed(self.handle, _stream(stream), _vp(emit_begin.cuda_event),
+                                           _vp(emit_end.cuda_event)), "ps_plan_launch_timed")
 
     def config(self):
         k, w, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -2206,18 +2206,26 @@ struct ps_plan {
   void* ws;
   WsLayout w;
   int K, waves, stage;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
+  // count -> scan, then emit (-> dash): two graphs launched back to back, so
+  // that a caller can bracket the emit with events on the launch stream
+  hipGraph_t graph[2];
+  hipGraphExec_t exec[2];
 };
 
 namespace {
 
-int enqueue_chain(ps_plan* P, hipStream_t s) {
+int enqueue_count(ps_plan* P, hipStream_t s) {
   const WsView v = ws_view(P->ws, P->w);
   int rc;
   if ((rc = launch_count(&P->b, &P->p, P->link_ribs, v, s))) return rc;
   if ((rc = do_scan_i32(P->link_ribs, n_links_of(&P->b), nullptr, P->off, v.scan, &v.st->total_ribs, s)))
     return rc;
+  return PS_OK;
+}
+
+int enqueue_emit(ps_plan* P, hipStream_t s) {
+  const WsView v = ws_view(P->ws, P->w);
+  int rc;
   if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->K, P->waves,
                         P->stage, s)))
     return rc;
@@ -2226,6 +2234,27 @@ int enqueue_chain(ps_plan* P, hipStream_t s) {
                           P->dash_rib_cap, P->dash_cap, v, P->w, s)))
       return rc;
   }
+  return PS_OK;
+}
+
+// Captures part 0 (count -> scan) or part 1 (emit -> dash) of a plan on a
+// stream of its own and instantiates it.
+int capture_part(ps_plan* P, int part) {
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PS_E_HIP, "stream");
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(PS_E_HIP, "begin capture failed");
+  }
+  const int rc = part == 0 ? enqueue_count(P, cs) : enqueue_emit(P, cs);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess || !g) return fail(PS_E_HIP, "end capture: %s", hipGetErrorString(e));
+  P->graph[part] = g;
+  e = hipGraphInstantiate(&P->exec[part], g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail(PS_E_HIP, "instantiate: %s", hipGetErrorString(e));
   return PS_OK;
 }
 
@@ -2451,7 +2480,7 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   P->dx = dx; P->dy = dy; P->ds = ds; P->range = range;
   P->dash_rib_cap = dash_rib_cap; P->dash_cap = dash_cap;
   P->ws = ws; P->w = w;
-  P->graph = nullptr; P->exec = nullptr;
+  P->graph[0] = P->graph[1] = nullptr; P->exec[0] = P->exec[1] = nullptr;
   hipStream_t s = (hipStream_t)stream;
   // autotune the emit mapping on this batch: ribs per lane K, waves per
   // workgroup, and whether link records are staged in LDS
@@ -2478,36 +2507,39 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
         if ((rc = time_emit(P, Ks[ki], Ws[wi], st, s, &ms))) { delete P; return rc; }
         if (ms < best) { best = ms; P->K = Ks[ki]; P->waves = Ws[wi]; P->stage = st; }
       }
-  // capture the chain into one graph
-  hipStream_t cs;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete P; return fail(PS_E_HIP, "stream"); }
-  if (hipStreamSynchronize(s) != hipSuccess ||
-      hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    (void)hipStreamDestroy(cs); delete P; return fail(PS_E_HIP, "begin capture failed");
+  // capture count -> scan and emit (-> dash) into a graph each
+  if (hipStreamSynchronize(s) != hipSuccess) { delete P; return fail(PS_E_HIP, "stream synchronize failed"); }
+  for (int part = 0; part < 2; ++part) {
+    if ((rc = capture_part(P, part))) { ps_plan_destroy(P); return rc; }
   }
-  rc = enqueue_chain(P, cs);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(cs, &g);
-  (void)hipStreamDestroy(cs);
-  if (rc) { if (g) (void)hipGraphDestroy(g); delete P; return rc; }
-  if (e != hipSuccess || !g) { delete P; return fail(PS_E_HIP, "end capture: %s", hipGetErrorString(e)); }
-  P->graph = g;
-  e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
-  if (e != hipSuccess) { (void)hipGraphDestroy(g); delete P; return fail(PS_E_HIP, "instantiate: %s", hipGetErrorString(e)); }
   *out = P;
   return PS_OK;
 }
 
 int ps_plan_launch(ps_plan* P, void* stream) {
-  if (!P || !P->exec) return fail(PS_E_ARG, "invalid plan");
-  PS_HIP(hipGraphLaunch(P->exec, (hipStream_t)stream));
+  if (!P || !P->exec[0] || !P->exec[1]) return fail(PS_E_ARG, "invalid plan");
+  PS_HIP(hipGraphLaunch(P->exec[0], (hipStream_t)stream));
+  PS_HIP(hipGraphLaunch(P->exec[1], (hipStream_t)stream));
+  return PS_OK;
+}
+
+int ps_plan_launch_timed(ps_plan* P, void* stream, void* emit_begin, void* emit_end) {
+  if (!P || !P->exec[0] || !P->exec[1]) return fail(PS_E_ARG, "invalid plan");
+  if (!emit_begin || !emit_end) return fail(PS_E_ARG, "NULL event");
+  hipStream_t s = (hipStream_t)stream;
+  PS_HIP(hipGraphLaunch(P->exec[0], s));
+  PS_HIP(hipEventRecord((hipEvent_t)emit_begin, s));
+  PS_HIP(hipGraphLaunch(P->exec[1], s));
+  PS_HIP(hipEventRecord((hipEvent_t)emit_end, s));
   return PS_OK;
 }
 
 int ps_plan_destroy(ps_plan* P) {
   if (!P) return PS_OK;
-  if (P->exec) (void)hipGraphExecDestroy(P->exec);
-  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (int part = 0; part < 2; ++part) {
+    if (P->exec[part]) (void)hipGraphExecDestroy(P->exec[part]);
+    if (P->graph[part]) (void)hipGraphDestroy(P->graph[part]);
+  }
   delete P;
   return PS_OK;
 }

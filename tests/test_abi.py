@@ -114,6 +114,7 @@ def test_plan_rejects_null_buffers():
                             None, None, None, None, 0, 0, 0x1000, 1 << 30, None, ctypes.byref(h))
     assert rc == ps.PS_E_ARG and not h.value
     assert lib.ps_plan_launch(None, None) == ps.PS_E_ARG
+    assert lib.ps_plan_launch_timed(None, None, None, None) == ps.PS_E_ARG
     assert lib.ps_plan_destroy(None) == ps.PS_OK
 
 

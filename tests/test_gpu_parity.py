@@ -336,6 +336,14 @@ def test_plan_graph_replays_match_eager():
         # unrelated eager work between replays
         torch.ones(1 << 20, device="cuda").sum().item()
     assert plan.status().flags == 0
+    # the timed launch: the same output, and events around the emit graph
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(); e1.record()
+    plan.vx.zero_()
+    plan.launch_timed(e0, e1)
+    torch.cuda.synchronize()
+    assert torch.equal(plan.vx[:2 * R], eager["vx"])
+    assert e0.elapsed_time(e1) > 0
     plan.close()
 
 
