@@ -219,8 +219,6 @@ void hodo_coeffs(const Seg& s, V2 N, double* A, double* B1, double* C) {
   }
 }
 
-double h_at(double A, double B1, double C, double t) { return (A * t + B1) * t + C; }
-
 // t_[Psi_{k-1},Psi_k](psi): Eq. angle2t plus the endpoint rule that follows it.
 // Among the real roots inside [lo, hi] the one whose gradient points along the
 // tangent (cos psi, sin psi) is taken -- a true root scores > 0, a cusp root 0,
