@@ -288,12 +288,12 @@ int ps_read_status(const void* ws, ps_status* out, void* stream);
 
 /*
  * Batched form: ps_plan_create picks the emit mapping for this batch (it runs
- * the pipeline several times on `stream` and times it), then captures
- * count -> scan and emit (-> dash when params->n_dash > 0) into two hipGraphs
- * bound to these buffers.  ps_plan_launch replays both on `stream`, back to
- * back; ps_plan_launch_timed does the same and records the caller's events
- * emit_begin and emit_end (hipEvent_t, created with timing) on `stream` just
- * before and after the emit graph, so their elapsed time is that step's emit.
+ * the pipeline several times on `stream` and times it), then builds one
+ * hipGraph bound to these buffers: count -> scan, an event-record node, emit
+ * (-> dash when params->n_dash > 0), an event-record node.  ps_plan_launch
+ * replays it on `stream`; ps_plan_launch_timed replays it with the two nodes
+ * recording the caller's events emit_begin and emit_end (hipEvent_t, created
+ * with timing), so their elapsed time is that launch's emit.
  * ps_plan_destroy frees the plan.  link_ribs [ps_num_links], offsets
  * [ps_num_links+1]; the dash buffers may be NULL when dashing is off.  The
  * plan keeps all pointers given here.

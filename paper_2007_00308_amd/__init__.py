@@ -339,9 +339,9 @@ class Plan:
         _check(load().ps_plan_launch(self.handle, _stream(stream)), "ps_plan_launch")
 
     def launch_timed(self, emit_begin, emit_end, stream=None):
-        """launch(), recording the torch.cuda.Events emit_begin / emit_end on the
-        launch stream around the emit graph (the events must exist: record
-        each once before)."""
+        """launch(), with the graph's event nodes recording the torch.cuda.Events
+        emit_begin / emit_end on either side of the emit (the events must exist:
+        record each once before)."""
         _check(load().ps_plan_launch_timed(self.handle, _stream(stream), _vp(emit_begin.cuda_event),
                                            _vp(emit_end.cuda_event)), "ps_plan_launch_timed")
 

@@ -2206,10 +2206,14 @@ struct ps_plan {
   void* ws;
   WsLayout w;
   int K, waves, stage;
-  // count -> scan, then emit (-> dash): two graphs launched back to back, so
-  // that a caller can bracket the emit with events on the launch stream
-  hipGraph_t graph[2];
-  hipGraphExec_t exec[2];
+  // one graph: child graph count -> scan, an event-record node, child graph
+  // emit (-> dash), an event-record node.  The nodes record the plan's own
+  // events unless a timed launch points them at the caller's.
+  hipGraph_t part[2];
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipGraphNode_t ev_node[2];
+  hipEvent_t ev_own[2];
 };
 
 namespace {
@@ -2238,7 +2242,7 @@ int enqueue_emit(ps_plan* P, hipStream_t s) {
 }
 
 // Captures part 0 (count -> scan) or part 1 (emit -> dash) of a plan on a
-// stream of its own and instantiates it.
+// stream of its own.
 int capture_part(ps_plan* P, int part) {
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PS_E_HIP, "stream");
@@ -2252,8 +2256,24 @@ int capture_part(ps_plan* P, int part) {
   (void)hipStreamDestroy(cs);
   if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
   if (e != hipSuccess || !g) return fail(PS_E_HIP, "end capture: %s", hipGetErrorString(e));
-  P->graph[part] = g;
-  e = hipGraphInstantiate(&P->exec[part], g, nullptr, nullptr, 0);
+  P->part[part] = g;
+  return PS_OK;
+}
+
+// Assembles the plan's graph from its two parts and the event-record nodes.
+int assemble_plan(ps_plan* P) {
+  for (int k = 0; k < 2; ++k)
+    if (hipEventCreate(&P->ev_own[k]) != hipSuccess) return fail(PS_E_HIP, "event create failed");
+  hipGraph_t g;
+  if (hipGraphCreate(&g, 0) != hipSuccess) return fail(PS_E_HIP, "graph create failed");
+  P->graph = g;
+  hipGraphNode_t a, b;
+  if (hipGraphAddChildGraphNode(&a, g, nullptr, 0, P->part[0]) != hipSuccess ||
+      hipGraphAddEventRecordNode(&P->ev_node[0], g, &a, 1, P->ev_own[0]) != hipSuccess ||
+      hipGraphAddChildGraphNode(&b, g, &P->ev_node[0], 1, P->part[1]) != hipSuccess ||
+      hipGraphAddEventRecordNode(&P->ev_node[1], g, &b, 1, P->ev_own[1]) != hipSuccess)
+    return fail(PS_E_HIP, "graph assembly failed");
+  const hipError_t e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) return fail(PS_E_HIP, "instantiate: %s", hipGetErrorString(e));
   return PS_OK;
 }
@@ -2480,7 +2500,8 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   P->dx = dx; P->dy = dy; P->ds = ds; P->range = range;
   P->dash_rib_cap = dash_rib_cap; P->dash_cap = dash_cap;
   P->ws = ws; P->w = w;
-  P->graph[0] = P->graph[1] = nullptr; P->exec[0] = P->exec[1] = nullptr;
+  P->part[0] = P->part[1] = nullptr; P->graph = nullptr; P->exec = nullptr;
+  P->ev_node[0] = P->ev_node[1] = nullptr; P->ev_own[0] = P->ev_own[1] = nullptr;
   hipStream_t s = (hipStream_t)stream;
   // autotune the emit mapping on this batch: ribs per lane K, waves per
   // workgroup, and whether link records are staged in LDS
@@ -2507,38 +2528,42 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
         if ((rc = time_emit(P, Ks[ki], Ws[wi], st, s, &ms))) { delete P; return rc; }
         if (ms < best) { best = ms; P->K = Ks[ki]; P->waves = Ws[wi]; P->stage = st; }
       }
-  // capture count -> scan and emit (-> dash) into a graph each
+  // capture count -> scan and emit (-> dash), then join them in one graph
   if (hipStreamSynchronize(s) != hipSuccess) { delete P; return fail(PS_E_HIP, "stream synchronize failed"); }
   for (int part = 0; part < 2; ++part) {
     if ((rc = capture_part(P, part))) { ps_plan_destroy(P); return rc; }
   }
+  if ((rc = assemble_plan(P))) { ps_plan_destroy(P); return rc; }
   *out = P;
   return PS_OK;
 }
 
 int ps_plan_launch(ps_plan* P, void* stream) {
-  if (!P || !P->exec[0] || !P->exec[1]) return fail(PS_E_ARG, "invalid plan");
-  PS_HIP(hipGraphLaunch(P->exec[0], (hipStream_t)stream));
-  PS_HIP(hipGraphLaunch(P->exec[1], (hipStream_t)stream));
+  if (!P || !P->exec) return fail(PS_E_ARG, "invalid plan");
+  PS_HIP(hipGraphLaunch(P->exec, (hipStream_t)stream));
   return PS_OK;
 }
 
 int ps_plan_launch_timed(ps_plan* P, void* stream, void* emit_begin, void* emit_end) {
-  if (!P || !P->exec[0] || !P->exec[1]) return fail(PS_E_ARG, "invalid plan");
+  if (!P || !P->exec) return fail(PS_E_ARG, "invalid plan");
   if (!emit_begin || !emit_end) return fail(PS_E_ARG, "NULL event");
-  hipStream_t s = (hipStream_t)stream;
-  PS_HIP(hipGraphLaunch(P->exec[0], s));
-  PS_HIP(hipEventRecord((hipEvent_t)emit_begin, s));
-  PS_HIP(hipGraphLaunch(P->exec[1], s));
-  PS_HIP(hipEventRecord((hipEvent_t)emit_end, s));
+  // a launch takes the events its nodes hold when it is enqueued
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[0], (hipEvent_t)emit_begin));
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[1], (hipEvent_t)emit_end));
+  const hipError_t e = hipGraphLaunch(P->exec, (hipStream_t)stream);
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[0], P->ev_own[0]));
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[1], P->ev_own[1]));
+  PS_HIP(e);
   return PS_OK;
 }
 
 int ps_plan_destroy(ps_plan* P) {
   if (!P) return PS_OK;
-  for (int part = 0; part < 2; ++part) {
-    if (P->exec[part]) (void)hipGraphExecDestroy(P->exec[part]);
-    if (P->graph[part]) (void)hipGraphDestroy(P->graph[part]);
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (int k = 0; k < 2; ++k) {
+    if (P->part[k]) (void)hipGraphDestroy(P->part[k]);
+    if (P->ev_own[k]) (void)hipEventDestroy(P->ev_own[k]);
   }
   delete P;
   return PS_OK;
