@@ -288,12 +288,14 @@ int ps_read_status(const void* ws, ps_status* out, void* stream);
 
 /*
  * Batched form: ps_plan_create picks the emit mapping for this batch (it runs
- * the pipeline several times on `stream` and times it), then builds one
- * hipGraph bound to these buffers: count -> scan, an event-record node, emit
- * (-> dash when params->n_dash > 0), an event-record node.  ps_plan_launch
- * replays it on `stream`; ps_plan_launch_timed replays it with the two nodes
+ * the pipeline several times on `stream` and times it), then captures
+ * count -> scan -> emit (-> dash when params->n_dash > 0) into a hipGraph
+ * bound to these buffers, and a second copy with an event-record node
+ * between scan and emit and one after the emit.  ps_plan_launch replays the
+ * first on `stream`; ps_plan_launch_timed replays the second with its nodes
  * recording the caller's events emit_begin and emit_end (hipEvent_t, created
- * with timing), so their elapsed time is that launch's emit.
+ * with timing), so their elapsed time is that launch's emit (the event nodes
+ * add some launch latency, which is why plain launches skip them).
  * ps_plan_destroy frees the plan.  link_ribs [ps_num_links], offsets
  * [ps_num_links+1]; the dash buffers may be NULL when dashing is off.  The
  * plan keeps all pointers given here.

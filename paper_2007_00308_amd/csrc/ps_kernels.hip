@@ -2206,12 +2206,13 @@ struct ps_plan {
   void* ws;
   WsLayout w;
   int K, waves, stage;
-  // one graph: child graph count -> scan, an event-record node, child graph
-  // emit (-> dash), an event-record node.  The nodes record the plan's own
-  // events unless a timed launch points them at the caller's.
-  hipGraph_t part[2];
-  hipGraph_t graph;
-  hipGraphExec_t exec;
+  // graph[0]: count -> scan -> emit (-> dash).  graph[1]: the same chain with
+  // an event-record node between scan and emit and one after the emit; the
+  // nodes record the plan's own events unless a timed launch points them at
+  // the caller's.  Event nodes add launch latency, so plain launches replay
+  // graph[0].
+  hipGraph_t graph[2];
+  hipGraphExec_t exec[2];
   hipGraphNode_t ev_node[2];
   hipEvent_t ev_own[2];
 };
@@ -2241,39 +2242,40 @@ int enqueue_emit(ps_plan* P, hipStream_t s) {
   return PS_OK;
 }
 
-// Captures part 0 (count -> scan) or part 1 (emit -> dash) of a plan on a
-// stream of its own.
-int capture_part(ps_plan* P, int part) {
+// Appends an event-record node for `ev` to the graph being captured on cs,
+// after everything captured so far; later captured work follows it.
+int capture_event_node(hipStream_t cs, hipEvent_t ev, hipGraphNode_t* node) {
+  hipStreamCaptureStatus st;
+  unsigned long long id;
+  hipGraph_t g;
+  const hipGraphNode_t* deps;
+  size_t n_deps;
+  PS_HIP(hipStreamGetCaptureInfo_v2(cs, &st, &id, &g, &deps, &n_deps));
+  PS_HIP(hipGraphAddEventRecordNode(node, g, deps, n_deps, ev));
+  PS_HIP(hipStreamUpdateCaptureDependencies(cs, node, 1, hipStreamSetCaptureDependencies));
+  return PS_OK;
+}
+
+// Captures the chain on a stream of its own into graph[timed] and
+// instantiates it; the timed graph gets the two event-record nodes.
+int capture_plan(ps_plan* P, int timed) {
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PS_E_HIP, "stream");
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipStreamDestroy(cs);
     return fail(PS_E_HIP, "begin capture failed");
   }
-  const int rc = part == 0 ? enqueue_count(P, cs) : enqueue_emit(P, cs);
+  int rc = enqueue_count(P, cs);
+  if (!rc && timed) rc = capture_event_node(cs, P->ev_own[0], &P->ev_node[0]);
+  if (!rc) rc = enqueue_emit(P, cs);
+  if (!rc && timed) rc = capture_event_node(cs, P->ev_own[1], &P->ev_node[1]);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &g);
   (void)hipStreamDestroy(cs);
   if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
   if (e != hipSuccess || !g) return fail(PS_E_HIP, "end capture: %s", hipGetErrorString(e));
-  P->part[part] = g;
-  return PS_OK;
-}
-
-// Assembles the plan's graph from its two parts and the event-record nodes.
-int assemble_plan(ps_plan* P) {
-  for (int k = 0; k < 2; ++k)
-    if (hipEventCreate(&P->ev_own[k]) != hipSuccess) return fail(PS_E_HIP, "event create failed");
-  hipGraph_t g;
-  if (hipGraphCreate(&g, 0) != hipSuccess) return fail(PS_E_HIP, "graph create failed");
-  P->graph = g;
-  hipGraphNode_t a, b;
-  if (hipGraphAddChildGraphNode(&a, g, nullptr, 0, P->part[0]) != hipSuccess ||
-      hipGraphAddEventRecordNode(&P->ev_node[0], g, &a, 1, P->ev_own[0]) != hipSuccess ||
-      hipGraphAddChildGraphNode(&b, g, &P->ev_node[0], 1, P->part[1]) != hipSuccess ||
-      hipGraphAddEventRecordNode(&P->ev_node[1], g, &b, 1, P->ev_own[1]) != hipSuccess)
-    return fail(PS_E_HIP, "graph assembly failed");
-  const hipError_t e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+  P->graph[timed] = g;
+  e = hipGraphInstantiate(&P->exec[timed], g, nullptr, nullptr, 0);
   if (e != hipSuccess) return fail(PS_E_HIP, "instantiate: %s", hipGetErrorString(e));
   return PS_OK;
 }
@@ -2500,7 +2502,7 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   P->dx = dx; P->dy = dy; P->ds = ds; P->range = range;
   P->dash_rib_cap = dash_rib_cap; P->dash_cap = dash_cap;
   P->ws = ws; P->w = w;
-  P->part[0] = P->part[1] = nullptr; P->graph = nullptr; P->exec = nullptr;
+  P->graph[0] = P->graph[1] = nullptr; P->exec[0] = P->exec[1] = nullptr;
   P->ev_node[0] = P->ev_node[1] = nullptr; P->ev_own[0] = P->ev_own[1] = nullptr;
   hipStream_t s = (hipStream_t)stream;
   // autotune the emit mapping on this batch: ribs per lane K, waves per
@@ -2528,41 +2530,41 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
         if ((rc = time_emit(P, Ks[ki], Ws[wi], st, s, &ms))) { delete P; return rc; }
         if (ms < best) { best = ms; P->K = Ks[ki]; P->waves = Ws[wi]; P->stage = st; }
       }
-  // capture count -> scan and emit (-> dash), then join them in one graph
+  // capture the chain twice: plain, and with the emit's event-record nodes
   if (hipStreamSynchronize(s) != hipSuccess) { delete P; return fail(PS_E_HIP, "stream synchronize failed"); }
-  for (int part = 0; part < 2; ++part) {
-    if ((rc = capture_part(P, part))) { ps_plan_destroy(P); return rc; }
-  }
-  if ((rc = assemble_plan(P))) { ps_plan_destroy(P); return rc; }
+  for (int k = 0; k < 2; ++k)
+    if (hipEventCreate(&P->ev_own[k]) != hipSuccess) { ps_plan_destroy(P); return fail(PS_E_HIP, "event create failed"); }
+  for (int timed = 0; timed < 2; ++timed)
+    if ((rc = capture_plan(P, timed))) { ps_plan_destroy(P); return rc; }
   *out = P;
   return PS_OK;
 }
 
 int ps_plan_launch(ps_plan* P, void* stream) {
-  if (!P || !P->exec) return fail(PS_E_ARG, "invalid plan");
-  PS_HIP(hipGraphLaunch(P->exec, (hipStream_t)stream));
+  if (!P || !P->exec[0]) return fail(PS_E_ARG, "invalid plan");
+  PS_HIP(hipGraphLaunch(P->exec[0], (hipStream_t)stream));
   return PS_OK;
 }
 
 int ps_plan_launch_timed(ps_plan* P, void* stream, void* emit_begin, void* emit_end) {
-  if (!P || !P->exec) return fail(PS_E_ARG, "invalid plan");
+  if (!P || !P->exec[1]) return fail(PS_E_ARG, "invalid plan");
   if (!emit_begin || !emit_end) return fail(PS_E_ARG, "NULL event");
   // a launch takes the events its nodes hold when it is enqueued
-  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[0], (hipEvent_t)emit_begin));
-  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[1], (hipEvent_t)emit_end));
-  const hipError_t e = hipGraphLaunch(P->exec, (hipStream_t)stream);
-  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[0], P->ev_own[0]));
-  PS_HIP(hipGraphExecEventRecordNodeSetEvent(P->exec, P->ev_node[1], P->ev_own[1]));
+  hipGraphExec_t x = P->exec[1];
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(x, P->ev_node[0], (hipEvent_t)emit_begin));
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(x, P->ev_node[1], (hipEvent_t)emit_end));
+  const hipError_t e = hipGraphLaunch(x, (hipStream_t)stream);
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(x, P->ev_node[0], P->ev_own[0]));
+  PS_HIP(hipGraphExecEventRecordNodeSetEvent(x, P->ev_node[1], P->ev_own[1]));
   PS_HIP(e);
   return PS_OK;
 }
 
 int ps_plan_destroy(ps_plan* P) {
   if (!P) return PS_OK;
-  if (P->exec) (void)hipGraphExecDestroy(P->exec);
-  if (P->graph) (void)hipGraphDestroy(P->graph);
   for (int k = 0; k < 2; ++k) {
-    if (P->part[k]) (void)hipGraphDestroy(P->part[k]);
+    if (P->exec[k]) (void)hipGraphExecDestroy(P->exec[k]);
+    if (P->graph[k]) (void)hipGraphDestroy(P->graph[k]);
     if (P->ev_own[k]) (void)hipEventDestroy(P->ev_own[k]);
   }
   delete P;
