@@ -275,8 +275,10 @@ int ps_coverage(const ps_batch* batch, const int64_t* offsets, const float* vx, 
  * dash_range [2*dash_capacity] int64 pairs [first rib, end rib) per dash.  A
  * pattern boundary s_b inside a step (s_{j-1}, s_j] inserts a rib interpolated
  * linearly in s; steps of zero length hold no boundary; the pattern restarts
- * at every path.  Totals go to the status word; on overflow nothing past the
- * capacities is written and PS_STATUS_DASH_OVERFLOW is set.
+ * at every path.  Each call first clears PS_STATUS_DASH_OVERFLOW and the dash
+ * totals of the status word, then writes its own totals there; on overflow
+ * nothing past the capacities is written and PS_STATUS_DASH_OVERFLOW is set,
+ * and a second call with capacities of at least those totals fits.
  */
 int ps_dash(const ps_batch* batch, const ps_params* params, const int64_t* offsets,
             const float* vx, const float* vy, const float* vs, int64_t vertex_capacity,

@@ -283,9 +283,10 @@ def stroke(db: DeviceBatch, q: float, precision: int = PS_PREC_FP64, vertex_capa
                vs=None if vs is None else vs[:2 * R], total_ribs=R, ws=ws, params=params,
                capacity=cap)
     if dash:
-        # a first pass sizes the dash output from the status word
+        # a first pass with a guessed capacity; on overflow the status word
+        # holds the exact totals, and one more pass with those must fit
         rcap, dcap = max(16, 2 * R), max(16, R)
-        while True:
+        for attempt in range(2):
             dx = torch.empty(2 * rcap, dtype=torch.float32, device=dev)
             dy = torch.empty_like(dx)
             ds = torch.empty_like(dx)
@@ -294,7 +295,10 @@ def stroke(db: DeviceBatch, q: float, precision: int = PS_PREC_FP64, vertex_capa
             st = ps_read_status(ws, stream)
             if not (st.flags & PS_STATUS_DASH_OVERFLOW):
                 break
-            rcap, dcap = int(st.dash_ribs) + 1, int(st.dash_count) + 1
+            if attempt == 1:
+                raise RuntimeError(f"ps_dash overflowed twice (needs {st.dash_ribs} ribs, "
+                                   f"{st.dash_count} dashes)")
+            rcap, dcap = max(16, int(st.dash_ribs)), max(16, int(st.dash_count))
         nr, nd = int(st.dash_ribs), int(st.dash_count)
         out.update(dx=dx[:2 * nr], dy=dy[:2 * nr], ds=ds[:2 * nr], dash_range=rng[:2 * nd].view(-1, 2))
     out["status"] = ps_read_status(ws, stream)

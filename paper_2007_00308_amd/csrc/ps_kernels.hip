@@ -1839,6 +1839,16 @@ __device__ __forceinline__ void dash_boundaries(const DashArgs& A, double u0, do
   }
 }
 
+// Each ps_dash reports its own totals and overflow: clear them first (the
+// other status bits belong to the count and emit of the same workspace).
+__global__ void reset_dash_status_kernel(DevStatus* st) {
+  if (threadIdx.x == 0) {
+    atomicAnd(&st->flags, ~(unsigned)PS_STATUS_DASH_OVERFLOW);
+    st->dash_ribs = 0;
+    st->dash_count = 0;
+  }
+}
+
 __global__ void __launch_bounds__(256) dash_count_kernel(DashArgs A) {
   const int64_t R = A.off[A.n_links];
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
@@ -2190,6 +2200,7 @@ int launch_dash(const ps_batch* b, const ps_params* p, const int64_t* off, const
   for (int i = p->n_dash + 1; i <= kMaxDash; ++i) a.cum[i] = 0;
   const int grid = num_cus() * 8;
   const int64_t* R_dev = off + a.n_links;
+  hipLaunchKernelGGL(reset_dash_status_kernel, dim3(1), dim3(64), 0, s, v.st);
   hipLaunchKernelGGL(dash_count_kernel, dim3(grid), dim3(256), 0, s, a);
   int rc;
   if ((rc = do_scan_i32(v.dash_r, w.max_ribs, R_dev, v.dash_rpos, v.dash_scan, nullptr, s))) return rc;

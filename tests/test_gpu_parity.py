@@ -311,6 +311,64 @@ def test_dash_config3_unique_quantities():
     np.testing.assert_allclose(dx[2 * rng[:, 0]], dref["dx"][2 * dref["ranges"][:, 0]], atol=0.05)
 
 
+def test_dash_overflow_then_retry_fits():
+    # a dash call that overflows reports the totals; a second call on the same
+    # workspace with those capacities must succeed (the overflow bit is the
+    # call's own, not left over from the first)
+    import torch
+    b = W.config3(n_segs=200)
+    db, out = _gpu(b, dash=(7.0, 3.0, 2.0, 3.0), dash_phase=0.0)   # workspace sized for dashing
+    params = out["params"]
+    dev = out["vx"].device
+    small = 64
+    bufs = [torch.empty(2 * small, dtype=torch.float32, device=dev) for _ in range(3)]
+    rng = torch.empty(2 * small, dtype=torch.int64, device=dev)
+    ps.ps_dash(db, params, out["offsets"], out["vx"], out["vy"], out["vs"], out["capacity"], *bufs, rng,
+               small, small, out["ws"])
+    st = ps.ps_read_status(out["ws"])
+    assert st.flags & ps.PS_STATUS_DASH_OVERFLOW
+    nr, nd = int(st.dash_ribs), int(st.dash_count)
+    assert nr > small and nd > small
+    bufs = [torch.empty(2 * nr, dtype=torch.float32, device=dev) for _ in range(3)]
+    rng = torch.empty(2 * nd, dtype=torch.int64, device=dev)
+    ps.ps_dash(db, params, out["offsets"], out["vx"], out["vy"], out["vs"], out["capacity"], *bufs, rng,
+               nr, nd, out["ws"])
+    st = ps.ps_read_status(out["ws"])
+    assert not (st.flags & ps.PS_STATUS_DASH_OVERFLOW)
+    assert (int(st.dash_ribs), int(st.dash_count)) == (nr, nd)
+
+
+def test_dash_mixed_batch_with_closed_paths_and_external_conics():
+    # dashing restarts at s = 0 on every path; closed contours run on through
+    # the closing join; a four-entry pattern with a phase
+    b = W.random_mixed(81, n_paths=30, max_segs=8, extent=600.0, join=W.JOIN_MITER, cap=W.CAP_ROUND)
+    k = np.flatnonzero(b.kind == W.KIND_K)
+    b.conic_w[k[::2]] = -np.float32(0.4)
+    closed = np.zeros(b.n_paths, np.uint8)
+    for p in range(0, b.n_paths, 3):
+        s0, s1 = int(b.seg_begin[p]), int(b.seg_begin[p + 1]) - 1
+        n = W.NPTS[int(b.kind[s1])]
+        b.cx[n - 1, s1], b.cy[n - 1, s1] = b.cx[0, s0], b.cy[0, s0]
+        closed[p] = 1
+    b.closed = closed
+    pattern, phase = (7.0, 3.0, 2.0, 3.0), 1.5
+    ref = oracle.stroke(b)
+    pr = oracle.path_rib_begin(b, ref["offsets"])
+    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], list(pattern), phase)
+    _, out = _gpu(b, dash=pattern, dash_phase=phase)
+    rng = _np(out["dash_range"])
+    assert rng.shape == dref["ranges"].shape and rng.shape[0] > 100
+    ds = _np(out["ds"])[0::2].astype(np.float64)
+    np.testing.assert_allclose(ds[rng[:, 0]], dref["ds"][dref["ranges"][:, 0]], atol=0.05)
+    np.testing.assert_allclose(ds[rng[:, 1] - 1], dref["ds"][dref["ranges"][:, 1] - 1], atol=0.05)
+    dx, dy = _np(out["dx"]).astype(np.float64), _np(out["dy"]).astype(np.float64)
+    for col in (0, 1):
+        i = 2 * (rng[:, col] - col) + 1
+        j = 2 * (dref["ranges"][:, col] - col) + 1
+        np.testing.assert_allclose(dx[i], dref["dx"][j], atol=0.05)
+        np.testing.assert_allclose(dy[i], dref["dy"][j], atol=0.05)
+
+
 # ------------------------------------------------------------------ plan / graph
 def test_small_links_overflow_the_lds_window():
     # single-segment paths with butt caps and many zero-length segments: a
@@ -424,6 +482,29 @@ def test_facet_stats_match_oracle():
     assert oracle.stats_from_sums(_np(stats))["max_deg"] < 2 * 4.0 + 0.05
 
 
+def test_facet_stats_on_exact_cusps_match_oracle():
+    # exact cusps (P2 = P0 + P1 - P3): fans at the cusp, swallowtails of the
+    # inner offset right after it; the same classification on both sides
+    import torch
+    rng = np.random.default_rng(12)
+    segs = []
+    for _ in range(96):
+        P0 = rng.uniform(0, 512, 2); P3 = P0 + rng.uniform(-300, 300, 2)
+        P1 = P0 + rng.uniform(-200, 200, 2); P2 = P0 + P1 - P3
+        segs.append([(W.KIND_C, [tuple(np.round(P * 256) / 256) for P in (P0, P1, P2, P3)], 1.0)])
+    b = W.paths(segs, widths=[60.0] * 96, q=math.radians(4.0))
+    db, out = _gpu(b)
+    R = out["total_ribs"]
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ps.ps_facet_stats(db, out["offsets"], out["vx"], out["vy"], stats)
+    torch.cuda.synchronize()
+    got = oracle.stats_from_sums(_np(stats))
+    ref = oracle.facet_stats(b, _np(out["offsets"]), _np(out["vx"])[:2 * R], _np(out["vy"])[:2 * R])
+    assert got["count"] == ref["count"] > 1000
+    for k in ("max_deg", "mean_deg", "sd_deg"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-9, abs=1e-12), k
+
+
 # ------------------------------------------------------------------ coverage
 def _cover_gpu(b, o, x0, y0, Wd, Hd, mode):
     """ps_coverage on the oracle's own rib stream (uploaded as FP32)."""
@@ -528,9 +609,10 @@ def test_coverage_full_batch_sampled():
     # the 4096-path batch on a 4096 x 4096 canvas, checked at sampled pixels
     b = W.config2()
     o = oracle.stroke(b)
-    got = _cover_gpu(b, o, 0.0, 0.0, 4096, 4096, ps.PS_COVER_QUAD)
     rng = np.random.default_rng(7)
     pi, pj = rng.integers(0, 4096, 384), rng.integers(0, 4096, 384)
-    ref = oracle.coverage_at(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, pi, pj)
-    np.testing.assert_array_equal(got[pj, pi], ref)
-    assert (ref >= 0).mean() > 0.5
+    for mode in (ps.PS_COVER_QUAD, ps.PS_COVER_TRIANGLES):
+        got = _cover_gpu(b, o, 0.0, 0.0, 4096, 4096, mode)
+        ref = oracle.coverage_at(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, pi, pj, mode)
+        np.testing.assert_array_equal(got[pj, pi], ref)
+        assert (ref >= 0).mean() > 0.5
