@@ -188,7 +188,9 @@ int ps_scan(const int32_t* link_ribs, int64_t n_links, int64_t* offsets, void* w
  * rib of each path, constant across joins and caps, with a step whose t
  * decreases adding nothing.  Consecutive ribs of a path form its quads.
  * Requires ws from ps_count (same batch and params) and offsets from ps_scan.
- * If 2*R > vertex_capacity nothing is written and PS_STATUS_OVERFLOW is set.
+ * If 2*R > vertex_capacity nothing is written and PS_STATUS_OVERFLOW is set;
+ * each call clears that bit first, so a retry with enough capacity reports
+ * no overflow.
  */
 int ps_emit(const ps_batch* batch, const ps_params* params, const int64_t* offsets,
             float* vx, float* vy, float* vs, int64_t vertex_capacity, void* ws,

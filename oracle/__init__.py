@@ -193,6 +193,8 @@ def dash(rib_begin: np.ndarray, vx: np.ndarray, vy: np.ndarray, vs: np.ndarray, 
     vs = np.ascontiguousarray(vs, np.float32)
     rib_begin = np.ascontiguousarray(rib_begin, np.int64)
     pat = np.ascontiguousarray(pattern, np.float64)
+    if len(pat) < 2 or len(pat) % 2 or not (pat.sum() > 0):
+        raise ValueError("bad dash pattern")
     cap = 16
     while True:
         dx = np.zeros(2 * cap); dy = np.zeros(2 * cap); ds = np.zeros(cap)
@@ -201,8 +203,6 @@ def dash(rib_begin: np.ndarray, vx: np.ndarray, vy: np.ndarray, vs: np.ndarray, 
         n = _load().oracle_dash(len(rib_begin) - 1, _p(rib_begin), _p(vx), _p(vy), _p(vs), _p(pat),
                                 len(pat), ctypes.c_double(phase), _p(dx), _p(dy), _p(ds), _p(rng),
                                 cap, cap, _p(nd))
-        if n == -1 and len(pat) < 2:
-            raise ValueError("bad dash pattern")
         if n >= 0 and nd[0] <= cap:
             return dict(dx=dx[:2 * n], dy=dy[:2 * n], ds=ds[:n], ranges=rng[:2 * nd[0]].reshape(-1, 2))
         cap = max(2 * cap, int(abs(n)) + 1, int(nd[0]) + 1)

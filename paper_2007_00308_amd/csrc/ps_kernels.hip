@@ -580,7 +580,11 @@ __global__ void __launch_bounds__(256) emit_prepare_kernel(const int64_t* off, i
   const int64_t R = off[n_links];
   const int64_t n_tiles = (R + TS - 1) / TS;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid == 0) st->tile_counter = 0;
+  // each emit reports its own overflow (cleared and set by the same thread)
+  if (tid == 0) {
+    st->tile_counter = 0;
+    atomicAnd(&st->flags, ~(unsigned)PS_STATUS_OVERFLOW);
+  }
   if (2 * R > capacity || n_tiles > max_tiles) {
     if (tid == 0) atomicOr(&st->flags, (unsigned)PS_STATUS_OVERFLOW);
     return;

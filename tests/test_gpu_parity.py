@@ -223,9 +223,22 @@ def test_overflow_sets_status_and_writes_nothing():
     db = ps.DeviceBatch(b)
     ref = oracle.stroke(b)
     R = int(ref["offsets"][-1])
-    cap = 2 * R - 2
-    out = ps.stroke(db, b.q, vertex_capacity=cap)
-    assert out["status"].flags & ps.PS_STATUS_OVERFLOW
+    params = ps.make_params(b.q)
+    link_ribs = torch.empty(db.n_links, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(db.n_links + 1, dtype=torch.int64, device="cuda")
+    ws = ps.alloc_workspace(ps.ps_workspace_bytes(db, params, 2 * R), link_ribs.device)
+    ps.ps_count(db, params, link_ribs, ws)
+    ps.ps_scan(link_ribs, db.n_links, offsets, ws)
+    vx = torch.full((2 * R,), 12345.0, device="cuda")
+    vy, vs = torch.full_like(vx, 12345.0), torch.full_like(vx, 12345.0)
+    ps.ps_emit(db, params, offsets, vx, vy, vs, 2 * R - 2, ws)
+    assert ps.ps_read_status(ws).flags & ps.PS_STATUS_OVERFLOW
+    assert bool(torch.all(vx == 12345.0)) and bool(torch.all(vs == 12345.0))
+    # a retry with enough capacity on the same workspace fits and reports no overflow
+    ps.ps_emit(db, params, offsets, vx, vy, vs, 2 * R, ws)
+    assert not (ps.ps_read_status(ws).flags & ps.PS_STATUS_OVERFLOW)
+    err = np.hypot(_np(vx) - ref["vx"], _np(vy) - ref["vy"])
+    assert err.max() <= VERTEX_TOL
 
 
 def test_nonfinite_and_bad_values_flagged():

@@ -773,3 +773,11 @@ def test_coverage_skips_non_finite_quads():
     vx[1] = np.nan
     assert np.all(oracle.coverage(b, off, vx, vy, 0.0, 0.0, 12, 12) == -1)
     assert oracle.coverage_at(b, off, vx, vy, 0.0, 0.0, [3], [3])[0] == -1
+
+
+@pytest.mark.parametrize("pattern", [[5.0], [5.0, 2.0, 1.0], [0.0, 0.0]])
+def test_dash_rejects_bad_patterns(pattern):
+    b = W.path([(W.KIND_L, [(0, 0), (40, 0)], 1.0)], width=2.0)
+    o = oracle.stroke(b)
+    with pytest.raises(ValueError):
+        oracle.dash(oracle.path_rib_begin(b, o["offsets"]), o["vx"], o["vy"], o["vs"], pattern)
