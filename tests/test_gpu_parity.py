@@ -588,6 +588,49 @@ def test_coverage_far_from_the_origin(shift):
         np.testing.assert_array_equal(_cover_gpu(b, o, *frame, mode), ref)
 
 
+def _degenerate_batch():
+    # empty paths, zero-length and point segments, collinear folds, an exact
+    # cusp, a conic of weight 0 and a closed contour of one line pair
+    segs = [[],
+            [(W.KIND_L, [(10, 10), (60, 10)], 1.0), (W.KIND_C, [(60, 10), (60, 10), (60, 10), (60, 10)], 1.0),
+             (W.KIND_C, [(60, 10), (110, 10), (80, 10), (160, 10)], 1.0)],
+            [],
+            [(W.KIND_Q, [(20, 60), (20, 60), (70, 110)], 1.0), (W.KIND_K, [(70, 110), (40, 140), (120, 150)], 0.0),
+             (W.KIND_C, [(120, 150), (121, 151), (120, 151), (121, 150)], 1.0)],
+            [(W.KIND_L, [(30, 170), (90, 170)], 1.0), (W.KIND_L, [(90, 170), (30, 170)], 1.0)],
+            [(W.KIND_L, [(140, 40), (140, 40)], 1.0)]]
+    n = len(segs)
+    return W.paths(segs, widths=[6.0, 8.0, 5.0, 12.0, 4.0, 3.0], q=math.pi / 16,
+                   joins=[W.JOIN_ROUND, W.JOIN_MITER, W.JOIN_BEVEL, W.JOIN_NONE, W.JOIN_MITER_CLIP, W.JOIN_ROUND],
+                   caps=[W.CAP_ROUND, W.CAP_SQUARE, W.CAP_BUTT, W.CAP_TRIANGLE, W.CAP_ROUND, W.CAP_ROUND],
+                   closed=[0, 0, 0, 0, 1, 0][:n])
+
+
+def test_next_rows_on_degenerate_batches():
+    import torch
+    b = _degenerate_batch()
+    r = _compare(b)
+    assert r["R"] > 50
+    o = oracle.stroke(b)
+    for mode in (ps.PS_COVER_QUAD, ps.PS_COVER_TRIANGLES):
+        ref = oracle.coverage(b, o["offsets"], o["vx"], o["vy"], 0.0, 0.0, 200, 200, mode)
+        np.testing.assert_array_equal(_cover_gpu(b, o, 0.0, 0.0, 200, 200, mode), ref)
+    db, out = _gpu(b)
+    R = out["total_ribs"]
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ps.ps_facet_stats(db, out["offsets"], out["vx"], out["vy"], stats)
+    torch.cuda.synchronize()
+    got = oracle.stats_from_sums(_np(stats))
+    ref = oracle.facet_stats(b, _np(out["offsets"]), _np(out["vx"])[:2 * R], _np(out["vy"])[:2 * R])
+    assert got["count"] == ref["count"]
+    uref = oracle.stroke(b, uniform=True)
+    vx, vy = torch.empty_like(out["vx"]), torch.empty_like(out["vy"])
+    ps.ps_emit_uniform(db, out["params"], out["offsets"], vx, vy, out["capacity"], out["ws"])
+    torch.cuda.synchronize()
+    err = np.hypot(_np(vx)[:2 * R] - uref["vx"], _np(vy)[:2 * R] - uref["vy"])
+    assert err.max() <= VERTEX_TOL, err.max()
+
+
 def test_coverage_bow_ties_differ_from_triangles():
     b = _tight_turns(65)
     o = oracle.stroke(b)
