@@ -71,6 +71,60 @@ def test_config2_reduced(prec):
     _compare(W.config2(n_paths=96, max_segs=64), precision=prec)
 
 
+def test_config2_full_in_the_bench_mapping():
+    # the benchmark batch through an autotuned plan, as bench.py runs it:
+    # every count bit-exact, every vertex and arc length against the oracle
+    import torch
+    b = W.config2_fast()
+    db = ps.DeviceBatch(b)
+    first = ps.stroke(db, b.q)
+    R = first["total_ribs"]
+    del first
+    plan = ps.Plan(db, b.q, vertex_capacity=2 * R)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert plan.status().flags == 0
+    ref = oracle.stroke(b)
+    np.testing.assert_array_equal(_np(plan.link_ribs[:db.n_links]), ref["link_ribs"])
+    np.testing.assert_array_equal(_np(plan.offsets), ref["offsets"])
+    err = np.hypot(_np(plan.vx[:2 * R]).astype(np.float64) - ref["vx"],
+                   _np(plan.vy[:2 * R]).astype(np.float64) - ref["vy"])
+    assert err.max() <= VERTEX_TOL, err.max()
+    vs = _np(plan.vs[:2 * R]).astype(np.float64)
+    assert np.abs(vs[0::2] - ref["vs"]).max() <= _arc_tol(ref["vs"])
+    plan.close()
+
+
+def test_config5_full_sampled():
+    # 2^20 segments at q = pi/256 (4.9e8 vertices): every link count, and the
+    # ribs of 200 sampled paths plus the longest one against the oracle
+    import torch
+    b = W.config5(q=math.pi / 256)
+    db, out = _gpu(b)
+    assert out["status"].flags == 0
+    np.testing.assert_array_equal(_np(out["link_ribs"]), oracle.count(b))
+    off = out["offsets"]
+    sb = b.seg_begin.astype(np.int64)
+    rng = np.random.default_rng(5)
+    counts = np.diff(sb)
+    idx = np.union1d(rng.choice(b.n_paths, 200, replace=False), [int(np.argmax(counts))])
+    sub = b.subset(idx)
+    ref = oracle.stroke(sub)
+    rsb = sub.seg_begin.astype(np.int64)
+    for k, p in enumerate(idx):
+        a, e = int(off[2 * sb[p] + p]), int(off[2 * sb[p + 1] + p + 1])
+        ra, re = int(ref["offsets"][2 * rsb[k] + k]), int(ref["offsets"][2 * rsb[k + 1] + k + 1])
+        assert e - a == re - ra, p
+        if e == a:
+            continue
+        vx = _np(out["vx"][2 * a:2 * e]).astype(np.float64)
+        vy = _np(out["vy"][2 * a:2 * e]).astype(np.float64)
+        err = np.hypot(vx - ref["vx"][2 * ra:2 * re], vy - ref["vy"][2 * ra:2 * re])
+        assert err.max() <= VERTEX_TOL, (p, err.max())
+        vs = _np(out["vs"][2 * a:2 * e:2]).astype(np.float64)
+        assert np.abs(vs - ref["vs"][ra:re]).max() <= _arc_tol(ref["vs"][ra:re]), p
+
+
 def test_config3_full_path():
     r = _compare(W.config3())
     assert r["R"] > 100_000
