@@ -244,15 +244,10 @@ __device__ __forceinline__ double sqrt64(double x) {
   return fma(d, h, g);
 }
 
-// sin and cos of an unwrapped tangent angle in FP64 (|x| < 2^20; the angles
-// here stay within a few turns).  x = k pi/2 + y with pi/2 split in three
-// parts, the first two of 33 significant bits so that k P1 and k P2 are exact,
-// then the Taylor series of sin (to y^17) and cos (to y^16) on |y| <= pi/4,
-// whose truncation errors there are below 3e-18.
-__device__ __forceinline__ void sincos_rd(double x, double* s, double* c) {
-  const double P1 = 1.5707963267341256, P2 = 6.077100506303966e-11, P3 = 2.0222662487959506e-21;
-  const double k = rint(x * 0.6366197723675814);
-  const double y = ((x - k * P1) - k * P2) - k * P3;
+// sin and cos in FP64 of y + q pi/2 for |y| <= pi/4: the Taylor series of
+// sin (to y^17) and cos (to y^16), whose truncation errors there are below
+// 3e-18, then the quadrant q (mod 4).
+__device__ __forceinline__ void sincos_quadrant(double y, int q, double* s, double* c) {
   const double z = y * y;
   double ps = 2.8114572543455206e-15;       //  1/17!
   ps = ps * z - 7.647163731819816e-13;      // -1/15!
@@ -272,10 +267,63 @@ __device__ __forceinline__ void sincos_rd(double x, double* s, double* c) {
   pc = pc * z + 4.1666666666666664e-02;     //  1/4!
   pc = pc * z - 0.5;                        // -1/2!
   const double cs = 1.0 + z * pc;
-  const int q = (int)k & 3;
+  q &= 3;
   const double s0 = (q & 1) ? cs : sn, c0 = (q & 1) ? sn : cs;
   *s = (q & 2) ? -s0 : s0;
   *c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// pi/2 in three parts, the first two of 33 significant bits, so that k P1 and
+// k P2 are exact for |k| < 2^20
+constexpr double kHalfPi1 = 1.5707963267341256, kHalfPi2 = 6.077100506303966e-11,
+                 kHalfPi3 = 2.0222662487959506e-21;
+
+// sin and cos of an unwrapped tangent angle in FP64 (|x| < 2^20; the angles
+// here stay within a few turns): x = k pi/2 + y, |y| <= pi/4, by Cody-Waite
+// reduction with the three parts of pi/2.
+__device__ __forceinline__ void sincos_rd(double x, double* s, double* c) {
+  const double k = rint(x * 0.6366197723675814);
+  const double y = ((x - k * kHalfPi1) - k * kHalfPi2) - k * kHalfPi3;
+  sincos_quadrant(y, (int)k, s, c);
+}
+
+// Table-driven sin and cos for the per-rib directions.  The table holds
+// (sin, cos) of k 2pi/kSinTab, k = 0..kSinTab-1, and lives in LDS (filled once
+// per workgroup by fill_sincos_tab).  x = k 2pi/kSinTab + y with 2pi/kSinTab
+// split in three parts (those of pi/2 divided by kSinTab/4, a power of two),
+// so |y| <= pi/kSinTab; then sin y to y^7 and cos y - 1 to y^8, whose truncation
+// errors there are below 4e-19 relative, and the angle-sum identities.  Few
+// coefficients, none of them large in register count, instead of the two
+// degree-17 series with quadrant selection.
+constexpr int kSinTab = 128;
+
+__device__ __forceinline__ void fill_sincos_tab(double2* tab) {
+  // entry k is the angle q pi/2 + m 2pi/kSinTab with q the nearest quadrant
+  // and |m| <= kSinTab/8, the residual formed from the same three parts
+  constexpr int kQ = kSinTab / 4;
+  for (int k = threadIdx.x; k < kSinTab; k += blockDim.x) {
+    const int q = (k + kQ / 2) / kQ;
+    const double m = (double)(k - q * kQ);
+    const double y = (m * (kHalfPi1 / kQ) + m * (kHalfPi2 / kQ)) + m * (kHalfPi3 / kQ);
+    double s, c;
+    sincos_quadrant(y, q, &s, &c);
+    tab[k] = make_double2(s, c);
+  }
+}
+
+__device__ __forceinline__ void sincos_tab(const double2* tab, double x, double* s, double* c) {
+  constexpr double P1 = kHalfPi1 / (kSinTab / 4), P2 = kHalfPi2 / (kSinTab / 4),
+                   P3 = kHalfPi3 / (kSinTab / 4);
+  const double k = rint(x * (kSinTab / kTwoPi));
+  const double y = ((x - k * P1) - k * P2) - k * P3;
+  const double z = y * y;
+  const double ps = (z * (1.0 / 120) - 1.0 / 6) - z * z * (1.0 / 5040);   // (sin y - y) / y^3
+  const double sy = y + y * z * ps;
+  const double pc = (z * (1.0 / 24) - 0.5) + z * z * (z * (1.0 / 40320) - 1.0 / 720);
+  const double cm1 = z * pc;                                              // cos y - 1
+  const double2 t = tab[(int)k & (kSinTab - 1)];
+  *s = fma(t.y, sy, fma(t.x, cm1, t.x));
+  *c = fma(-t.x, sy, fma(t.y, cm1, t.y));
 }
 
 // ===========================================================================
@@ -359,20 +407,17 @@ __device__ __forceinline__ SolveOut<F> solve_t(const Hodo<F>& h, F nx, F ny, F t
     r0 = r1 = -C / B1;
   }
   SolveOut<F> o;
-  o.found = false;
-  o.t = hi;
-  F best = (F)0;
-  if (r0 >= lo && r0 <= hi) {
+  const bool in0 = r0 >= lo && r0 <= hi;
+  const bool in1 = r1 >= lo && r1 <= hi && r1 != r0;
+  o.found = in0 || in1;
+  o.t = in0 ? r0 : (in1 ? r1 : hi);
+  if (in0 && in1) {
+    // two candidates: the larger score g'(t).T (r0 on a tie)
     F gx, gy;
     hodo_eval(h, r0, gx, gy);
-    best = gx * tx + gy * ty;
-    o.t = r0; o.found = true;
-  }
-  if (r1 >= lo && r1 <= hi && r1 != r0) {
-    F gx, gy;
+    const F s0 = gx * tx + gy * ty;
     hodo_eval(h, r1, gx, gy);
-    const F sc = gx * tx + gy * ty;
-    if (!o.found || sc > best) { o.t = r1; o.found = true; }
+    if (gx * tx + gy * ty > s0) o.t = r1;
   }
   if (!o.found) {
     const F ul = (F)1 - lo, uh = (F)1 - hi;

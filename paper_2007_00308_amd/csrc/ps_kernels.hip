@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256) count_angles_kernel(CountArgs A) {
 
 __device__ inline void clear_rec(LinkRec& r) {
   r.role = ROLE_EMPTY; r.n_iv = 0; r.kind = 0; r.flags = 0; r.r = 0; r.w = 1;
-  for (int k = 0; k < kMaxIv; ++k) r.dsum[k] = 0;
+  for (int k = 0; k < kMaxIv; ++k) r.dsum[k] = INT_MAX;   // past the last interval
   for (int k = 0; k < 4; ++k) { r.x[k] = 0; r.y[k] = 0; }
   for (int k = 0; k < kMaxIv - 1; ++k) r.p[k] = 0;
   for (int k = 0; k <= kMaxIv; ++k) r.psi[k] = 0;
@@ -669,7 +669,7 @@ __device__ __forceinline__ void miter_vertex(const Rec& rp, int j, int style, do
 }
 template <int PREC, int ROLES = kAnyRole, typename Rec>
 __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol, double miter_limit,
-                                            RibOut& o) {
+                                            const double2* sc_tab, RibOut& o) {
   const uint8_t role = rp.role;
   const bool seg = ROLES == kSegOnly || (ROLES == kAnyRole && role == ROLE_SEG);
   const double rad = (double)rp.r;
@@ -677,17 +677,16 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
   o.seg_path_start = (rp.flags & kFirstSegInPath) && j == 0;
   o.fixed = false;
   // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]; pivots have one.  The
-  // cumulative counts increase strictly, so k - 1 is the number of interior
-  // boundaries j has passed: counted without a chain of dependent reads
+  // cumulative counts increase strictly (the entries past the last interval
+  // hold INT_MAX), so k - 1 is the number of boundaries j has passed: counted
+  // without a chain of dependent reads
   const int n_iv = rp.n_iv;
-  int k = 1, d0 = 0;
+  int k = 1;
+  if (ROLES != kPivotOnly) {
 #pragma unroll
-  for (int m = 0; m < kMaxIv - 1; ++m) {
-    const int dm = rp.dsum[m];
-    const bool past = (m < n_iv - 1) && (j > dm);
-    k += past ? 1 : 0;
-    d0 = past ? dm : d0;
+    for (int m = 0; m < kMaxIv - 1; ++m) k += (j > rp.dsum[m]) ? 1 : 0;
   }
+  const int d0 = (k > 1) ? rp.dsum[k - 2] : 0;
   const int d1 = rp.dsum[k - 1];
   const double psa = rp.psi[k - 1], psb = rp.psi[k];
   const bool at0 = j == d0, at1 = j == d1;
@@ -700,7 +699,7 @@ __device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol,
     nx = -(double)s32; ny = (double)c32;
   } else {
     double sn, cs;
-    sincos_rd(psi, &sn, &cs);
+    sincos_tab(sc_tab, psi, &sn, &cs);
     nx = -sn; ny = cs;
   }
   double rN = rad, rP = rad;
@@ -827,9 +826,15 @@ __device__ __forceinline__ long long dpp_i64(long long v) {
   const unsigned hi = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)((unsigned long long)v >> 32));
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
-// the value of lane - 1 (wave_shr:1); lane 0 reads 0
-__device__ __forceinline__ double wave_shr1(double v) {
-  return __longlong_as_double(dpp_i64<0x138, 0xf>(__double_as_longlong(v)));
+// the value of lane - 1 (wave_shr:1); lane 0, which has no source lane,
+// keeps the DPP's old value: `first`
+__device__ __forceinline__ double wave_shr1(double v, double first) {
+  const unsigned long long a = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long f = (unsigned long long)__double_as_longlong(first);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)a, 0x138, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(a >> 32), 0x138,
+                                                            0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 __device__ __forceinline__ long long readlane_i64(long long v, int l) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(unsigned long long)v, l);
@@ -876,6 +881,16 @@ __host__ __device__ constexpr size_t emit_lds_per_wave(int K, bool ws, bool stag
   return (stage ? sizeof(WinLDS) : 0) + (ws ? (size_t)K * 64 * sizeof(long long) : 0);
 }
 
+// One ticket per workgroup per round: the workgroup's waves take tiles
+// ticket * waves + w.  Returns the ticket every thread of the group read.
+__device__ __forceinline__ unsigned int take_group_ticket(unsigned long long* counter, unsigned int& slot) {
+  if (threadIdx.x == 0) slot = (unsigned int)atomicAdd(counter, 1ull);
+  __syncthreads();
+  const unsigned int t = slot;
+  __syncthreads();   // every wave has read the ticket before the next round writes it
+  return t;
+}
+
 template <int K, int PREC, bool WXY, bool WS, bool STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PS_PREC_FP32_FIXUP ? 3 : 4)))
 emit_kernel(EmitArgs A) {
@@ -883,6 +898,7 @@ emit_kernel(EmitArgs A) {
   unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_lds_per_wave(K, WS, STAGE);
   WinLDS& win = *reinterpret_cast<WinLDS*>(wave_lds);
   long long* srel = reinterpret_cast<long long*>(wave_lds + (STAGE ? sizeof(WinLDS) : 0));
+  __shared__ double2 sc_tab[kSinTab];
   const int lane = threadIdx.x & 63;
   const int64_t L = A.n_links;
   const int64_t R = A.off[L];
@@ -895,12 +911,14 @@ emit_kernel(EmitArgs A) {
   // fewer tickets per rib matter more than their latency)
   __shared__ unsigned int group_ticket;
   const int n_waves = blockDim.x >> 6;
-  const int wave = threadIdx.x >> 6;
-  for (;;) {
-    if (threadIdx.x == 0) group_ticket = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
-    __syncthreads();
-    const int64_t first = (int64_t)group_ticket * n_waves;
-    __syncthreads();   // every wave has read the ticket before the next round writes it
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  // a workgroup without a tile leaves before filling the sincos table
+  unsigned int ticket = take_group_ticket(&A.st->tile_counter, group_ticket);
+  if ((int64_t)ticket * n_waves >= n_tiles) return;
+  fill_sincos_tab(sc_tab);
+  __syncthreads();
+  for (;; ticket = take_group_ticket(&A.st->tile_counter, group_ticket)) {
+    const int64_t first = (int64_t)ticket * n_waves;
     if (first >= n_tiles) break;
     const int64_t tile = first + wave;
     if (tile < n_tiles) {
@@ -950,7 +968,7 @@ emit_kernel(EmitArgs A) {
                 const int m = (a + b + 1) >> 1;
                 if (win.off[m] <= r) a = m; else b = m - 1;
               }
-              compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, A.miter_limit, o);
+              compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, A.miter_limit, sc_tab, o);
               pending = false;
             }
             const unsigned long long pm = __ballot(pending);
@@ -960,7 +978,7 @@ emit_kernel(EmitArgs A) {
           }
         } else if (valid) {
           l = link_of(A.off, l, lhi, r);
-          compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, A.miter_limit, o);
+          compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, A.miter_limit, sc_tab, o);
         }
         if (valid) {
           if (WXY && mine) {
@@ -971,8 +989,7 @@ emit_kernel(EmitArgs A) {
         }
         if (WS) {
           // chord from the previous rib; zero when t decreases
-          double pgx = wave_shr1(o.gx), pgy = wave_shr1(o.gy), pt = wave_shr1(o.t);
-          if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
+          const double pgx = wave_shr1(o.gx, cgx), pgy = wave_shr1(o.gy, cgy), pt = wave_shr1(o.t, ct);
           long long c = 0;
           if (mine && o.chord_ok && o.t >= pt) {
             const double dx = o.gx - pgx, dy = o.gy - pgy;
@@ -1147,14 +1164,16 @@ __device__ __forceinline__ bool finish_tile(const EmitArgs& A, const TileState& 
 }
 
 template <int K, int PREC, bool WXY, bool WS>
-// 3 wavefronts per SIMD (up to 168 VGPRs): a cap of 128 makes the FP64 solve
-// spill 160 bytes per lane to scratch, which costs more than it hides.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// 4 wavefronts per SIMD (at most 128 VGPRs, which the FP64 solve fits without
+// spilling once the wave index is known to be wave-uniform); how many are
+// resident is then up to the LDS per workgroup, which K sets.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 emit_split_kernel(EmitArgs A) {
   extern __shared__ unsigned char smem_raw[];
   unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_split_lds_per_wave(K, WS);
   SplitLDS& w = *reinterpret_cast<SplitLDS*>(wave_lds);
   long long* const srel_base = reinterpret_cast<long long*>(wave_lds + sizeof(SplitLDS));   // 2 x (rib - r0)
+  __shared__ double2 sc_tab[kSinTab];
   const int lane = threadIdx.x & 63;
   const int64_t L = A.n_links;
   const int64_t R = A.off[L];
@@ -1165,15 +1184,17 @@ emit_split_kernel(EmitArgs A) {
   unsigned long long fixups = 0;
   __shared__ unsigned int group_ticket;
   const int n_waves = blockDim.x >> 6;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   TileState parked;
   parked.tile = -1; parked.r0 = parked.r1 = 0; parked.agg = 0;
   parked.seen_start = parked.any_need = false; parked.buf = 0;
-  for (;;) {
-    if (threadIdx.x == 0) group_ticket = (unsigned int)atomicAdd(&A.st->tile_counter, 1ull);
-    __syncthreads();
-    const int64_t first_tile = (int64_t)group_ticket * n_waves;
-    __syncthreads();   // every wave has read the ticket before the next round writes it
+  // a workgroup without a tile leaves before filling the sincos table
+  unsigned int ticket = take_group_ticket(&A.st->tile_counter, group_ticket);
+  if ((int64_t)ticket * n_waves >= n_tiles) return;
+  fill_sincos_tab(sc_tab);
+  __syncthreads();
+  for (;; ticket = take_group_ticket(&A.st->tile_counter, group_ticket)) {
+    const int64_t first_tile = (int64_t)ticket * n_waves;
     if (first_tile >= n_tiles) break;
     const int64_t tile = first_tile + wave;
     if (tile < n_tiles) {
@@ -1219,6 +1240,8 @@ emit_split_kernel(EmitArgs A) {
           er = e < (long long)INT_MAX ? (int)e : INT_MAX;
         }
         const int ns_in = wave_incl_scan(ns), np_in = wave_incl_scan(np);
+        const int segpos_l = ns_in - ns;   // lane m <= kWin: exclusive positions of slot m
+        const int pivpos_l = np_in - np;
         const int NS = __builtin_amdgcn_readlane(ns_in, 63), NP = __builtin_amdgcn_readlane(np_in, 63);
         if (lane <= kWin) {
           w.segpos[lane] = ns_in - ns;
@@ -1227,20 +1250,28 @@ emit_split_kernel(EmitArgs A) {
         }
         if (lane < kWin) { w.first[lane] = fr; w.jfirst[lane] = jf; w.endrel[lane] = er; }
         // ---- sweep A: segment ribs
+        int i_lo = 0;   // the slot holding rib position q0 - 1 (or 0)
         for (int q0 = 0; q0 < NS; q0 += 64) {
           const int q = q0 + lane;
           RibOut o;
           o.gx = o.gy = o.t = 0; o.chord_ok = false; o.seg_path_start = false; o.fixed = false;
           int rel = -1;   // rib - r0
-          int i = 0;
+          // largest i with segpos[i] <= q (the slot holding q: of equal
+          // positions the last one has the ribs); the positions do not
+          // decrease, so only the slots from i_lo up to the first one that
+          // starts past this batch are compared, their positions read from
+          // the slot lanes as wave-uniform values
+          int i = i_lo;
+          for (int m = i_lo + 1; m < kWin; m = __builtin_amdgcn_readfirstlane(m + 1)) {
+            const int sp = __builtin_amdgcn_readlane(segpos_l, m);
+            if (sp > q0 + 63) break;
+            i = (q >= sp) ? m : i;
+          }
+          i_lo = __builtin_amdgcn_readlane(i, 63);
           if (q < NS) {
-            // largest i with segpos[i] <= q (it holds segment ribs); the
-            // positions do not decrease, so i counts the slots at or below q
-#pragma unroll
-            for (int m = 1; m < kWin; ++m) i += (w.segpos[m] <= q) ? 1 : 0;
             const int d = q - w.segpos[i];
             rel = w.first[i] - 1 + d;
-            compute_rib<PREC, kSegOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, o);
+            compute_rib<PREC, kSegOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, sc_tab, o);
             if (WXY && rel >= 0) {
               *reinterpret_cast<float2*>(vxt + 2 * rel) = make_float2(o.Nx, o.Px);
               *reinterpret_cast<float2*>(vyt + 2 * rel) = make_float2(o.Ny, o.Py);
@@ -1249,8 +1280,7 @@ emit_split_kernel(EmitArgs A) {
           }
           if (WS) {
             const bool mine = q < NS && rel >= 0;
-            double pgx = wave_shr1(o.gx), pgy = wave_shr1(o.gy), pt = wave_shr1(o.t);
-            if (lane == 0) { pgx = cgx; pgy = cgy; pt = ct; }
+            const double pgx = wave_shr1(o.gx, cgx), pgy = wave_shr1(o.gy, cgy), pt = wave_shr1(o.t, ct);
             long long c = 0;
             if (mine && o.chord_ok && o.t >= pt) {
               const double dx = o.gx - pgx, dy = o.gy - pgy;
@@ -1291,17 +1321,22 @@ emit_split_kernel(EmitArgs A) {
             cgx = readlane_f64(o.gx, last); cgy = readlane_f64(o.gy, last); ct = readlane_f64(o.t, last);
           }
         }
-        // ---- sweep B: pivot ribs
+        // ---- sweep B: pivot ribs (the slot found as in sweep A)
+        int ip_lo = 0;
         for (int p0 = 0; p0 < NP; p0 += 64) {
           const int pq = p0 + lane;
+          int i = ip_lo;
+          for (int m = ip_lo + 1; m < kWin; m = __builtin_amdgcn_readfirstlane(m + 1)) {
+            const int sp = __builtin_amdgcn_readlane(pivpos_l, m);
+            if (sp > p0 + 63) break;
+            i = (pq >= sp) ? m : i;
+          }
+          ip_lo = __builtin_amdgcn_readlane(i, 63);
           if (pq < NP) {
-            int i = 0;
-#pragma unroll
-            for (int m = 1; m < kWin; ++m) i += (w.pivpos[m] <= pq) ? 1 : 0;
             const int d = pq - w.pivpos[i];
             const int rel = w.first[i] - 1 + d;   // >= 0: pivots never reach back before r0
             RibOut o;
-            compute_rib<PREC, kPivotOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, o);
+            compute_rib<PREC, kPivotOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, sc_tab, o);
             if (WXY) {
               *reinterpret_cast<float2*>(vxt + 2 * rel) = make_float2(o.Nx, o.Px);
               *reinterpret_cast<float2*>(vyt + 2 * rel) = make_float2(o.Ny, o.Py);
@@ -1361,6 +1396,9 @@ struct UniformArgs {
 // One thread per link slot: segment ribs at t_j = j/N on Eq. NaiveStroking,
 // joins and caps as the polar emit.
 __global__ void __launch_bounds__(256) uniform_emit_kernel(UniformArgs A) {
+  __shared__ double2 sc_tab[kSinTab];
+  fill_sincos_tab(sc_tab);
+  __syncthreads();
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= A.n_links || 2 * A.off[A.n_links] > A.capacity) return;
   const int64_t r0 = A.off[l], n = A.off[l + 1] - r0;
@@ -1369,7 +1407,7 @@ __global__ void __launch_bounds__(256) uniform_emit_kernel(UniformArgs A) {
   if (rp.role != ROLE_SEG) {
     for (int j = 0; j < (int)n; ++j) {
       RibOut o;
-      compute_rib<PS_PREC_FP64, kPivotOnly>(rp, j, 0.f, A.miter_limit, o);
+      compute_rib<PS_PREC_FP64, kPivotOnly>(rp, j, 0.f, A.miter_limit, sc_tab, o);
       *reinterpret_cast<float2*>(A.vx + 2 * (r0 + j)) = make_float2(o.Nx, o.Px);
       *reinterpret_cast<float2*>(A.vy + 2 * (r0 + j)) = make_float2(o.Ny, o.Py);
     }
