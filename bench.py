@@ -401,7 +401,7 @@ def study_emit(args, torch, ps, W, dev):
     P, cap, ws = plan.params, 2 * R, plan.ws
     rows = []
     for stage in (1, 2):
-        for K in (4, 8, 16):
+        for K in (4, 6, 8, 16):
             for waves in (1, 2, 4):
                 ps.ps_set_emit_config(K, waves, stage)
                 row = {"stage": stage, "K": K, "waves": waves,

@@ -1107,6 +1107,18 @@ __host__ __device__ constexpr size_t emit_split_lds_per_wave(int K, bool ws) {
   return sizeof(SplitLDS) + (ws ? 2 * (size_t)K * 64 * sizeof(long long) : 0);
 }
 
+// Stores of a tile's vertex pairs through a buffer resource that spans only
+// the tile's own bytes: 32-bit offsets from the tile start instead of 64-bit
+// addresses per lane, and a store outside the tile is dropped by the hardware.
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(float* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);   // raw dwords (gfx9)
+}
+__device__ __forceinline__ void store_pair(__amdgpu_buffer_rsrc_t r, int rel, float a, float b) {
+  const v2u32 d = {__float_as_uint(a), __float_as_uint(b)};
+  __builtin_amdgcn_raw_buffer_store_b64(d, r, rel * 8, 0, 0);
+}
+
 // A computed tile whose arc length still needs its prefix.
 struct TileState {
   int64_t tile, r0, r1;
@@ -1150,14 +1162,16 @@ __device__ __forceinline__ bool finish_tile(const EmitArgs& A, const TileState& 
   }
   const long long pre = (long long)prefix;
   const long long* sr = srel + (size_t)T.buf * (64 * K);
+  const int n = (int)(T.r1 - T.r0);
+  const __amdgpu_buffer_rsrc_t rs = tile_rsrc(A.vs + 2 * T.r0, (uint32_t)n * 8u);
 #pragma unroll 2
   for (int k = 0; k < K; ++k) {
-    const int64_t d = 64 * k + lane;
-    if (d < T.r1 - T.r0) {
+    const int d = 64 * k + lane;
+    if (d < n) {
       const unsigned long long sv = (unsigned long long)sr[d];
       const long long sf = (long long)(sv & ~kNeed) + ((sv & kNeed) ? pre : 0);
       const float sx = (float)((double)sf * (1.0 / kFix));
-      *reinterpret_cast<float2*>(A.vs + 2 * (T.r0 + d)) = make_float2(sx, sx);
+      store_pair(rs, d, sx, sx);
     }
   }
   return true;
@@ -1203,8 +1217,9 @@ emit_split_kernel(EmitArgs A) {
       const int64_t r0 = tile * TS;
       const int64_t r1 = (r0 + TS < R) ? r0 + TS : R;
       // ribs of the tile are addressed by 32-bit offsets from r0
-      float* const vxt = A.vx + 2 * r0;
-      float* const vyt = A.vy + 2 * r0;
+      const uint32_t tile_bytes = (uint32_t)(r1 - r0) * 8u;
+      const __amdgpu_buffer_rsrc_t vxt = tile_rsrc(A.vx + 2 * r0, tile_bytes);
+      const __amdgpu_buffer_rsrc_t vyt = tile_rsrc(A.vy + 2 * r0, tile_bytes);
       int64_t base = A.tile_link[tile];
       long long run = 0;                 // segment chord sum since the tile start or its last path start
       bool seen_start = false;
@@ -1273,8 +1288,8 @@ emit_split_kernel(EmitArgs A) {
             rel = w.first[i] - 1 + d;
             compute_rib<PREC, kSegOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, sc_tab, o);
             if (WXY && rel >= 0) {
-              *reinterpret_cast<float2*>(vxt + 2 * rel) = make_float2(o.Nx, o.Px);
-              *reinterpret_cast<float2*>(vyt + 2 * rel) = make_float2(o.Ny, o.Py);
+              store_pair(vxt, rel, o.Nx, o.Px);
+              store_pair(vyt, rel, o.Ny, o.Py);
             }
             fixups += o.fixed ? 1 : 0;
           }
@@ -1338,8 +1353,8 @@ emit_split_kernel(EmitArgs A) {
             RibOut o;
             compute_rib<PREC, kPivotOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, sc_tab, o);
             if (WXY) {
-              *reinterpret_cast<float2*>(vxt + 2 * rel) = make_float2(o.Nx, o.Px);
-              *reinterpret_cast<float2*>(vyt + 2 * rel) = make_float2(o.Ny, o.Py);
+              store_pair(vxt, rel, o.Nx, o.Px);
+              store_pair(vyt, rel, o.Ny, o.Py);
             }
             if (WS) {
               // a join or end cap takes its segment's end value (slot i - 1)
@@ -2144,6 +2159,7 @@ template <int PREC, bool WXY, bool WS, int MAP>
 EmitLaunch pick_k(int K) {
   switch (K) {
     case 4: return emit_launcher<4, PREC, WXY, WS, MAP>;
+    case 6: return emit_launcher<6, PREC, WXY, WS, MAP>;
     case 8: return emit_launcher<8, PREC, WXY, WS, MAP>;
     case 16: return emit_launcher<16, PREC, WXY, WS, MAP>;
     default: return nullptr;
@@ -2175,7 +2191,7 @@ EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws, int map) {
   }
 }
 
-bool valid_k(int K) { return K == 4 || K == 8 || K == 16; }
+bool valid_k(int K) { return K == 4 || K == 6 || K == 8 || K == 16; }
 
 // Largest Newton step (in t) accepted when polishing an FP32 root in FP64;
 // a larger step means the FP32 root was ill-conditioned and the rib is
@@ -2395,7 +2411,7 @@ size_t ps_workspace_bytes(const ps_batch* b, const ps_params* p, int64_t vertex_
 }
 
 int ps_set_emit_config(int32_t K, int32_t waves, int32_t stage) {
-  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 4, 8 or 16");
+  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 4, 6, 8 or 16");
   if (waves < 0 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   if (stage < -1 || stage > 2) return fail(PS_E_ARG, "stage must be -1 (keep), 0, 1 or 2");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -2591,10 +2607,10 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
     tune = g_autotune;
   }
   float best = 1e30f;
-  const int Ks[3] = {4, 8, 16};
+  const int Ks[4] = {4, 6, 8, 16};
   const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
   for (int st = 2; tune && st >= 0; --st)
-    for (int ki = 0; ki < 3; ++ki)
+    for (int ki = 0; ki < 4; ++ki)
       for (int wi = 0; wi < 3; ++wi) {
         float ms = 0;
         if ((rc = time_emit(P, Ks[ki], Ws[wi], st, s, &ms))) { delete P; return rc; }

@@ -311,7 +311,7 @@ def test_mappings_agree_and_are_deterministic():
     outs = []
     try:
         for stage in (2, 1, 0):
-            for K in (4, 8, 16):
+            for K in (4, 6, 8, 16):
                 for waves in (1, 4):
                     ps.ps_set_emit_config(K, waves, stage)
                     _, o = _gpu(b)
