@@ -2012,7 +2012,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 struct EmitConfig {
-  int K = 8;
+  int K = 6;
   int waves = 4;
   int stage = 2;   // 0 rib-major (global records), 1 rib-major (LDS records), 2 role-split
 };
