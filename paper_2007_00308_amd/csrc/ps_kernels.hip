@@ -1701,19 +1701,22 @@ __device__ __forceinline__ int dpp_incl_max(int v) {
 }
 
 constexpr int kCovWaves = 4;   // wavefronts per workgroup
-// chunks of 64 samples whose canvas reads overlap (1: 33 ms, 2: 28 ms, 4:
-// 27 ms on the 4096-path batch at 4096 x 4096)
-constexpr int kCovChunks = 4;
+// A lane takes a group of kCovGroup consecutive samples of one row run, so
+// that laying the samples out over the lanes is paid once per group; chunks
+// of 64 groups per round whose canvas reads overlap
+constexpr int kCovGroup = 4;
+constexpr int kCovChunks = 1;
 
 // One wavefront per 64 consecutive quads, taken from the end of the rib
 // stream so that later paths land first and most samples need no atomic.
 // The rows of the 64 quads are spread over the lanes by a prefix sum; each
 // row lane finds the row's covered samples exactly (the flip index of every
 // crossing edge, by the same FP64 side test a per-sample evaluation makes)
-// as at most two runs.  The samples of 64 rows are then laid end to end and
-// taken 64 at a time: every row marks where its samples start in a per-wave
-// LDS slot array, a max-scan over the marks gives each lane its row, and the
-// lane reads, compares and raises one canvas word.
+// as at most two runs.  The runs of 64 rows are then cut into groups of
+// kCovGroup consecutive samples, laid end to end and taken 64 groups at a
+// time: every row marks where its groups start in a per-wave LDS slot array,
+// a max-scan over the marks gives each lane its row, and the lane reads,
+// compares and raises the group's canvas words.
 template <int MODE>
 __global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
   __shared__ int mark[kCovWaves][64];
@@ -1775,18 +1778,23 @@ __global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
           cov_runs<3>(t2, A.x0, A.W, a1, n1, a2, n2);
         }
       }
-      // this row's samples occupy [st, st + ns) of the wave's laid-out samples;
-      // sample at position g is canvas word (g < bnd ? c1 : c2) + g
-      const int ns = n1 + n2;
-      const int incl2 = dpp_incl_sum(ns);
+      // this row's runs [a1, a1 + n1) and [a2, a2 + n2) make g1 + g2 groups,
+      // positions [st, st + g1 + g2) of the wave's laid-out groups; group g
+      // starts at canvas word c + G g (c = c1 before bnd, else c2) and ends
+      // at its run's end e1 or e2
+      constexpr int G = kCovGroup;
+      const int g1 = (n1 + G - 1) / G, g2 = (n2 + G - 1) / G, ng = g1 + g2;
+      const int incl2 = dpp_incl_sum(ng);
       const int total2 = __shfl(incl2, 63, 64);
-      const int st = incl2 - ns, bnd = st + n1;
-      const int c1 = j * A.W + a1 - st, c2 = j * A.W + a2 - bnd;
-      // kCovChunks chunks of 64 samples per round, so that their canvas reads
+      const int st = incl2 - ng, bnd = st + g1;
+      const int rowbase = j * A.W;
+      const int c1 = rowbase + a1 - G * st, c2 = rowbase + a2 - G * bnd;
+      const int e1 = rowbase + a1 + n1, e2 = rowbase + a2 + n2;
+      // kCovChunks chunks of 64 groups per round, so that their canvas reads
       // are all in flight before any result is needed
       int carry = 0;
       for (int base2 = 0; base2 < total2; base2 += 64 * kCovChunks) {
-        int idx[kCovChunks], sp[kCovChunks];
+        int w0[kCovChunks], wl[kCovChunks], sp[kCovChunks];
         bool act[kCovChunks];
 #pragma unroll
         for (int u = 0; u < kCovChunks; ++u) {
@@ -1794,7 +1802,7 @@ __global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
           mark[wv][lane] = 0;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
-          if (ns > 0 && st >= b2 && st < b2 + 64) mark[wv][st - b2] = lane + 1;
+          if (ng > 0 && st >= b2 && st < b2 + 64) mark[wv][st - b2] = lane + 1;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1802,21 +1810,29 @@ __global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
           const int o2 = m > 0 ? m - 1 : carry;
           carry = __shfl(o2, 63, 64);
           const int g = b2 + lane;
-          const int sb = __shfl(bnd, o2, 64), s1 = __shfl(c1, o2, 64), s2 = __shfl(c2, o2, 64);
+          const int sb = __shfl(bnd, o2, 64);
+          const int s1 = __shfl(c1, o2, 64), s2 = __shfl(c2, o2, 64);
+          const int t1 = __shfl(e1, o2, 64), t2 = __shfl(e2, o2, 64);
           sp[u] = __shfl(qp, o2, 64);
           act[u] = g < total2;
-          idx[u] = (g < sb ? s1 : s2) + g;
+          w0[u] = (g < sb ? s1 : s2) + G * g;   // first word of the group
+          wl[u] = (g < sb ? t1 : t2) - 1;       // last word of its run
           __builtin_amdgcn_wave_barrier();
         }
-        // unconditional reads (a lane past the end reads word 0), so that
-        // neither waits inside a branch of its own
-        int cur[kCovChunks];
+        // unconditional reads (a lane past the end reads word 0; a short
+        // group re-reads its run's last word), so that none waits inside a
+        // branch of its own
+        int cur[kCovChunks][G];
 #pragma unroll
-        for (int u = 0; u < kCovChunks; ++u) cur[u] = A.top[act[u] ? idx[u] : 0];
+        for (int u = 0; u < kCovChunks; ++u)
+#pragma unroll
+          for (int k = 0; k < G; ++k) cur[u][k] = A.top[act[u] ? min(w0[u] + k, wl[u]) : 0];
         // values only grow, so a stale read costs at most a redundant atomic
 #pragma unroll
         for (int u = 0; u < kCovChunks; ++u)
-          if (act[u] && cur[u] < sp[u]) atomicMax(A.top + idx[u], sp[u]);
+#pragma unroll
+          for (int k = 0; k < G; ++k)
+            if (act[u] && w0[u] + k <= wl[u] && cur[u][k] < sp[u]) atomicMax(A.top + w0[u] + k, sp[u]);
       }
     }
   }
