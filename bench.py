@@ -224,6 +224,13 @@ def main() -> int:
                "sample": f"the full workload ({b.n_paths} paths, {V} vertices), {passes} passes, "
                          f"{cpu_s:.3f} s each (output allocation included)"}
         log(f"oracle: {cpu_s:.2f} s ({V / cpu_s / 1e6:.1f} M vertices/s)")
+        # and one pass on a single thread, for the per-core rate
+        t3 = time.perf_counter()
+        del ref
+        ref = oracle.stroke(b, nthreads=1)
+        one_s = time.perf_counter() - t3
+        cpu["one_thread"] = {"value": V / one_s, "unit": "vertices/s", "s_per_pass": one_s}
+        log(f"oracle, 1 thread: {one_s:.2f} s ({V / one_s / 1e6:.1f} M vertices/s)")
         counts_equal = bool(np.array_equal(plan.link_ribs[:db.n_links].cpu().numpy(), ref["link_ribs"]))
         vx = plan.vx[:V].cpu().numpy(); vy = plan.vy[:V].cpu().numpy(); vs = plan.vs[:V].cpu().numpy()
         verr = np.hypot(vx - ref["vx"], vy - ref["vy"])
