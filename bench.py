@@ -366,7 +366,7 @@ def study_c5(args, torch, ps, W, dev):
             e1.record(stream)
             torch.cuda.synchronize()
             emit_ms[name] = e0.elapsed_time(e1) / args.steps
-        ps.ps_set_emit_config(6, 4, 2)   # the default mapping
+        ps.ps_set_emit_config(7, 4, 2)   # the default mapping
         plan.close()
         V = 2 * R
         row = {"q": f"pi/{qn}", "ribs": R, "vertices": V, "ms_per_step": ms,
@@ -408,7 +408,7 @@ def study_emit(args, torch, ps, W, dev):
     P, cap, ws = plan.params, 2 * R, plan.ws
     rows = []
     for stage in (1, 2):
-        for K in (4, 6, 8, 16):
+        for K in (4, 6, 7, 8, 16):
             for waves in (1, 2, 4):
                 ps.ps_set_emit_config(K, waves, stage)
                 row = {"stage": stage, "K": K, "waves": waves,
@@ -418,7 +418,7 @@ def study_emit(args, torch, ps, W, dev):
                        "ms_s": timed(lambda: ps.ps_arclen(db, P, plan.offsets, plan.vs, cap, ws))}
                 rows.append(row)
                 log(str(row))
-    ps.ps_set_emit_config(6, 4, 2)   # the default mapping
+    ps.ps_set_emit_config(7, 4, 2)   # the default mapping
     plan.close()
     print(json.dumps({"study": "emit", "ribs": R, "rows": rows}), flush=True)
     return 0

@@ -319,13 +319,13 @@ int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_p
 
 /*
  * Emit mapping for the unplanned calls: each wavefront tile is K iterations of
- * 64 consecutive ribs (K = 4, 6, 8 or 16) and workgroups hold 1..4 wavefronts.
+ * 64 consecutive ribs (K = 4, 6, 7, 8 or 16) and workgroups hold 1..4 wavefronts.
  * stage selects how a tile is walked: 0 rib-major with link records read
  * from global memory per rib, 1 rib-major with the records staged in LDS,
  * 2 role-split (records in LDS; the tile's segment ribs and its join and cap
  * ribs are swept separately, so a wavefront never mixes the two); -1 keeps
  * the current choice.  0 for K or waves keeps the current value.  The default
- * is K = 6, 4 wavefronts, role-split.  Output bits do not depend on the mapping.
+ * is K = 7, 4 wavefronts, role-split.  Output bits do not depend on the mapping.
  */
 int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group, int32_t stage);
 

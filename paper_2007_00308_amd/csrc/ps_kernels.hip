@@ -2028,7 +2028,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 struct EmitConfig {
-  int K = 6;
+  int K = 7;
   int waves = 4;
   int stage = 2;   // 0 rib-major (global records), 1 rib-major (LDS records), 2 role-split
 };
@@ -2176,6 +2176,7 @@ EmitLaunch pick_k(int K) {
   switch (K) {
     case 4: return emit_launcher<4, PREC, WXY, WS, MAP>;
     case 6: return emit_launcher<6, PREC, WXY, WS, MAP>;
+    case 7: return emit_launcher<7, PREC, WXY, WS, MAP>;
     case 8: return emit_launcher<8, PREC, WXY, WS, MAP>;
     case 16: return emit_launcher<16, PREC, WXY, WS, MAP>;
     default: return nullptr;
@@ -2207,7 +2208,7 @@ EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws, int map) {
   }
 }
 
-bool valid_k(int K) { return K == 4 || K == 6 || K == 8 || K == 16; }
+bool valid_k(int K) { return K == 4 || K == 6 || K == 7 || K == 8 || K == 16; }
 
 // Largest Newton step (in t) accepted when polishing an FP32 root in FP64;
 // a larger step means the FP32 root was ill-conditioned and the rib is
@@ -2427,7 +2428,7 @@ size_t ps_workspace_bytes(const ps_batch* b, const ps_params* p, int64_t vertex_
 }
 
 int ps_set_emit_config(int32_t K, int32_t waves, int32_t stage) {
-  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 4, 6, 8 or 16");
+  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 4, 6, 7, 8 or 16");
   if (waves < 0 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   if (stage < -1 || stage > 2) return fail(PS_E_ARG, "stage must be -1 (keep), 0, 1 or 2");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -2623,10 +2624,10 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
     tune = g_autotune;
   }
   float best = 1e30f;
-  const int Ks[4] = {4, 6, 8, 16};
+  const int Ks[5] = {4, 6, 7, 8, 16};
   const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
   for (int st = 2; tune && st >= 0; --st)
-    for (int ki = 0; ki < 4; ++ki)
+    for (int ki = 0; ki < 5; ++ki)
       for (int wi = 0; wi < 3; ++wi) {
         float ms = 0;
         if ((rc = time_emit(P, Ks[ki], Ws[wi], st, s, &ms))) { delete P; return rc; }

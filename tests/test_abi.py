@@ -89,7 +89,7 @@ def test_bad_precision_and_emit_config_rejected():
     assert lib.ps_set_emit_config(8, 99, -1) == ps.PS_E_ARG
     assert lib.ps_set_emit_config(8, 5, -1) == ps.PS_E_ARG   # above the 256-thread launch bound
     assert lib.ps_set_emit_config(8, 4, 3) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(6, 4, 2) == ps.PS_OK
+    assert lib.ps_set_emit_config(7, 4, 2) == ps.PS_OK
     assert lib.ps_set_emit_config(0, 0, -1) == ps.PS_OK
     assert lib.ps_set_plan_autotune(2) == ps.PS_E_ARG
     assert lib.ps_set_plan_autotune(-1) == ps.PS_E_ARG

@@ -311,13 +311,13 @@ def test_mappings_agree_and_are_deterministic():
     outs = []
     try:
         for stage in (2, 1, 0):
-            for K in (4, 6, 8, 16):
+            for K in (4, 6, 7, 8, 16):
                 for waves in (1, 4):
                     ps.ps_set_emit_config(K, waves, stage)
                     _, o = _gpu(b)
                     outs.append(((K, waves, stage), _np(o["vx"]), _np(o["vy"]), _np(o["vs"])))
     finally:
-        ps.ps_set_emit_config(6, 4, 2)   # the default mapping
+        ps.ps_set_emit_config(7, 4, 2)   # the default mapping
     for cfg, vx, vy, vs in outs[1:]:
         assert np.array_equal(vx, outs[0][1]) and np.array_equal(vy, outs[0][2]), cfg
         assert np.array_equal(vs, outs[0][3]), cfg
