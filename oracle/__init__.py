@@ -17,27 +17,44 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "polar_oracle.cpp")
 _LIB_PATH = os.path.join(_HERE, "libpolar_oracle.so")
+_SAN_LIB_PATH = os.path.join(_HERE, "libpolar_oracle_san.so")
 _lib = None
 
 ROLE_SEGMENT, ROLE_JOIN, ROLE_START_CAP, ROLE_END_CAP = 0, 1, 2, 3
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (FP64, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with g++ (FP64, no FMA contraction, no fast-math).
+
+    sanitize=True builds a separate copy instrumented with AddressSanitizer and
+    UndefinedBehaviorSanitizer (CPU only, for the tests).  A process loads that
+    copy instead of the plain one when PS_ORACLE_SANITIZE=1 is set, and needs
+    the ASan runtime preloaded (LD_PRELOAD, see asan_runtime())."""
+    out = _SAN_LIB_PATH if sanitize else _LIB_PATH
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        flags = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                 "-pthread"]
+        if sanitize:
+            flags += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                      "-fno-sanitize-recover=undefined"]
+        subprocess.check_call(["g++", *flags, _SRC, "-o", tmp])
+        os.replace(tmp, out)
+    return out
+
+
+def asan_runtime() -> str:
+    """Path of g++'s ASan runtime, for LD_PRELOAD of a process that loads the
+    sanitized oracle."""
+    return subprocess.check_output(["g++", "-print-file-name=libasan.so"], text=True).strip()
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB_PATH)
+        sanitize = os.environ.get("PS_ORACLE_SANITIZE") == "1"
+        path = build(force=False, sanitize=sanitize)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_int] + [P] * 9 + [ctypes.c_double, P, ctypes.c_int]
         lib.oracle_count.restype = ctypes.c_int
@@ -195,6 +212,8 @@ def dash(rib_begin: np.ndarray, vx: np.ndarray, vy: np.ndarray, vs: np.ndarray, 
     pat = np.ascontiguousarray(pattern, np.float64)
     if len(pat) < 2 or len(pat) % 2 or not (pat.sum() > 0):
         raise ValueError("bad dash pattern")
+    if not (0 <= phase <= 2.0 ** 40 * pat.sum()):
+        raise ValueError("dash phase must be in [0, 2^40 periods]")
     cap = 16
     while True:
         dx = np.zeros(2 * cap); dy = np.zeros(2 * cap); ds = np.zeros(cap)
@@ -203,6 +222,8 @@ def dash(rib_begin: np.ndarray, vx: np.ndarray, vy: np.ndarray, vs: np.ndarray, 
         n = _load().oracle_dash(len(rib_begin) - 1, _p(rib_begin), _p(vx), _p(vy), _p(vs), _p(pat),
                                 len(pat), ctypes.c_double(phase), _p(dx), _p(dy), _p(ds), _p(rng),
                                 cap, cap, _p(nd))
+        if n == np.iinfo(np.int64).min:
+            raise ValueError("a step lies beyond 2^50 dash periods or spans more than 2^20")
         if n >= 0 and nd[0] <= cap:
             return dict(dx=dx[:2 * n], dy=dy[:2 * n], ds=ds[:n], ranges=rng[:2 * nd[0]].reshape(-1, 2))
         cap = max(2 * cap, int(abs(n)) + 1, int(nd[0]) + 1)

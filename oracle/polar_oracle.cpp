@@ -865,6 +865,8 @@ int oracle_segment_intervals(int kind, const double* px, const double* py, doubl
 // ribs: dx/dy [2*cap_ribs] (N then P vertex), ds [cap_ribs]; dash d spans
 // output ribs [range[2d], range[2d+1]).  Returns the number of output ribs
 // (negative on capacity overflow); *n_dashes receives the dash count.
+const int64_t kDashOutOfRange = INT64_MIN;
+
 int64_t oracle_dash(int n_paths, const int64_t* path_rib_begin, const float* vx, const float* vy,
                     const float* vs, const double* pattern, int n_pattern, double phase,
                     double* dx, double* dy, double* ds, int64_t* range, int64_t cap_ribs,
@@ -872,6 +874,10 @@ int64_t oracle_dash(int n_paths, const int64_t* path_rib_begin, const float* vx,
   double period = 0;
   for (int i = 0; i < n_pattern; ++i) period += pattern[i];
   if (n_pattern < 2 || (n_pattern & 1) || !(period > 0)) return -1;
+  // the phase is at most 2^40 periods, and a step may not end 2^50 periods or
+  // more into the pattern or span more than 2^20 periods: within these bounds
+  // the period count m below is exact and every boundary loop ends
+  if (!(phase >= 0 && phase <= std::ldexp(period, 40))) return -1;
   std::vector<double> cum(n_pattern + 1, 0.0);
   for (int i = 0; i < n_pattern; ++i) cum[i + 1] = cum[i] + pattern[i];
   int64_t out = 0, nd = 0;
@@ -900,6 +906,8 @@ int64_t oracle_dash(int n_paths, const int64_t* path_rib_begin, const float* vx,
     if (on) put(vx[2 * rb], vy[2 * rb], vx[2 * rb + 1], vy[2 * rb + 1], vs[rb]);
     for (int64_t j = rb + 1; j < re; ++j) {
       double u0 = (double)vs[j - 1] + phase, u1 = (double)vs[j] + phase;
+      if (u1 > u0 && !(u1 < std::ldexp(period, 50) && u1 - u0 <= std::ldexp(period, 20)))
+        return kDashOutOfRange;
       if (u1 > u0) {
         // boundaries u_b = m*period + cum[i] with u0 < u_b <= u1, in order
         double m = std::floor(u0 / period);

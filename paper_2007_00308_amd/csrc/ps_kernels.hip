@@ -39,6 +39,7 @@ constexpr int kMinTileRibs = 64 * 1 - 1;              // smallest emit tile (K =
 constexpr double kFix = 4294967296.0;                 // arc length in fixed point: 2^-32 px
 constexpr unsigned long long kValMask = (1ull << 62) - 1;
 constexpr int kMaxDash = 64;
+constexpr double kMaxDashPhase = 1099511627776.0;      // 2^40 periods
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -1839,8 +1840,11 @@ __global__ void __launch_bounds__(256) coverage_kernel(CovArgs A) {
 }
 
 // ===========================================================================
-// Dash (Sec. "Dashing")
+// Dash (Sec. "Dashing").  Boundary positions, pattern states and the
+// interpolation are plain IEEE operations without FMA contraction, so a given
+// rib stream is cut at the same places whoever computes it.
 // ===========================================================================
+#pragma clang fp contract(off)
 struct DashArgs {
   const int64_t* off;        // link offsets [n_links+1]
   int64_t n_links;
@@ -1859,6 +1863,7 @@ struct DashArgs {
   int64_t* range;
   int64_t rib_cap;
   int64_t dash_cap;
+  int64_t max_ribs;          // ribs the input stream (and the per-rib scratch) can hold
   DevStatus* st;
   double phase;
   int n_pat;
@@ -1889,16 +1894,19 @@ __device__ __forceinline__ bool dash_on(const DashArgs& A, double u) {
   return (idx & 1) == 0;
 }
 
-// visit the boundaries u_b = m*period + cum[i] with u0 < u_b <= u1 in order
-// Steps longer than kMaxDashPeriods periods, or non-finite, are left undashed
-// (and flagged) so the loop is always bounded.
-constexpr double kMaxDashPeriods = 1048576.0;
+// visit the boundaries u_b = m*period + cum[i] with u0 < u_b <= u1 in order.
+// Steps longer than kMaxDashPeriods periods, steps ending kMaxDashU periods or
+// more into the pattern, and non-finite ones are left undashed (and flagged):
+// below kMaxDashU periods the period index m stays exact and u_b grows by at
+// least 3/4 of a period per step of m, so the loop always ends.
+constexpr double kMaxDashPeriods = 1048576.0;            // 2^20
+constexpr double kMaxDashU = 1125899906842624.0;         // 2^50
 
 template <class Fn>
 __device__ __forceinline__ void dash_boundaries(const DashArgs& A, double u0, double u1, Fn fn) {
   if (!(u1 > u0)) return;
   const double per = A.cum[A.n_pat];
-  if (!isfinite(u0) || !isfinite(u1) || (u1 - u0) > kMaxDashPeriods * per) {
+  if (!isfinite(u0) || !isfinite(u1) || (u1 - u0) > kMaxDashPeriods * per || !(u1 < kMaxDashU * per)) {
     atomicOr(&A.st->flags, (unsigned)PS_STATUS_DASH_OVERFLOW);
     return;
   }
@@ -1922,8 +1930,18 @@ __global__ void reset_dash_status_kernel(DevStatus* st) {
   }
 }
 
+// The rib stream holds R = offsets[n_links] ribs; if that exceeds the vertex
+// capacity the workspace was sized with (the emit overflowed), nothing is
+// read or written and the dash reports an overflow.
+__device__ __forceinline__ bool dash_input_fits(const DashArgs& A, int64_t R) {
+  if (R <= A.max_ribs) return true;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&A.st->flags, (unsigned)PS_STATUS_DASH_OVERFLOW);
+  return false;
+}
+
 __global__ void __launch_bounds__(256) dash_count_kernel(DashArgs A) {
   const int64_t R = A.off[A.n_links];
+  if (!dash_input_fits(A, R)) return;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
        r += (int64_t)gridDim.x * blockDim.x) {
     const int p = rib_path(A, r);
@@ -1948,6 +1966,7 @@ __global__ void __launch_bounds__(256) dash_count_kernel(DashArgs A) {
 
 __global__ void __launch_bounds__(256) dash_emit_kernel(DashArgs A) {
   const int64_t R = A.off[A.n_links];
+  if (!dash_input_fits(A, R)) return;
   const int64_t tot_r = A.rib_pos[R], tot_d = A.dash_pos[R];
   const int64_t tid0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool over = tot_r > A.rib_cap || tot_d > A.dash_cap;
@@ -2001,6 +2020,8 @@ __global__ void __launch_bounds__(256) dash_emit_kernel(DashArgs A) {
     if (on && r + 1 == path_end) A.range[2 * (dn - 1) + 1] = o;
   }
 }
+
+#pragma clang fp contract(on)
 
 }  // namespace
 
@@ -2072,6 +2093,8 @@ int check_params(const ps_params* p) {
     if (!(sum > 0)) return fail(PS_E_ARG, "dash pattern sums to zero");
     if (!(p->dash_phase >= 0) || !std::isfinite(p->dash_phase))
       return fail(PS_E_ARG, "dash phase must be finite and >= 0");
+    if (!(p->dash_phase <= kMaxDashPhase * sum))
+      return fail(PS_E_ARG, "dash phase must be at most 2^40 pattern periods");
   }
   return PS_OK;
 }
@@ -2269,6 +2292,7 @@ int launch_dash(const ps_batch* b, const ps_params* p, const int64_t* off, const
   a.vx = vx; a.vy = vy; a.vs = vs; a.cnt_r = v.dash_r; a.cnt_d = v.dash_d;
   a.rib_pos = v.dash_rpos; a.dash_pos = v.dash_dpos;
   a.dx = dx; a.dy = dy; a.ds = ds; a.range = range; a.rib_cap = rib_cap; a.dash_cap = dash_cap;
+  a.max_ribs = w.max_ribs;
   a.st = v.st; a.phase = p->dash_phase; a.n_pat = p->n_dash;
   a.cum[0] = 0;
   for (int i = 0; i < p->n_dash; ++i) a.cum[i + 1] = a.cum[i] + p->dash[i];

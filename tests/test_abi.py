@@ -80,6 +80,19 @@ def test_bad_dash_rejected(dash):
     assert rc == ps.PS_E_ARG
 
 
+def test_dash_phase_beyond_2_40_periods_rejected():
+    # the boundary walk counts periods in FP64; beyond 2^40 periods of phase
+    # it could stall, so such a phase is refused before anything is queued
+    lib = ps.load()
+    b = _batch()
+    ok = ps.make_params(0.1, dash=(5e-4, 5e-4), dash_phase=1e-3 * 2.0 ** 40)
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(ok), 0x1000, 0x1000, 1 << 30, None) != ps.PS_E_ARG or \
+        b"phase" not in lib.ps_last_error()
+    bad = ps.make_params(0.1, dash=(5e-4, 5e-4), dash_phase=1e15)
+    assert lib.ps_count(ctypes.byref(b), ctypes.byref(bad), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
+    assert b"2^40" in lib.ps_last_error()
+
+
 def test_bad_precision_and_emit_config_rejected():
     lib = ps.load()
     b = _batch()
@@ -147,3 +160,4 @@ def test_coverage_rejects_a_canvas_of_2_31_pixels():
     cv = ps.ps_canvas(0.0, 0.0, 65536, 32768, 0)
     assert lib.ps_coverage(ctypes.byref(b), 0x1000, 0x1000, 0x1000, 4, ctypes.byref(cv), 0x1000, None) == ps.PS_E_ARG
     assert b"2^31" in lib.ps_last_error()
+

@@ -30,10 +30,36 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _arc_tol(ref_s):
-    # FP32 output of s: half an ulp of the largest value, plus accumulated
-    # chord rounding (relative 1e-6)
-    return float(np.spacing(np.float32(max(1.0, ref_s.max())))) + 1e-6 * float(ref_s.max())
+# Arc length per rib (Eq. arc-length-approximation): the GPU sums chords of its
+# FP64 rib points, each rounded to 2^-32 px (at most 2^-33 off), as exact
+# integers, and rounds the sum once to FP32.  The bound at a rib k chords into
+# its path is one FP32 spacing of s (the final rounding, counted in full to
+# cover the oracle's own FP64 sum) plus 2^-30 px per chord (the fixed-point
+# rounding and the FP64 chord difference between the two sides' points).
+ARC_PER_CHORD = 2.0 ** -30
+
+
+def _arc_tol(ref_s, k):
+    ref_s = np.asarray(ref_s, np.float64)
+    return np.spacing(np.abs(ref_s).astype(np.float32)).astype(np.float64) + (k + 1) * ARC_PER_CHORD
+
+
+def _rib_index_in_path(b, off):
+    """For every rib: how many ribs of its path come before it."""
+    first = oracle.path_rib_begin(b, off)
+    R = int(off[-1])
+    owner = np.repeat(np.arange(b.n_paths), np.diff(first))
+    return np.arange(R, dtype=np.int64) - first[owner]
+
+
+def _check_arc(vs_gpu, ref_s, k, what=""):
+    vs_gpu = np.asarray(vs_gpu, np.float64)
+    err = np.abs(vs_gpu - ref_s)
+    tol = _arc_tol(ref_s, k)
+    bad = np.flatnonzero(err > tol)
+    assert bad.size == 0, (f"{what} arc length off at {bad.size} ribs; first rib {bad[0]}: "
+                           f"gpu {vs_gpu[bad[0]]!r} oracle {ref_s[bad[0]]!r} tol {tol[bad[0]]:.3e}")
+    return float(err.max()) if err.size else 0.0
 
 
 def _compare(b, precision=ps.PS_PREC_FP64, vertex_tol=VERTEX_TOL, check_s=True):
@@ -55,8 +81,7 @@ def _compare(b, precision=ps.PS_PREC_FP64, vertex_tol=VERTEX_TOL, check_s=True):
     if check_s and R:
         vs = _np(out["vs"]).astype(np.float64)
         assert np.array_equal(vs[0::2], vs[1::2])
-        s_err = float(np.abs(vs[0::2] - ref["vs"]).max())
-        assert s_err <= _arc_tol(ref["vs"]), f"arc length error {s_err:.3e}"
+        s_err = _check_arc(vs[0::2], ref["vs"], _rib_index_in_path(b, ref["offsets"]))
     return dict(R=R, vmax=float(err.max()) if err.size else 0.0, smax=s_err, fixups=st.fixups)
 
 
@@ -91,7 +116,7 @@ def test_config2_full_in_the_bench_mapping():
                    _np(plan.vy[:2 * R]).astype(np.float64) - ref["vy"])
     assert err.max() <= VERTEX_TOL, err.max()
     vs = _np(plan.vs[:2 * R]).astype(np.float64)
-    assert np.abs(vs[0::2] - ref["vs"]).max() <= _arc_tol(ref["vs"])
+    _check_arc(vs[0::2], ref["vs"], _rib_index_in_path(b, ref["offsets"]), "config 2")
     plan.close()
 
 
@@ -122,7 +147,7 @@ def test_config5_full_sampled():
         err = np.hypot(vx - ref["vx"][2 * ra:2 * re], vy - ref["vy"][2 * ra:2 * re])
         assert err.max() <= VERTEX_TOL, (p, err.max())
         vs = _np(out["vs"][2 * a:2 * e:2]).astype(np.float64)
-        assert np.abs(vs - ref["vs"][ra:re]).max() <= _arc_tol(ref["vs"][ra:re]), p
+        _check_arc(vs, ref["vs"][ra:re], np.arange(re - ra), f"path {p}")
 
 
 def test_config3_full_path():
@@ -362,20 +387,46 @@ def test_dash_exact_on_axis_lines():
     np.testing.assert_array_equal(_np(out["ds"])[0::2], dref["ds"].astype(np.float32))
 
 
-def test_dash_config3_unique_quantities():
-    b = W.config3(n_segs=600)
+def _dash_same_stream(b, out, pattern, phase):
+    """The oracle's dasher run on the GPU's own FP32 rib stream: ranges must be
+    identical and every output vertex and arc length within the vertex bar
+    (both sides cut the same stream with the same FP64 operations)."""
+    pr = oracle.path_rib_begin(b, _np(out["offsets"]))
+    dref = oracle.dash(pr, _np(out["vx"]), _np(out["vy"]), _np(out["vs"])[0::2], list(pattern), phase)
+    rng = _np(out["dash_range"])
+    np.testing.assert_array_equal(rng, dref["ranges"])
+    dx, dy = _np(out["dx"]).astype(np.float64), _np(out["dy"]).astype(np.float64)
+    ds = _np(out["ds"]).astype(np.float64)
+    assert dx.shape == dref["dx"].shape and ds.shape[0] == 2 * dref["ds"].shape[0]
+    assert np.array_equal(ds[0::2], ds[1::2])
+    err = np.hypot(dx - dref["dx"], dy - dref["dy"])
+    assert err.max() <= VERTEX_TOL, err.max()
+    np.testing.assert_allclose(ds[0::2], dref["ds"], rtol=0, atol=VERTEX_TOL)
+    return dref
+
+
+def _dash_own_streams(b, out, pattern, phase):
+    """Secondary check: the oracle dashing its own rib stream.  Each side cuts
+    its own stream, so an FP32 arc length half an ulp apart can move a cut by a
+    rib; the dash count and the cut positions must still agree."""
     ref = oracle.stroke(b)
     pr = oracle.path_rib_begin(b, ref["offsets"])
-    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], list(b.dash), b.dash_phase)
-    _, out = _gpu(b, dash=b.dash, dash_phase=b.dash_phase)
+    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], list(pattern), phase)
     rng = _np(out["dash_range"])
-    ds = _np(out["ds"])[0::2].astype(np.float64)
     assert rng.shape == dref["ranges"].shape
-    # dash start / end arc lengths are the pattern's boundaries
+    ds = _np(out["ds"])[0::2].astype(np.float64)
     np.testing.assert_allclose(ds[rng[:, 0]], dref["ds"][dref["ranges"][:, 0]], atol=0.05)
     np.testing.assert_allclose(ds[rng[:, 1] - 1], dref["ds"][dref["ranges"][:, 1] - 1], atol=0.05)
-    dx = _np(out["dx"]).astype(np.float64)
-    np.testing.assert_allclose(dx[2 * rng[:, 0]], dref["dx"][2 * dref["ranges"][:, 0]], atol=0.05)
+    return rng
+
+
+def test_dash_config3_full_path():
+    # the whole 5,000-cubic walk with its [10 on, 5 off] pattern
+    b = W.config3()
+    _, out = _gpu(b, dash=b.dash, dash_phase=b.dash_phase)
+    dref = _dash_same_stream(b, out, b.dash, b.dash_phase)
+    assert dref["ranges"].shape[0] > 10_000
+    _dash_own_streams(b, out, b.dash, b.dash_phase)
 
 
 def test_dash_overflow_then_retry_fits():
@@ -419,21 +470,43 @@ def test_dash_mixed_batch_with_closed_paths_and_external_conics():
         closed[p] = 1
     b.closed = closed
     pattern, phase = (7.0, 3.0, 2.0, 3.0), 1.5
-    ref = oracle.stroke(b)
-    pr = oracle.path_rib_begin(b, ref["offsets"])
-    dref = oracle.dash(pr, ref["vx"], ref["vy"], ref["vs"], list(pattern), phase)
     _, out = _gpu(b, dash=pattern, dash_phase=phase)
-    rng = _np(out["dash_range"])
-    assert rng.shape == dref["ranges"].shape and rng.shape[0] > 100
-    ds = _np(out["ds"])[0::2].astype(np.float64)
-    np.testing.assert_allclose(ds[rng[:, 0]], dref["ds"][dref["ranges"][:, 0]], atol=0.05)
-    np.testing.assert_allclose(ds[rng[:, 1] - 1], dref["ds"][dref["ranges"][:, 1] - 1], atol=0.05)
-    dx, dy = _np(out["dx"]).astype(np.float64), _np(out["dy"]).astype(np.float64)
-    for col in (0, 1):
-        i = 2 * (rng[:, col] - col) + 1
-        j = 2 * (dref["ranges"][:, col] - col) + 1
-        np.testing.assert_allclose(dx[i], dref["dx"][j], atol=0.05)
-        np.testing.assert_allclose(dy[i], dref["dy"][j], atol=0.05)
+    dref = _dash_same_stream(b, out, pattern, phase)
+    assert dref["ranges"].shape[0] > 100
+    _dash_own_streams(b, out, pattern, phase)
+
+
+def test_dash_after_an_emit_overflow_touches_nothing():
+    # an emit whose capacity is too small writes nothing; a dash over that
+    # stream must then read and write nothing either (it reports an overflow)
+    import torch
+    b = W.config3(n_segs=100)
+    db = ps.DeviceBatch(b)
+    params = ps.make_params(b.q, dash=b.dash, dash_phase=b.dash_phase)
+    link_ribs = torch.empty(db.n_links, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(db.n_links + 1, dtype=torch.int64, device="cuda")
+    ref_R = int(oracle.offsets(oracle.count(b))[-1])
+    cap = 2 * (ref_R // 2)                      # half the ribs fit
+    need = ps.ps_workspace_bytes(db, params, cap)
+    guard = 4096
+    ws_all = ps.alloc_workspace(need + guard, "cuda")
+    ws_all.fill_(0xA5)
+    ws = ws_all[:need]
+    ps.ps_count(db, params, link_ribs, ws)
+    ps.ps_scan(link_ribs, db.n_links, offsets, ws)
+    vx = torch.zeros(cap, device="cuda"); vy = torch.zeros_like(vx); vs = torch.zeros_like(vx)
+    ps.ps_emit(db, params, offsets, vx, vy, vs, cap, ws)
+    assert ps.ps_read_status(ws).flags & ps.PS_STATUS_OVERFLOW
+    n = 64
+    dx = torch.full((2 * n + 64,), 777.0, device="cuda"); dy = dx.clone(); ds = dx.clone()
+    rng = torch.full((2 * n + 64,), -5, dtype=torch.int64, device="cuda")
+    ps.ps_dash(db, params, offsets, vx, vy, vs, cap, dx, dy, ds, rng, n, n, ws)
+    st = ps.ps_read_status(ws)
+    assert st.flags & ps.PS_STATUS_DASH_OVERFLOW
+    for t in (dx, dy, ds):
+        assert bool(torch.all(t == 777.0))
+    assert bool(torch.all(rng == -5))
+    assert bool(torch.all(ws_all[need:] == 0xA5))
 
 
 # ------------------------------------------------------------------ plan / graph

@@ -461,6 +461,33 @@ def test_collinear_fold_is_a_cusp():
     np.testing.assert_allclose([iv[1][0], iv[3][0]], turns, atol=2e-6)
 
 
+def test_collinear_quadratic_fold():
+    # Q (0,0), (20,0), (10,0): g(t) = (40t - 30t^2, 0) runs out to x = 40/3 at
+    # t = 2/3, where g' = 40 - 60t vanishes, and back to 10.  One fold: flat,
+    # a +pi pivot of ceil(pi/q) steps at t = 2/3, flat (R10).
+    pts = [(0, 0), (20, 0), (10, 0)]
+    q = math.pi / 16
+    iv = oracle.segment_intervals(W.KIND_Q, pts, q)
+    assert [v[4] for v in iv] == [1, 16, 1]
+    assert [v[3] for v in iv] == [0.0, math.pi, 0.0]
+    assert iv[1][0] == iv[1][1]
+    # the fold is where the densely sampled x velocity changes sign
+    ts = np.linspace(0, 1, 1_000_001)
+    x = G.point(W.KIND_Q, pts, ts)[:, 0]
+    turns = ts[1:-1][np.sign(np.diff(x))[1:] != np.sign(np.diff(x))[:-1]]
+    assert turns.size == 1
+    np.testing.assert_allclose(iv[1][0], turns[0], atol=2e-6)
+    # every pivot rib sits at the fold point, the far end of the segment's run
+    b, o = stroke1(W.KIND_Q, pts, q, width=2.0)
+    sl = seg_ribs(o, b)
+    t = o["t"][sl]
+    assert len(t) == 1 + 1 + 16 + 1
+    np.testing.assert_allclose(t[1:18], turns[0], atol=2e-6)
+    Gx = 0.5 * (o["vx"][0::2][sl] + o["vx"][1::2][sl])
+    np.testing.assert_allclose(Gx[1:18], x.max(), atol=1e-9)
+    np.testing.assert_allclose(x.max(), 40.0 / 3.0, atol=1e-9)
+
+
 @pytest.mark.parametrize("pts", [
     [(0, 0), (0, 0), (40, 30), (80, 0)],        # P1 = P0
     [(0, 0), (40, 30), (80, 0), (80, 0)],       # P2 = P3
@@ -627,6 +654,31 @@ def test_uniform_ribs_sit_at_uniform_parameters(case):
     np.testing.assert_allclose(cross[ok], 1.0, atol=1e-5)
 
 
+def test_uniform_rib_on_an_exact_cusp_takes_the_nearby_tangent():
+    # The exact cusp cubic of the golden cases has N = 68 steps, so its uniform
+    # rib 34 sits at t = 1/2, where g' = 0.  Its normal then comes from the
+    # tangent just before the cusp (2^-20/N back into the segment), which is
+    # the direction of motion on the way in: the one-sided chord over
+    # [1/2 - 2e-6, 1/2 - 1e-6] by the independent evaluator.  The way out has
+    # the opposite direction, so taking the other side flips the cross product.
+    c = gold("exact cusp cubic")
+    pts = c["points"]
+    b = W.single(c["kind"], pts, width=3.0, q=math.radians(c["q_deg"]))
+    o = oracle.stroke(b, uniform=True)
+    sl = seg_ribs(o, b)
+    N = sl.stop - sl.start - 1
+    assert N == 68
+    j = N // 2
+    p = G.point(c["kind"], pts, [0.5 - 2e-6, 0.5 - 1e-6, 0.5 + 1e-6, 0.5 + 2e-6])
+    d_in, d_out = p[1] - p[0], p[3] - p[2]
+    d_in /= np.hypot(*d_in); d_out /= np.hypot(*d_out)
+    assert d_in @ d_out < -0.999                     # a cusp: the motion reverses
+    r = sl.start + j
+    n = np.array([o["vx"][2 * r + 1] - o["vx"][2 * r], o["vy"][2 * r + 1] - o["vy"][2 * r]]) / 3.0
+    assert abs(np.hypot(*n) - 1.0) < 1e-12
+    assert d_in[0] * n[1] - d_in[1] * n[0] > 1 - 1e-6
+
+
 # ------------------------------------------------------------------ coverage
 def _samples(W_, H_, x0=0.0, y0=0.0):
     i, j = np.meshgrid(np.arange(W_), np.arange(H_))
@@ -781,3 +833,22 @@ def test_dash_rejects_bad_patterns(pattern):
     o = oracle.stroke(b)
     with pytest.raises(ValueError):
         oracle.dash(oracle.path_rib_begin(b, o["offsets"]), o["vx"], o["vy"], o["vs"], pattern)
+
+
+def test_dash_bounds_the_boundary_walk():
+    # a phase beyond 2^40 periods, or a step ending 2^50 periods into the
+    # pattern, is refused rather than walked (the FP64 period count would stop
+    # advancing and the walk would not end)
+    b = W.path([(W.KIND_L, [(0, 0), (40, 0)], 1.0)], width=2.0)
+    o = oracle.stroke(b)
+    pr = oracle.path_rib_begin(b, o["offsets"])
+    with pytest.raises(ValueError):
+        oracle.dash(pr, o["vx"], o["vy"], o["vs"], [5e-4, 5e-4], 1e15)
+    # (an FP32 arc length that far out moves in steps of 2^27 periods or more,
+    # so such a step also spans more than 2^20 periods)
+    far = np.array([2.0 ** 51, 2.0 ** 51 + 2.0 ** 28], np.float32)
+    with pytest.raises(ValueError):
+        oracle.dash(pr, o["vx"], o["vy"], far, [0.5, 0.5], 0.0)
+    # just inside both bounds it still dashes
+    d = oracle.dash(pr, o["vx"], o["vy"], o["vs"], [10.0, 5.0], 15.0 * 2.0 ** 39)
+    assert d["ranges"].shape[0] == 3
