@@ -287,6 +287,28 @@ int ps_dash(const ps_batch* batch, const ps_params* params, const int64_t* offse
             float* dx, float* dy, float* ds, int64_t* dash_range, int64_t rib_capacity,
             int64_t dash_capacity, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * ps_stroke_static -- ps_count -> ps_scan -> ps_emit (vertices and, when vs is
+ * not NULL, arc length) in one call that allocates nothing and takes no
+ * workspace, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid it).  Its scratch
+ * memory is a 64 MiB array in the library's device code, one per GPU the
+ * library runs on, held until the process ends; batches whose workspace
+ * (ps_workspace_bytes for this vertex_capacity, no dashing) exceeds it are
+ * refused with PS_E_WORKSPACE before anything is queued (the 64-cubic path and
+ * the 5,000-cubic walk fit; the 4,096-path batch does not).  Outputs as those
+ * of ps_count, ps_scan and ps_emit: link_ribs [ps_num_links], offsets
+ * [ps_num_links+1], vx, vy, vs [vertex_capacity], all DEVICE, caller-owned.
+ * status_flags: DEVICE uint32, may be NULL; receives the PS_STATUS_* bits of
+ * this call once the stream reaches its end.  params->n_dash must be 0
+ * (PS_E_UNSUPPORTED otherwise).  The stream must belong to the current
+ * device.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on one GPU (other streams, other threads) race and must not be made.
+ */
+int ps_stroke_static(const ps_batch* batch, const ps_params* params, int32_t* link_ribs,
+                     int64_t* offsets, float* vx, float* vy, float* vs, int64_t vertex_capacity,
+                     uint32_t* status_flags, void* stream);
+
 /* Copy the status word of ws to the host (synchronises `stream`). */
 int ps_read_status(const void* ws, ps_status* out, void* stream);
 

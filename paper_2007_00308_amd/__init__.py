@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH):
                                    _vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, _vp,
                                    ctypes.c_size_t, _vp]),
         "ps_read_status": (ctypes.c_int, [_vp, P(ps_status), _vp]),
+        "ps_stroke_static": (ctypes.c_int, [P(ps_batch), P(ps_params), _vp, _vp, _vp, _vp, _vp,
+                                            ctypes.c_int64, _vp, _vp]),
         "ps_plan_create": (ctypes.c_int, [P(ps_batch), P(ps_params), _vp, _vp, _vp, _vp, _vp,
                                           ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_int64,
                                           ctypes.c_int64, _vp, ctypes.c_size_t, _vp, P(_vp)]),
@@ -227,6 +229,13 @@ def ps_dash(db, params, offsets, vx, vy, vs, vertex_capacity, dx, dy, ds, dash_r
                           _ptr(vy), _ptr(vs), int(vertex_capacity), _ptr(dx), _ptr(dy), _ptr(ds),
                           _ptr(dash_range), int(rib_capacity), int(dash_capacity), _ptr(ws),
                           ws.numel() * ws.element_size(), _stream(stream)), "ps_dash")
+
+
+def ps_stroke_static(db, params, link_ribs, offsets, vx, vy, vs, vertex_capacity, status_flags=None,
+                     stream=None):
+    _check(load().ps_stroke_static(ctypes.byref(db.struct), ctypes.byref(params), _ptr(link_ribs),
+                                   _ptr(offsets), _ptr(vx), _ptr(vy), _ptr(vs), int(vertex_capacity),
+                                   _ptr(status_flags), _stream(stream)), "ps_stroke_static")
 
 
 def ps_read_status(ws, stream=None) -> ps_status:

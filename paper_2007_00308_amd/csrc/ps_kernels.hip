@@ -420,6 +420,18 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
   }
 }
 
+// Scratch memory of ps_stroke_static: the workspace of one count -> scan ->
+// emit chain, for callers that cannot allocate.  Every GPU the library runs
+// on holds its own copy until the process ends.  Host code never uses this
+// name for memory: it takes the array's device address from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+__global__ void copy_status_flags_kernel(const DevStatus* st, uint32_t* out) {
+  if (threadIdx.x == 0) *out = st->flags;
+}
+
 __global__ void reset_status_kernel(DevStatus* st) {
   if (threadIdx.x == 0) {
     st->flags = 0; st->total_ribs = 0; st->fixups = 0; st->dash_ribs = 0; st->dash_count = 0;
@@ -2309,6 +2321,28 @@ int launch_dash(const ps_batch* b, const ps_params* p, const int64_t* off, const
   return PS_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = 0;
+  PS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PS_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PS_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return PS_OK;
+}
+
 EmitConfig current_cfg() {
   std::lock_guard<std::mutex> lk(g_mu);
   return g_cfg;
@@ -2591,6 +2625,31 @@ int ps_dash(const ps_batch* b, const ps_params* p, const int64_t* offsets, const
   if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
   return launch_dash(b, p, offsets, vx, vy, vs, dx, dy, ds, range, rib_cap, dash_cap, ws_view(ws, w), w,
                      (hipStream_t)stream);
+}
+
+int ps_stroke_static(const ps_batch* b, const ps_params* p, int32_t* link_ribs, int64_t* offsets,
+                     float* vx, float* vy, float* vs, int64_t cap, uint32_t* status_flags,
+                     void* stream) {
+  int rc;
+  if ((rc = check_batch(b)) || (rc = check_params(p))) return rc;
+  if (p->n_dash != 0) return fail(PS_E_UNSUPPORTED, "ps_stroke_static does not dash");
+  if (!offsets || !vx || !vy || (!link_ribs && n_links_of(b) > 0)) return fail(PS_E_ARG, "NULL array");
+  if (cap < 0) return fail(PS_E_ARG, "negative capacity");
+  const WsLayout w = ws_layout(n_links_of(b), cap, 0);
+  if (w.total > kStaticScratchBytes)
+    return fail(PS_E_WORKSPACE, "batch needs %zu bytes of scratch; the static scratch holds %zu",
+                w.total, kStaticScratchBytes);
+  void* base = nullptr;
+  if ((rc = static_scratch(&base))) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  const WsView v = ws_view(base, w);
+  const EmitConfig c = current_cfg();
+  if ((rc = launch_count(b, p, link_ribs, v, s))) return rc;
+  if ((rc = do_scan_i32(link_ribs, n_links_of(b), nullptr, offsets, v.scan, &v.st->total_ribs, s))) return rc;
+  if ((rc = launch_emit(b, p, offsets, vx, vy, vs, cap, v, w, c.K, c.waves, c.stage, s))) return rc;
+  if (status_flags) hipLaunchKernelGGL(copy_status_flags_kernel, dim3(1), dim3(64), 0, s, v.st, status_flags);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
 }
 
 int ps_read_status(const void* ws, ps_status* out, void* stream) {

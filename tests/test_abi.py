@@ -161,3 +161,16 @@ def test_coverage_rejects_a_canvas_of_2_31_pixels():
     assert lib.ps_coverage(ctypes.byref(b), 0x1000, 0x1000, 0x1000, 4, ctypes.byref(cv), 0x1000, None) == ps.PS_E_ARG
     assert b"2^31" in lib.ps_last_error()
 
+
+def test_static_chain_refuses_large_batches_and_dashing_on_the_host():
+    # both are decided before any device call
+    lib = ps.load()
+    b = _batch(1000, 1_000_000)
+    p = ps.make_params(0.1)
+    rc = lib.ps_stroke_static(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 0x1000, 0x1000, 0x1000,
+                              1 << 20, None, None)
+    assert rc == ps.PS_E_WORKSPACE and b"static scratch" in lib.ps_last_error()
+    pd = ps.make_params(0.1, dash=(10.0, 5.0))
+    rc = lib.ps_stroke_static(ctypes.byref(_batch()), ctypes.byref(pd), 0x1000, 0x1000, 0x1000, 0x1000,
+                              0x1000, 1 << 10, None, None)
+    assert rc == ps.PS_E_UNSUPPORTED
