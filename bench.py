@@ -73,8 +73,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-per-path", action="store_true", help="skip the per-path form")
     ap.add_argument("--profile", action="store_true", help="few steps, no oracle (for rocprofv3)")
-    ap.add_argument("--emit-config", default=None, metavar="K,W,S",
-                    help="fixed emit mapping (ribs per lane, waves per group, LDS staging) "
+    ap.add_argument("--emit-config", default=None, metavar="M,K,W",
+                    help="fixed emit mapping (PS_MAP_* mapping, ribs per lane, waves per group) "
                          "instead of the plan's autotuning, e.g. for profiles of one mapping")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -117,14 +117,10 @@ def main() -> int:
     del first
     torch.cuda.synchronize()
 
-    if args.emit_config:
-        k_, w_, s_ = (int(x) for x in args.emit_config.split(","))
-        ps.ps_set_emit_config(k_, w_, s_)
-        ps.ps_set_plan_autotune(False)
-    plan = ps.Plan(db, b.q, vertex_capacity=cap, precision=prec)
-    ps.ps_set_plan_autotune(True)
-    K, waves, stage = plan.config()
-    log(f"plan: autotuned emit mapping K={K} waves/group={waves} stage={stage}")
+    emit = tuple(int(x) for x in args.emit_config.split(",")) if args.emit_config else (ps.PS_MAP_DEFAULT, 0, 0)
+    plan = ps.Plan(db, b.q, vertex_capacity=cap, precision=prec, emit=emit)
+    mapping, K, waves = plan.config()
+    log(f"plan: emit mapping {mapping} K={K} waves/group={waves} ({'given' if args.emit_config else 'autotuned'})")
     stream = torch.cuda.current_stream()
 
     # one event pair per timed step around the emit graph, on the stream the
@@ -152,7 +148,6 @@ def main() -> int:
 
     # the emit (tile table + emit kernel) of every timed step, from its events
     emit_ms = sum(a.elapsed_time(c) for a, c in ev) / len(ev)
-    ps.ps_set_emit_config(K, waves, stage)
     emit_bytes = algorithmic_bytes(V, b.n_segs, b.n_paths)
     emit_gbs = emit_bytes / (emit_ms * 1e-3) / 1e9
     log(f"emit call: {emit_ms:.3f} ms, {emit_gbs:.0f} GB/s algorithmic ({emit_gbs / HBM_PEAK_GBS:.1%} of peak)")
@@ -260,11 +255,11 @@ def main() -> int:
         "config": {"workload": "batched: 4096 paths, log-uniform [1,512] segments, 60/25/15% C/Q/K, "
                                "q=pi/64, round joins, butt caps",
                    "paths": b.n_paths, "segments": b.n_segs, "ribs": R, "vertices": V,
-                   "precision": args.precision, "emit_K": K, "emit_waves_per_group": waves,
-                   "emit_stage": stage},
+                   "precision": args.precision, "emit_mapping": mapping, "emit_K": K,
+                   "emit_waves_per_group": waves},
         "gb_per_s": B_alg / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": emit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": emit_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(f"{K},{waves},{stage}"),
+                     "frac": emit_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(f"{mapping},{K},{waves}"),
                      "kernel": "emit (prepare + persistent emit, one ps_emit call)",
                      "ms_per_launch": emit_ms, "algorithmic_bytes_per_launch": emit_bytes},
         "per_path": per_path,
@@ -350,30 +345,29 @@ def study_c5(args, torch, ps, W, dev):
         R = first["total_ribs"]
         del first
         plan = ps.Plan(db, q, vertex_capacity=2 * R)
-        K, waves, stage = plan.config()
+        cfg = plan.config()
         ms = _time_plan(torch, plan, args.steps, args.warmup)
-        # the emit call alone: the autotuned mapping vs a fixed one (K=8, 4 waves, staged)
+        # the emit call alone: the autotuned mapping vs a fixed one (tiles, K=8, 4 waves)
         stream = torch.cuda.current_stream()
         emit_ms = {}
-        for name, cfg in (("autotuned", (K, waves, stage)), ("fixed", (8, 4, 1))):
-            ps.ps_set_emit_config(*cfg)
+        for name, emit in (("autotuned", cfg), ("fixed", (ps.PS_MAP_TILES, 8, 4))):
+            pp = ps.make_params(q, emit=emit)
             for _ in range(2):
-                ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
+                ps.ps_emit(db, pp, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(args.steps):
-                ps.ps_emit(db, plan.params, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
+                ps.ps_emit(db, pp, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
             e1.record(stream)
             torch.cuda.synchronize()
             emit_ms[name] = e0.elapsed_time(e1) / args.steps
-        ps.ps_set_emit_config(7, 4, 2)   # the default mapping
         plan.close()
         V = 2 * R
         row = {"q": f"pi/{qn}", "ribs": R, "vertices": V, "ms_per_step": ms,
                "vertices_per_s": V / (ms * 1e-3),
                "gb_per_s": algorithmic_bytes(V, b.n_segs, b.n_paths) / (ms * 1e-3) / 1e9,
-               "autotuned": {"K": K, "waves": waves, "stage": stage},
-               "emit_ms_autotuned": emit_ms["autotuned"], "emit_ms_fixed_K8_w4_staged": emit_ms["fixed"]}
+               "autotuned": {"mapping": cfg[0], "K": cfg[1], "waves": cfg[2]},
+               "emit_ms_autotuned": emit_ms["autotuned"], "emit_ms_fixed_tiles_K8_w4": emit_ms["fixed"]}
         rows.append(row)
         log(str(row))
         del db
@@ -385,7 +379,7 @@ def study_c5(args, torch, ps, W, dev):
 def study_emit(args, torch, ps, W, dev):
     """The emit stage of the benchmark batch by output mode and mapping: vertices
     and arc length (ps_emit), vertices only (ps_emit without vs), arc length only
-    (ps_arclen), for every mapping K x waves, rib-major (stage 1) and role-split (stage 2)."""
+    (ps_arclen), for every mapping."""
     b = W.config2_fast()
     db = ps.DeviceBatch(b, device=dev)
     first = ps.stroke(db, b.q)
@@ -405,20 +399,21 @@ def study_emit(args, torch, ps, W, dev):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    P, cap, ws = plan.params, 2 * R, plan.ws
+    cap, ws = 2 * R, plan.ws
     rows = []
-    for stage in (1, 2):
-        for K in (4, 6, 7, 8, 16):
-            for waves in (1, 2, 4):
-                ps.ps_set_emit_config(K, waves, stage)
-                row = {"stage": stage, "K": K, "waves": waves,
-                       "ms_xy_s": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, plan.vs,
-                                                           cap, ws)),
-                       "ms_xy": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, None, cap, ws)),
-                       "ms_s": timed(lambda: ps.ps_arclen(db, P, plan.offsets, plan.vs, cap, ws))}
-                rows.append(row)
-                log(str(row))
-    ps.ps_set_emit_config(7, 4, 2)   # the default mapping
+    configs = [(m, K, w_) for m in (ps.PS_MAP_TILES, ps.PS_MAP_LINKS) for K in (4, 5, 6, 7, 8, 16)
+               for w_ in (1, 2, 4)]
+    for emit in configs:
+        P = ps.make_params(b.q, emit=emit)
+        try:
+            row = {"mapping": emit[0], "K": emit[1], "waves": emit[2],
+                   "ms_xy_s": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, plan.vs, cap, ws)),
+                   "ms_xy": timed(lambda: ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, None, cap, ws)),
+                   "ms_s": timed(lambda: ps.ps_arclen(db, P, plan.offsets, plan.vs, cap, ws))}
+        except ps.PsError:
+            continue   # a mapping this build does not offer
+        rows.append(row)
+        log(str(row))
     plan.close()
     print(json.dumps({"study": "emit", "ribs": R, "rows": rows}), flush=True)
     return 0

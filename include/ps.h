@@ -114,14 +114,29 @@ typedef struct {
   const uint8_t* closed;
 } ps_batch;
 
+/* Emit mappings (how ribs are spread over wavefronts; the output bits do not
+ * depend on it):
+ *   PS_MAP_DEFAULT  unplanned calls: PS_MAP_TILES with K = 7, 4 wavefronts;
+ *                   ps_plan_create: the fastest mapping on the batch, timed
+ *   PS_MAP_TILES    persistent wavefronts over tiles of 64*K consecutive ribs,
+ *                   each tile's segment ribs and join/cap ribs swept apart,
+ *                   K = emit_ribs_per_lane in {4, 6, 7, 8, 16}
+ *   PS_MAP_LINKS    persistent wavefronts over groups of consecutive links,
+ *                   one link at a time: all 64 lanes take ribs of the same
+ *                   link, whose data the wavefront holds once */
+enum { PS_MAP_DEFAULT = 0, PS_MAP_TILES = 1, PS_MAP_LINKS = 2 };
+
 /*
  * Parameters: q is the maximum tangent-angle step (Sec. "Uniform Tangent Angle
  * Step Tessellation"), in radians, 1e-4 <= q <= pi.  precision is PS_PREC_*.
  * Dashing (Sec. "Dashing"): n_dash on/off lengths (even count >= 2, all >= 0,
  * positive sum) in the HOST array dash, starting at pattern position
- * dash_phase >= 0 at arc length 0 of every path; n_dash = 0 disables it.
- * miter_limit >= 1 bounds the miter ratio of the miter joins (4 is the usual
- * default of path-rendering standards).
+ * dash_phase >= 0 at arc length 0 of every path (at most 2^40 periods);
+ * n_dash = 0 disables it.  miter_limit >= 1 bounds the miter ratio of the
+ * miter joins (4 is the usual default of path-rendering standards).
+ * emit_mapping is PS_MAP_*; emit_ribs_per_lane (K of PS_MAP_TILES) and
+ * emit_waves (wavefronts per workgroup, 1..4) choose its shape, 0 for the
+ * default.  These only affect speed.
  */
 typedef struct {
   double q;
@@ -130,6 +145,10 @@ typedef struct {
   const double* dash;
   double dash_phase;
   double miter_limit;
+  int32_t emit_mapping;
+  int32_t emit_ribs_per_lane;
+  int32_t emit_waves;
+  int32_t reserved;   /* 0 */
 } ps_params;
 
 /* Status read back from a workspace. */
@@ -313,8 +332,9 @@ int ps_stroke_static(const ps_batch* batch, const ps_params* params, int32_t* li
 int ps_read_status(const void* ws, ps_status* out, void* stream);
 
 /*
- * Batched form: ps_plan_create picks the emit mapping for this batch (it runs
- * the pipeline several times on `stream` and times it), then captures
+ * Batched form: ps_plan_create picks the emit mapping for this batch when
+ * params->emit_mapping is PS_MAP_DEFAULT (it runs the pipeline several times
+ * on `stream` and times every mapping; otherwise it takes the one given), then captures
  * count -> scan -> emit (-> dash when params->n_dash > 0) into a hipGraph
  * bound to these buffers, and a second copy with an event-record node
  * between scan and emit and one after the emit.  ps_plan_launch replays the
@@ -335,29 +355,10 @@ int ps_plan_create(const ps_batch* batch, const ps_params* params, int32_t* link
 int ps_plan_launch(ps_plan* plan, void* stream);
 int ps_plan_launch_timed(ps_plan* plan, void* stream, void* emit_begin, void* emit_end);
 int ps_plan_destroy(ps_plan* plan);
-/* The emit mapping a plan chose: K, waves per workgroup, stage (0, 1 or 2). */
-int ps_plan_config(const ps_plan* plan, int32_t* ribs_per_lane, int32_t* waves_per_group,
-                   int32_t* stage);
-
-/*
- * Emit mapping for the unplanned calls: each wavefront tile is K iterations of
- * 64 consecutive ribs (K = 4, 6, 7, 8 or 16) and workgroups hold 1..4 wavefronts.
- * stage selects how a tile is walked: 0 rib-major with link records read
- * from global memory per rib, 1 rib-major with the records staged in LDS,
- * 2 role-split (records in LDS; the tile's segment ribs and its join and cap
- * ribs are swept separately, so a wavefront never mixes the two); -1 keeps
- * the current choice.  0 for K or waves keeps the current value.  The default
- * is K = 7, 4 wavefronts, role-split.  Output bits do not depend on the mapping.
- */
-int ps_set_emit_config(int32_t ribs_per_lane, int32_t waves_per_group, int32_t stage);
-
-/*
- * Whether ps_plan_create times the emit mappings (on = 1, the default) or
- * takes the current ps_set_emit_config mapping as is (0), e.g. so that a
- * profile of the plan holds only the launches of one mapping.  Other values
- * are rejected with PS_E_ARG.
- */
-int ps_set_plan_autotune(int32_t on);
+/* The emit mapping a plan runs: PS_MAP_TILES or PS_MAP_LINKS, K (0 for
+ * PS_MAP_LINKS) and wavefronts per workgroup. */
+int ps_plan_config(const ps_plan* plan, int32_t* mapping, int32_t* ribs_per_lane,
+                   int32_t* waves_per_group);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* ps_last_error(void);

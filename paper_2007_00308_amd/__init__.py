@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpolarstroke.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ps.h")
 
 PS_OK, PS_E_ARG, PS_E_WORKSPACE, PS_E_HIP, PS_E_NOMEM, PS_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+PS_MAP_DEFAULT, PS_MAP_TILES, PS_MAP_LINKS = 0, 1, 2
 PS_PREC_FP32, PS_PREC_FP32_FIXUP, PS_PREC_FP64 = 0, 1, 2
 PS_STATUS_OVERFLOW, PS_STATUS_NONFINITE, PS_STATUS_BAD_VALUE = 1, 2, 4
 PS_STATUS_DASH_OVERFLOW, PS_STATUS_INTERVALS = 8, 16
@@ -36,7 +37,9 @@ class ps_batch(ctypes.Structure):
 
 class ps_params(ctypes.Structure):
     _fields_ = [("q", ctypes.c_double), ("precision", ctypes.c_int32), ("n_dash", ctypes.c_int32),
-                ("dash", _vp), ("dash_phase", ctypes.c_double), ("miter_limit", ctypes.c_double)]
+                ("dash", _vp), ("dash_phase", ctypes.c_double), ("miter_limit", ctypes.c_double),
+                ("emit_mapping", ctypes.c_int32), ("emit_ribs_per_lane", ctypes.c_int32),
+                ("emit_waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 PS_COVER_QUAD, PS_COVER_TRIANGLES = 0, 1
@@ -93,8 +96,6 @@ def load(path: str = LIB_PATH):
         "ps_plan_launch_timed": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
         "ps_plan_destroy": (ctypes.c_int, [_vp]),
         "ps_plan_config": (ctypes.c_int, [_vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
-        "ps_set_emit_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
-        "ps_set_plan_autotune": (ctypes.c_int, [ctypes.c_int32]),
         "ps_emit_uniform": (ctypes.c_int, [P(ps_batch), P(ps_params), _vp, _vp, _vp, ctypes.c_int64, _vp,
                                            ctypes.c_size_t, _vp]),
         "ps_facet_stats": (ctypes.c_int, [P(ps_batch), _vp, _vp, _vp, _vp, _vp]),
@@ -161,10 +162,11 @@ class DeviceBatch:
 
 
 def make_params(q: float, precision: int = PS_PREC_FP64, dash=(), dash_phase: float = 0.0,
-                miter_limit: float = 4.0):
+                miter_limit: float = 4.0, emit=(PS_MAP_DEFAULT, 0, 0)):
+    """emit: (mapping PS_MAP_*, ribs per lane K, wavefronts per workgroup); 0 = default."""
     arr = (ctypes.c_double * max(1, len(dash)))(*dash) if len(dash) else None
     p = ps_params(float(q), int(precision), len(dash), ctypes.cast(arr, _vp) if arr else None,
-                  float(dash_phase), float(miter_limit))
+                  float(dash_phase), float(miter_limit), int(emit[0]), int(emit[1]), int(emit[2]), 0)
     p._keep = arr   # keep the host pattern alive with the struct
     return p
 
@@ -244,15 +246,6 @@ def ps_read_status(ws, stream=None) -> ps_status:
     return st
 
 
-def ps_set_emit_config(ribs_per_lane: int = 0, waves_per_group: int = 0, stage: int = -1):
-    _check(load().ps_set_emit_config(int(ribs_per_lane), int(waves_per_group), int(stage)),
-           "ps_set_emit_config")
-
-
-def ps_set_plan_autotune(on: bool):
-    _check(load().ps_set_plan_autotune(1 if on else 0), "ps_set_plan_autotune")
-
-
 def ps_version() -> str:
     return load().ps_version().decode()
 
@@ -269,11 +262,12 @@ def alloc_workspace(nbytes: int, device="cuda"):
 # Convenience: the whole chain, with the rib total read back once
 # ----------------------------------------------------------------------------
 def stroke(db: DeviceBatch, q: float, precision: int = PS_PREC_FP64, vertex_capacity=None,
-           with_arclen: bool = True, dash=(), dash_phase: float = 0.0, stream=None) -> dict:
+           with_arclen: bool = True, dash=(), dash_phase: float = 0.0, stream=None,
+           emit=(PS_MAP_DEFAULT, 0, 0)) -> dict:
     """count -> scan -> (read total) -> emit [-> dash]; returns device tensors."""
     import torch
     dev = db.seg_begin.device
-    params = make_params(q, precision, dash, dash_phase, db.miter_limit)
+    params = make_params(q, precision, dash, dash_phase, db.miter_limit, emit)
     link_ribs = torch.empty(max(1, db.n_links), dtype=torch.int32, device=dev)
     offsets = torch.empty(db.n_links + 1, dtype=torch.int64, device=dev)
     ws0 = alloc_workspace(ps_workspace_bytes(db, params, 0), dev)
@@ -319,11 +313,14 @@ class Plan:
 
     def __init__(self, db: DeviceBatch, q: float, vertex_capacity: int,
                  precision: int = PS_PREC_FP64, dash=(), dash_phase: float = 0.0,
-                 dash_rib_capacity: int = 0, dash_capacity: int = 0, stream=None):
+                 dash_rib_capacity: int = 0, dash_capacity: int = 0, stream=None,
+                 emit=(PS_MAP_DEFAULT, 0, 0)):
+        """emit = (PS_MAP_DEFAULT, 0, 0) times every mapping on the batch; an
+        explicit mapping is taken as is."""
         import torch
         dev = db.seg_begin.device
         self.db = db
-        self.params = make_params(q, precision, dash, dash_phase, db.miter_limit)
+        self.params = make_params(q, precision, dash, dash_phase, db.miter_limit, emit)
         self.capacity = int(vertex_capacity)
         self.link_ribs = torch.empty(max(1, db.n_links), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(db.n_links + 1, dtype=torch.int64, device=dev)
@@ -359,10 +356,11 @@ class Plan:
                                            _vp(emit_end.cuda_event)), "ps_plan_launch_timed")
 
     def config(self):
-        k, w, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(load().ps_plan_config(self.handle, ctypes.byref(k), ctypes.byref(w), ctypes.byref(s)),
+        """(mapping, K, wavefronts per workgroup) of the plan's emit."""
+        m, k, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().ps_plan_config(self.handle, ctypes.byref(m), ctypes.byref(k), ctypes.byref(w)),
                "ps_plan_config")
-        return int(k.value), int(w.value), int(s.value)
+        return int(m.value), int(k.value), int(w.value)
 
     def status(self, stream=None) -> ps_status:
         return ps_read_status(self.ws, stream)

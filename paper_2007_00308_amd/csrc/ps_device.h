@@ -230,9 +230,12 @@ __device__ __forceinline__ double rcp64(double x) {
 
 // sqrt(x) in FP64 for x >= 0: from the hardware 1/sqrt estimate, one coupled
 // Newton step on (sqrt x, 1/(2 sqrt x)) and two residual corrections
-// x - g^2.  x below 2^-960 (and 0) goes to the library routine.
+// x - g^2.  x below 2^-960 (and 0) gives 0: the uses here (squared chords in
+// px^2, discriminants of tangent equations) cannot tell roots below 2^-480
+// from 0, and a select costs less than a branch to the library routine.
 __device__ __forceinline__ double sqrt64(double x) {
-  if (!(x >= 0x1p-960)) return sqrt(x);
+  const bool tiny = !(x >= 0x1p-960);
+  x = tiny ? 1.0 : x;
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
   const double r = fma(-g, h, 0.5);
@@ -241,7 +244,7 @@ __device__ __forceinline__ double sqrt64(double x) {
   double d = fma(-g, g, x);
   g = fma(d, h, g);
   d = fma(-g, g, x);
-  return fma(d, h, g);
+  return tiny ? 0.0 : fma(d, h, g);
 }
 
 // sin and cos in FP64 of y + q pi/2 for |y| <= pi/4: the Taylor series of
@@ -384,23 +387,21 @@ __device__ __forceinline__ SolveOut<F> solve_t(const Hodo<F>& h, F nx, F ny, F t
   if (A != (F)0) {
     const F disc = B1 * B1 - (F)4 * A * C;
     if (disc >= (F)0) {
-      if constexpr (sizeof(F) == 8) {
-        // one reciprocal for both roots: qq/A = qq^2/(A qq), C/qq = C A/(A qq)
-        const F sq = sqrt64(disc);
-        const F qq = (F)-0.5 * (B1 + (B1 >= (F)0 ? sq : -sq));
-        const F aq = A * qq;
-        if (aq != (F)0) {
-          const F inv = rcp64(aq);
-          r0 = qq * qq * inv;
-          r1 = C * A * inv;
-        } else {
-          r0 = r1 = (F)0;   // qq = 0 only when B1 = C = 0: the double root t = 0
-        }
+      // one reciprocal for both roots: qq/A = qq^2/(A qq), C/qq = C A/(A qq)
+      // (FP32: the hardware square root and reciprocal, about 1 ulp each)
+      F sq;
+      if constexpr (sizeof(F) == 8) sq = sqrt64(disc);
+      else sq = __builtin_amdgcn_sqrtf(disc);
+      const F qq = (F)-0.5 * (B1 + (B1 >= (F)0 ? sq : -sq));
+      const F aq = A * qq;
+      if (aq != (F)0) {
+        F inv;
+        if constexpr (sizeof(F) == 8) inv = rcp64(aq);
+        else inv = __builtin_amdgcn_rcpf(aq);
+        r0 = qq * qq * inv;
+        r1 = C * A * inv;
       } else {
-        const F sq = sqrt(disc);
-        const F qq = (F)-0.5 * (B1 + (B1 >= (F)0 ? sq : -sq));
-        r0 = qq / A;
-        r1 = (qq != (F)0) ? C / qq : r0;
+        r0 = r1 = (F)0;   // qq = 0 only when B1 = C = 0: the double root t = 0
       }
     }
   } else if (B1 != (F)0) {
@@ -411,19 +412,24 @@ __device__ __forceinline__ SolveOut<F> solve_t(const Hodo<F>& h, F nx, F ny, F t
   const bool in1 = r1 >= lo && r1 <= hi && r1 != r0;
   o.found = in0 || in1;
   o.t = in0 ? r0 : (in1 ? r1 : hi);
-  if (in0 && in1) {
-    // two candidates: the larger score g'(t).T (r0 on a tie)
-    F gx, gy;
-    hodo_eval(h, r0, gx, gy);
-    const F s0 = gx * tx + gy * ty;
-    hodo_eval(h, r1, gx, gy);
-    if (gx * tx + gy * ty > s0) o.t = r1;
+  // (a wavefront skips these unless one of its lanes needs them)
+  if (__ballot(in0 && in1)) {
+    if (in0 && in1) {
+      // two candidates: the larger score g'(t).T (r0 on a tie)
+      F gx, gy;
+      hodo_eval(h, r0, gx, gy);
+      const F s0 = gx * tx + gy * ty;
+      hodo_eval(h, r1, gx, gy);
+      if (gx * tx + gy * ty > s0) o.t = r1;
+    }
   }
-  if (!o.found) {
-    const F ul = (F)1 - lo, uh = (F)1 - hi;
-    const F hl = ul * ul * al + (F)2 * ul * lo * be + lo * lo * ga;
-    const F hh = uh * uh * al + (F)2 * uh * hi * be + hi * hi * ga;
-    o.t = (fabs(hl) < fabs(hh)) ? lo : hi;
+  if (__ballot(!o.found)) {
+    if (!o.found) {
+      const F ul = (F)1 - lo, uh = (F)1 - hi;
+      const F hl = ul * ul * al + (F)2 * ul * lo * be + lo * lo * ga;
+      const F hh = uh * uh * al + (F)2 * uh * hi * be + hi * hi * ga;
+      o.t = (fabs(hl) < fabs(hh)) ? lo : hi;
+    }
   }
   hodo_eval(h, o.t, o.hx, o.hy);
   o.dh = fabs((F)2 * A * o.t + B1);

@@ -557,7 +557,6 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const TIn* in,
 // Emit (Eqs. func_t, func_N, RibVertices-N/P, arc-length-approximation)
 // ===========================================================================
 struct EmitArgs {
-  ps_batch B;
   const LinkRec* rec;
   const int64_t* off;
   int64_t n_links;
@@ -572,15 +571,6 @@ struct EmitArgs {
   float fix_tol;   // largest FP64 Newton step accepted on an FP32 root; beyond it the rib is re-solved in FP64
   double miter_limit;
 };
-
-__device__ __forceinline__ int link_of(const int64_t* off, int lo, int hi, int64_t r) {
-  // largest l in [lo, hi] with off[l] <= r: the link (with ribs) holding rib r
-  while (lo < hi) {
-    const int m = (lo + hi + 1) >> 1;
-    if (off[m] <= r) lo = m; else hi = m - 1;
-  }
-  return lo;
-}
 
 // Tile T stores ribs [T*TS, (T+1)*TS) and also reads rib T*TS - 1.  Writes the
 // link holding each tile's first-read rib, clears the look-back descriptors
@@ -621,29 +611,196 @@ __global__ void __launch_bounds__(256) emit_prepare_kernel(const int64_t* off, i
   }
 }
 
-template <typename F>
-__device__ __forceinline__ F reduce_angle(double psi) {
-  return (F)(psi - kTwoPi * rint(psi * (1.0 / kTwoPi)));
-}
-
+// One rib: its centre G and parameter t (segments), its two vertices, and
+// for the FP32 + FP64 fix-up mode whether it was re-solved in FP64.
 struct RibOut {
   double gx, gy, t;
   float Nx, Ny, Px, Py;
-  bool chord_ok;
-  bool path_start;       // first rib with ribs of its path
-  bool seg_path_start;   // first segment rib of its path
   bool fixed;
 };
 
-// One rib j of a link: Eqs. func_t / func_N for segments (t from the
-// tangent-angle solve), a pivot for joins and caps, then Eqs.
-// RibVertices-N/P.  A pivot is one interval [0, J] of its own, so the angle
-// and the direction are computed once for both roles (a wavefront usually
-// holds ribs of both) and only the t solve and the point differ.  ROLES says
-// which roles the caller can pass: kAnyRole, kSegOnly or kPivotOnly (the
-// other branch is then not compiled).  The record may live in LDS or in
-// global memory.
-constexpr int kAnyRole = 0, kSegOnly = 1, kPivotOnly = 2;
+// The interval k holding a segment rib j, Delta_Sigma(k-1) <= j <=
+// Delta_Sigma(k): its boundary ribs d0 < d1, the tangent angles psa, psb and
+// the parameters lo, hi at them.
+struct RibIval {
+  int d0, d1;
+  double psa, psb, lo, hi;
+};
+
+// For a record held per lane (in LDS): k - 1 is the number of boundaries j
+// has passed (dsum increases strictly and holds INT_MAX past the last
+// interval), counted without a chain of dependent reads; the interval's data
+// are then read by index.
+__device__ __forceinline__ RibIval rib_ival(const LinkRec& rp, int j) {
+  int k1 = 0;
+#pragma unroll
+  for (int m = 0; m < kMaxIv - 1; ++m) k1 += (j > rp.dsum[m]) ? 1 : 0;
+  RibIval v;
+  v.d0 = k1 ? rp.dsum[k1 - 1] : 0;
+  v.d1 = rp.dsum[k1];
+  v.psa = rp.psi[k1];
+  v.psb = rp.psi[k1 + 1];
+  v.lo = k1 ? rp.p[k1 - 1] : 0.0;
+  v.hi = (k1 + 1 < (int)rp.n_iv) ? rp.p[k1 < kMaxIv - 2 ? k1 : kMaxIv - 2] : 1.0;
+  return v;
+}
+
+// For a record every lane shares (in scalar registers): selections over the
+// record's n_iv intervals, a wavefront-uniform count, so a one-interval
+// segment selects nothing.
+__device__ __forceinline__ RibIval rib_ival_uniform(const LinkRec& rp, int j) {
+  const int n_iv = rp.n_iv;
+  RibIval v;
+  v.d0 = 0; v.d1 = rp.dsum[0];
+  v.psa = rp.psi[0]; v.psb = rp.psi[1];
+  v.lo = 0.0; v.hi = n_iv > 1 ? rp.p[0] : 1.0;
+#pragma unroll
+  for (int m = 1; m < kMaxIv; ++m) {
+    if (m < n_iv) {
+      const bool past = j > rp.dsum[m - 1];
+      const double hi_m = (m + 1 < n_iv) ? rp.p[m < kMaxIv - 1 ? m : 0] : 1.0;
+      v.d0 = past ? rp.dsum[m - 1] : v.d0;
+      v.d1 = past ? rp.dsum[m] : v.d1;
+      v.psa = past ? rp.psi[m] : v.psa;
+      v.psb = past ? rp.psi[m + 1] : v.psb;
+      v.lo = past ? rp.p[m - 1] : v.lo;
+      v.hi = past ? hi_m : v.hi;
+    }
+  }
+  return v;
+}
+
+// sin and cos in FP32 from an LDS table of kSinTab (sin, cos) pairs: x =
+// k 2pi/kSinTab + y with |y| <= pi/kSinTab, sin y to y^3 and cos y - 1 to y^4
+// (truncation below 4e-10 relative, under the FP32 rounding), then the
+// angle-sum identities.  2pi/kSinTab is split in two floats, the first of 12
+// significant bits, so that k times it is exact for |x| up to 200 (the
+// unwrapped angles here stay within a few turns).
+constexpr float kTab32Hi = 0.04907226562f;                    // 2pi/128 to 12 bits
+constexpr float kTab32Lo = (float)(kTwoPi / kSinTab - 0.04907226562);
+__device__ __forceinline__ void fill_sincos_tab32(float2* tab, const double2* tab64) {
+  for (int k = threadIdx.x; k < kSinTab; k += blockDim.x) tab[k] = make_float2((float)tab64[k].x, (float)tab64[k].y);
+}
+__device__ __forceinline__ void sincos_tab32(const float2* tab, float x, float* s, float* c) {
+  const float k = rintf(x * (float)(kSinTab / kTwoPi));
+  const float y = fmaf(-k, kTab32Lo, fmaf(-k, kTab32Hi, x));
+  const float z = y * y;
+  const float sy = fmaf(y * z, -1.0f / 6, y);
+  const float cm1 = z * fmaf(z, 1.0f / 24, -0.5f);
+  const float2 t = tab[(int)k & (kSinTab - 1)];
+  *s = fmaf(t.y, sy, fmaf(t.x, cm1, t.x));
+  *c = fmaf(-t.x, sy, fmaf(t.y, cm1, t.y));
+}
+
+// g(t) in FP32 (the single-precision mode): the same forms as eval_point.
+__device__ __forceinline__ void eval_point32(int kind, const float* X, const float* Y, float w, float t,
+                                             float& gx, float& gy) {
+  const float u = 1.0f - t;
+  if (kind == PS_KIND_CUBIC) {
+    const float b0 = u * u * u, b1 = 3.0f * u * u * t, b2 = 3.0f * u * t * t, b3 = t * t * t;
+    gx = b0 * X[0] + b1 * X[1] + b2 * X[2] + b3 * X[3];
+    gy = b0 * Y[0] + b1 * Y[1] + b2 * Y[2] + b3 * Y[3];
+  } else if (kind == PS_KIND_LINE) {
+    gx = u * X[0] + t * X[1];
+    gy = u * Y[0] + t * Y[1];
+  } else {
+    const float ww = (kind == PS_KIND_CONIC) ? w : 1.0f;
+    const float b0 = u * u, b1 = 2.0f * u * t * ww, b2 = t * t;
+    const float inv = __builtin_amdgcn_rcpf(b0 + b1 + b2);
+    gx = (b0 * X[0] + b1 * X[1] + b2 * X[2]) * inv;
+    gy = (b0 * Y[0] + b1 * Y[1] + b2 * Y[2]) * inv;
+  }
+}
+
+// Segment rib j of interval v (Eqs. func_t, func_N): the tangent angle
+// psi_j = psi_{k-1} + (j - Delta_Sigma(k-1)) delta_k / Delta_k (the boundary
+// angles exactly at the interval ends), n(psi) = (-sin psi, cos psi), t from
+// the tangent-angle solve (Eq. angle2t) on the interior ribs, G = g(t) and
+// the vertices N = G - r n, P = G + r n (Eqs. RibVertices-N/P).  PREC picks
+// the arithmetic (PS_PREC_*): FP64 throughout; FP32 throughout (the direction
+// from an FP32 table, the solve and the point in FP32); or an FP32 solve that
+// one FP64 Newton step polishes, with the rib re-solved in FP64 when that step
+// is not small.
+template <int PREC>
+__device__ __forceinline__ void seg_rib(const LinkRec& rp, int j, const RibIval& v, float fix_tol,
+                                        const double2* tab, const float2* tab32, RibOut& o) {
+  const bool at0 = j == v.d0, at1 = j == v.d1;
+  const bool solve = !at0 && !at1 && v.lo != v.hi;
+  const int kind = rp.kind;
+  o.fixed = false;
+  float X[4], Y[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { X[i] = rp.x[i]; Y[i] = rp.y[i]; }
+  if constexpr (PREC == PS_PREC_FP32) {
+    const float psa = (float)v.psa, psb = (float)v.psb;
+    const float psi = at0 ? psa
+                    : (at1 ? psb
+                           : fmaf(psb - psa, (float)(j - v.d0) * __builtin_amdgcn_rcpf((float)(v.d1 - v.d0)), psa));
+    float sn, cs;
+    sincos_tab32(tab32, psi, &sn, &cs);
+    const float nx = -sn, ny = cs;
+    float t = at1 ? (float)v.hi : (float)v.lo;
+    if (solve) {
+      const Hodo<float> h = hodo_of<float>(kind, X, Y, rp.w);
+      t = solve_t<float>(h, nx, ny, ny, -nx, (float)v.lo, (float)v.hi).t;
+    }
+    float gx, gy;
+    eval_point32(kind, X, Y, rp.w, t, gx, gy);
+    const float r = rp.r;
+    o.gx = gx; o.gy = gy; o.t = t;
+    o.Nx = fmaf(-r, nx, gx); o.Ny = fmaf(-r, ny, gy);
+    o.Px = fmaf(r, nx, gx); o.Py = fmaf(r, ny, gy);
+  } else {
+    const double psi =
+        at0 ? v.psa : (at1 ? v.psb : v.psa + (v.psb - v.psa) * ((double)(j - v.d0) * rcp64((double)(v.d1 - v.d0))));
+    double sn, cs;
+    sincos_tab(tab, psi, &sn, &cs);
+    const double nx = -sn, ny = cs;
+    double Xd[4], Yd[4];   // the FP32 inputs, converted once (exactly)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { Xd[i] = (double)X[i]; Yd[i] = (double)Y[i]; }
+    double t = at1 ? v.hi : v.lo;
+    if (solve) {
+      bool need64 = PREC == PS_PREC_FP64;
+      if constexpr (PREC == PS_PREC_FP32_FIXUP) {
+        // the FP32 quadratic isolates and selects the root, one FP64 Newton
+        // step on g'(t).n polishes it; no FP32 root, a step above fix_tol or
+        // a step out of the interval (a root close to a cusp or to the other
+        // root) sends the rib to the FP64 solve
+        const Hodo<float> h = hodo_of<float>(kind, X, Y, rp.w);
+        const SolveOut<float> so = solve_t<float>(h, (float)nx, (float)ny, (float)ny, (float)-nx,
+                                                  (float)v.lo, (float)v.hi);
+        need64 = true;
+        if (so.found) {
+          const Hodo<double> hd = hodo_of<double>(kind, Xd, Yd, (double)rp.w);
+          const double al = hd.e0x * nx + hd.e0y * ny;
+          const double be = hd.e1x * nx + hd.e1y * ny;
+          const double ga = hd.e2x * nx + hd.e2y * ny;
+          const double Aq = al - 2.0 * be + ga, Bq = 2.0 * (be - al);
+          const double t0 = (double)so.t;
+          const double hv = (Aq * t0 + Bq) * t0 + al;
+          const float dv = (float)(2.0 * Aq * t0 + Bq);
+          const double step = (double)__builtin_amdgcn_rcpf(dv) * hv;
+          const double t1 = t0 - step;
+          if (dv != 0.0f && fabs(step) <= (double)fix_tol && t1 >= v.lo && t1 <= v.hi) {
+            t = t1;
+            need64 = false;
+          }
+        }
+        o.fixed = need64;
+      }
+      if (need64) {
+        const Hodo<double> h = hodo_of<double>(kind, Xd, Yd, (double)rp.w);
+        t = solve_t<double>(h, nx, ny, ny, -nx, v.lo, v.hi).t;
+      }
+    }
+    eval_point(kind, Xd, Yd, (double)rp.w, t, o.gx, o.gy);
+    o.t = t;
+    const double r = (double)rp.r;
+    o.Nx = (float)(o.gx - r * nx); o.Ny = (float)(o.gy - r * ny);
+    o.Px = (float)(o.gx + r * nx); o.Py = (float)(o.gy + r * ny);
+  }
+}
 
 // The outer vertex of rib j (1 or 2) of a miter join (Sec. "Harder Joins:
 // Miter Truncate and Revert", which leaves the construction to standard
@@ -653,9 +810,9 @@ constexpr int kAnyRole = 0, kSegOnly = 1, kPivotOnly = 2;
 // stroke width) is 1/cos(|delta|/2) = 2/|o0 + o3|.  Within the limit both ribs
 // take M; beyond it PS_JOIN_MITER reverts to the bevel's ends and
 // PS_JOIN_MITER_CLIP cuts the miter square to its bisector b at limit * r
-// from c, rib 1 on the incoming offset line, rib 2 on the outgoing one.
-template <typename Rec>
-__device__ __forceinline__ void miter_vertex(const Rec& rp, int j, int style, double limit,
+// from c, rib 1 on the incoming offset line, rib 2 on the outgoing one.  The
+// join's record holds n0 and n3 in p[0..3].
+__device__ __forceinline__ void miter_vertex(const LinkRec& rp, int j, int style, double limit,
                                              double& vx, double& vy) {
   const double cx = rp.x[0], cy = rp.y[0], r = rp.r;
   const double sg = (rp.psi[1] - rp.psi[0]) > 0 ? -1.0 : 1.0;
@@ -680,129 +837,45 @@ __device__ __forceinline__ void miter_vertex(const Rec& rp, int j, int style, do
   if (j == 1) { vx = cx + r * o0x + u * t0x; vy = cy + r * o0y + u * t0y; }
   else { vx = cx + r * o3x - u * t3x; vy = cy + r * o3y - u * t3y; }
 }
-template <int PREC, int ROLES = kAnyRole, typename Rec>
-__device__ __forceinline__ void compute_rib(const Rec& rp, int j, float fix_tol, double miter_limit,
-                                            const double2* sc_tab, RibOut& o) {
-  const uint8_t role = rp.role;
-  const bool seg = ROLES == kSegOnly || (ROLES == kAnyRole && role == ROLE_SEG);
-  const double rad = (double)rp.r;
-  o.path_start = (rp.flags & kFirstInPath) && j == 0;
-  o.seg_path_start = (rp.flags & kFirstSegInPath) && j == 0;
-  o.fixed = false;
-  // interval k (1-based): dsum[k-2] <= j <= dsum[k-1]; pivots have one.  The
-  // cumulative counts increase strictly (the entries past the last interval
-  // hold INT_MAX), so k - 1 is the number of boundaries j has passed: counted
-  // without a chain of dependent reads
-  const int n_iv = rp.n_iv;
-  int k = 1;
-  if (ROLES != kPivotOnly) {
-#pragma unroll
-    for (int m = 0; m < kMaxIv - 1; ++m) k += (j > rp.dsum[m]) ? 1 : 0;
-  }
-  const int d0 = (k > 1) ? rp.dsum[k - 2] : 0;
-  const int d1 = rp.dsum[k - 1];
-  const double psa = rp.psi[k - 1], psb = rp.psi[k];
-  const bool at0 = j == d0, at1 = j == d1;
-  const double psi =
-      at0 ? psa : (at1 ? psb : psa + (psb - psa) * ((double)(j - d0) * rcp64((double)(d1 - d0))));
-  double nx, ny;   // n(psi) = (-sin psi, cos psi)
-  if (PREC == PS_PREC_FP32) {
+
+// Join or cap rib j: a pivot of J steps at a fixed point (Sec. "Tessellation
+// Approach for Caps and Joins"), psi_j = psi_0 + j delta / J (exact at both
+// ends); only the side away from the turn keeps its radius; the square cap's
+// ribs 1 and 3 reach r sqrt 2; miter joins replace the outer vertex of ribs
+// 1 and 2.
+template <int PREC>
+__device__ __forceinline__ void piv_rib(const LinkRec& rp, int j, double miter_limit, const double2* tab,
+                                        const float2* tab32, RibOut& o) {
+  const int style = rp.flags >> 4;
+  const int J = rp.dsum[0];
+  const double psa = rp.psi[0], psb = rp.psi[1];
+  const double psi = j == 0 ? psa : (j == J ? psb : psa + (psb - psa) * ((double)j * rcp64((double)J)));
+  double nx, ny;
+  if constexpr (PREC == PS_PREC_FP32) {
     float s32, c32;
-    sincosf(reduce_angle<float>(psi), &s32, &c32);
-    nx = -(double)s32; ny = (double)c32;
+    sincos_tab32(tab32, (float)psi, &s32, &c32);
+    nx = -s32; ny = c32;
   } else {
     double sn, cs;
-    sincos_tab(sc_tab, psi, &sn, &cs);
+    sincos_tab(tab, psi, &sn, &cs);
     nx = -sn; ny = cs;
   }
-  double rN = rad, rP = rad;
-  if (seg) {
-    const int kind = rp.kind;
-    float X[4], Y[4];
-    double Xd[4], Yd[4];   // the FP32 inputs, converted once (exactly)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      X[i] = rp.x[i]; Y[i] = rp.y[i];
-      Xd[i] = (double)X[i]; Yd[i] = (double)Y[i];
-    }
-    const float wf = rp.w;
-    const double lo = (k == 1) ? 0.0 : rp.p[k - 2];
-    const double hi = (k == n_iv) ? 1.0 : rp.p[k - 1];
-    double t = at1 ? hi : lo;
-    if (!at0 && !at1 && lo != hi) {
-      if (PREC == PS_PREC_FP32) {
-        // single precision throughout (precision studies only)
-        const float sn = (float)-nx, cs = (float)ny;
-        const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
-        t = (double)solve_t<float>(h, -sn, cs, cs, sn, (float)lo, (float)hi).t;
-      } else {
-        bool need64 = (PREC == PS_PREC_FP64);
-        if (PREC == PS_PREC_FP32_FIXUP) {
-          // the FP32 quadratic isolates and selects the root, one FP64 Newton
-          // step on g'(t).N polishes it.  No FP32 root, a large step or a step
-          // out of the interval (a root close to a cusp or to another root)
-          // sends the rib to the FP64 solve.
-          const Hodo<float> h = hodo_of<float>(kind, X, Y, wf);
-          const SolveOut<float> so = solve_t<float>(h, (float)nx, (float)ny, (float)ny,
-                                                    (float)-nx, (float)lo, (float)hi);
-          need64 = true;
-          if (so.found) {
-            const Hodo<double> hd = hodo_of<double>(kind, Xd, Yd, (double)wf);
-            const double al = hd.e0x * nx + hd.e0y * ny;
-            const double be = hd.e1x * nx + hd.e1y * ny;
-            const double ga = hd.e2x * nx + hd.e2y * ny;
-            const double Aq = al - 2.0 * be + ga, Bq = 2.0 * (be - al);
-            const double t0 = (double)so.t;
-            const double hv = (Aq * t0 + Bq) * t0 + al;
-            const double dv = 2.0 * Aq * t0 + Bq;
-            const double step = (dv != 0.0) ? hv * rcp64(dv) : 0.0;
-            const double t1 = t0 - step;
-            if (fabs(step) <= (double)fix_tol && t1 >= lo && t1 <= hi) { t = t1; need64 = false; }
-          }
-          o.fixed = need64;
-        }
-        if (need64) {
-          const Hodo<double> h = hodo_of<double>(kind, Xd, Yd, (double)wf);
-          t = solve_t<double>(h, nx, ny, ny, -nx, lo, hi).t;
-        }
-      }
-    }
-    eval_point(kind, Xd, Yd, (double)wf, t, o.gx, o.gy);
-    o.t = t;
-    o.chord_ok = (j > 0);
-  } else {
-    // join or cap: a pivot at a fixed point (Sec. "Tessellation Approach for
-    // Caps and Joins"); only the side away from the turn keeps its radius
-    double rout = rad;
-    if ((role == ROLE_SCAP || role == ROLE_ECAP) && (rp.flags >> 4) == PS_CAP_SQUARE && (j == 1 || j == 3))
-      rout = rad * 1.41421356237309504880;
-    const bool left_turn = (psb - psa) > 0;
-    rN = left_turn ? rout : 0.0;
-    rP = left_turn ? 0.0 : rout;
-    o.gx = (double)rp.x[0]; o.gy = (double)rp.y[0];
-    o.t = 0.0;
-    o.chord_ok = false;
-  }
-  o.Nx = (float)(o.gx - rN * nx); o.Ny = (float)(o.gy - rN * ny);
-  o.Px = (float)(o.gx + rP * nx); o.Py = (float)(o.gy + rP * ny);
-  if (!seg && role == ROLE_JOIN && (j == 1 || j == 2)) {
-    const int style = rp.flags >> 4;
-    if (style == PS_JOIN_MITER || style == PS_JOIN_MITER_CLIP) {
-      double vx, vy;
-      miter_vertex(rp, j, style, miter_limit, vx, vy);
-      if (rp.psi[1] - rp.psi[0] > 0) { o.Nx = (float)vx; o.Ny = (float)vy; }
-      else { o.Px = (float)vx; o.Py = (float)vy; }
-    }
+  double rout = rp.r;
+  if ((rp.role == ROLE_SCAP || rp.role == ROLE_ECAP) && style == PS_CAP_SQUARE && (j == 1 || j == 3))
+    rout *= 1.41421356237309504880;
+  const bool left_turn = (psb - psa) > 0;
+  const double rN = left_turn ? rout : 0.0, rP = left_turn ? 0.0 : rout;
+  const double cx = rp.x[0], cy = rp.y[0];
+  o.gx = cx; o.gy = cy; o.t = 0.0; o.fixed = false;
+  o.Nx = (float)(cx - rN * nx); o.Ny = (float)(cy - rN * ny);
+  o.Px = (float)(cx + rP * nx); o.Py = (float)(cy + rP * ny);
+  if (rp.role == ROLE_JOIN && (j == 1 || j == 2) && (style == PS_JOIN_MITER || style == PS_JOIN_MITER_CLIP)) {
+    double vx, vy;
+    miter_vertex(rp, j, style, miter_limit, vx, vy);
+    if (left_turn) { o.Nx = (float)vx; o.Ny = (float)vy; }
+    else { o.Px = (float)vx; o.Py = (float)vy; }
   }
 }
-
-// Link window staged in LDS, one per wave: kWin consecutive link slots
-// starting at `base`, their offsets and their records.
-constexpr int kWin = 12;
-struct WinLDS {
-  long long off[kWin + 1];
-  LinkRec rec[kWin];
-};
 
 // Look-back words are published with a device-scope atomic swap and read
 // with device-scope relaxed atomic loads.  At device scope both reach the
@@ -817,13 +890,14 @@ __device__ __forceinline__ unsigned long long desc_read(const unsigned long long
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// round(x) to int64 for x >= 0 (ties to even, as llrint): below 2^52 the sum
-// x + 2^52 is rounded to an integer by the FP64 add itself, and its bits
-// minus those of 2^52 are that integer
+// round(x) to int64 for 0 <= x < 2^63 (ties to even, as llrint), with no
+// branch: the rounded value split at 2^32 (both parts exact in FP64) and each
+// half converted on its own.
 __device__ __forceinline__ long long fix_round(double x) {
-  if (x < 4503599627370496.0)
-    return __double_as_longlong(x + 4503599627370496.0) - 0x4330000000000000ll;
-  return llrint(x);
+  const double xr = rint(x);
+  const double hi = trunc(xr * 0x1p-32);
+  const double lo = fma(-hi, 4294967296.0, xr);
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // Cross-lane moves on the VALU (DPP) rather than through the LDS crossbar.
@@ -872,237 +946,51 @@ __device__ __forceinline__ void seg_scan_step(long long& c, int& f) {
   f |= fu;
 }
 
-// Persistent emit.  Tile T covers ribs [T*TS, (T+1)*TS), TS = 64*K - 1; lane
-// slot (k, lane) handles rib T*TS - 1 + 64k + lane, so slot (0,0) re-reads the
-// previous tile's last rib for the first chord and stores nothing.  A
-// workgroup of W waves claims W consecutive tiles per ticket, one per wave, in
-// increasing order, so every tile a wave waits on belongs to a wave that is
-// already running.  No wave holds more than one tile at a time on purpose: a
-// wave holding several consecutive tiles would publish the last of them only
-// after the look-backs of the others, and the next group's first tile waits on
-// exactly that one, which chains all waves into one sequence.
-//
-// STAGE: link records are staged per wave in LDS (one cooperative load per
-// window of kWin links) instead of being read from global memory per rib.
+// Tile rounds.  With arc length, tiles wait on earlier tiles' look-back
+// words, so tiles are claimed in increasing order by running wavefronts: one
+// ticket (an atomic counter) per workgroup per round, the workgroup's waves
+// taking tiles ticket * waves + w.  The ticket goes through one of two LDS
+// slots by round parity, so one barrier per round suffices (a slot is written
+// again two rounds later, after every wave has passed the barrier of the
+// round between).  Without arc length no tile waits on another, and
+// workgroup g simply takes rounds g, g + gridDim.x, ... with no atomic and no
+// barrier.
+template <bool ORDERED>
+struct TileRounds {
+  unsigned int ticket, round;
+  __device__ __forceinline__ unsigned int first(unsigned long long* counter, unsigned int* slot) {
+    round = 0;
+    ticket = ORDERED ? claim(counter, slot) : blockIdx.x;
+    return ticket;
+  }
+  __device__ __forceinline__ unsigned int next(unsigned long long* counter, unsigned int* slot) {
+    ++round;
+    ticket = ORDERED ? claim(counter, slot) : ticket + gridDim.x;
+    return ticket;
+  }
+  __device__ __forceinline__ unsigned int claim(unsigned long long* counter, unsigned int* slot) {
+    if (threadIdx.x == 0) slot[round & 1] = (unsigned int)atomicAdd(counter, 1ull);
+    __syncthreads();
+    return slot[round & 1];
+  }
+};
+
+// Role-split emit.  Persistent workgroups of W wavefronts take one ticket per
+// round and their wavefronts tiles ticket * W + w, so every tile a wavefront
+// waits on belongs to a wavefront already running.  Tile T stores ribs
+// [T*TS, (T+1)*TS), TS = 64*K.  A wavefront stages windows of kWin
+// consecutive link slots (their offsets and records) in LDS
+// and sweeps each window twice: once over its segment ribs, 64 at a time in
+// rib order (solve, point, vertices, chords, arc-length scan), once over its
+// join and cap ribs; a wavefront never mixes the two roles.  Chords join
+// consecutive ribs of one segment, so the arc length is a scan over the
+// segment ribs alone (a path restarts at its first segment rib); a pivot's s
+// is the s of its segment's last rib, or 0 for a start cap.
 //
 // Arc length is accumulated in 64-bit fixed point (2^-32 px per unit): each
 // chord is rounded once and every sum after that is an integer sum, so s does
 // not depend on the tiling, the mapping or the order tiles finish in.
-// Dynamic LDS per wave: the link window (STAGE) and the in-tile arc-length
-// sums of its K x 64 rib slots (WS), kept until the tile's prefix is known.
-__host__ __device__ constexpr size_t emit_lds_per_wave(int K, bool ws, bool stage) {
-  return (stage ? sizeof(WinLDS) : 0) + (ws ? (size_t)K * 64 * sizeof(long long) : 0);
-}
-
-// One ticket per workgroup per round: the workgroup's waves take tiles
-// ticket * waves + w.  Returns the ticket every thread of the group read.
-__device__ __forceinline__ unsigned int take_group_ticket(unsigned long long* counter, unsigned int& slot) {
-  if (threadIdx.x == 0) slot = (unsigned int)atomicAdd(counter, 1ull);
-  __syncthreads();
-  const unsigned int t = slot;
-  __syncthreads();   // every wave has read the ticket before the next round writes it
-  return t;
-}
-
-template <int K, int PREC, bool WXY, bool WS, bool STAGE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PS_PREC_FP32_FIXUP ? 3 : 4)))
-emit_kernel(EmitArgs A) {
-  extern __shared__ unsigned char smem_raw[];
-  unsigned char* wave_lds = smem_raw + (threadIdx.x >> 6) * emit_lds_per_wave(K, WS, STAGE);
-  WinLDS& win = *reinterpret_cast<WinLDS*>(wave_lds);
-  long long* srel = reinterpret_cast<long long*>(wave_lds + (STAGE ? sizeof(WinLDS) : 0));
-  __shared__ double2 sc_tab[kSinTab];
-  const int lane = threadIdx.x & 63;
-  const int64_t L = A.n_links;
-  const int64_t R = A.off[L];
-  constexpr int TS = 64 * K - 1;
-  const int64_t n_tiles = (R + TS - 1) / TS;
-  if (2 * R > A.capacity || n_tiles > A.max_tiles) return;
-  unsigned long long fixups = 0;
-  // one ticket per workgroup per round: wave w of the group takes tile
-  // ticket * waves + w (a single ticket counter serialises its atomics, so
-  // fewer tickets per rib matter more than their latency)
-  __shared__ unsigned int group_ticket;
-  const int n_waves = blockDim.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  // a workgroup without a tile leaves before filling the sincos table
-  unsigned int ticket = take_group_ticket(&A.st->tile_counter, group_ticket);
-  if ((int64_t)ticket * n_waves >= n_tiles) return;
-  fill_sincos_tab(sc_tab);
-  __syncthreads();
-  for (;; ticket = take_group_ticket(&A.st->tile_counter, group_ticket)) {
-    const int64_t first = (int64_t)ticket * n_waves;
-    if (first >= n_tiles) break;
-    const int64_t tile = first + wave;
-    if (tile < n_tiles) {
-      const int64_t r0 = tile * TS;
-      const int lhi = A.tile_link[tile + 1];
-      int l = A.tile_link[tile];
-      int base = -1;              // first link slot of the staged window (STAGE)
-      long long wend = -1;        // first rib past the staged window
-      long long run = 0;          // chord sum since the tile start or its last path start
-      bool seen_start = false;
-      double cgx = 0, cgy = 0, ct = 0;   // the previous iteration's last rib
-      unsigned int need_prefix = 0;
-#pragma unroll 1
-      for (int k = 0; k < K; ++k) {
-        const int64_t r = r0 - 1 + 64 * k + lane;
-        const bool valid = (r >= 0) && (r < R);
-        const bool mine = valid && (r >= r0);
-        RibOut o;
-        o.gx = o.gy = o.t = 0; o.chord_ok = false; o.path_start = false; o.fixed = false;
-        if (STAGE) {
-          // every record comes from the LDS window; an iteration whose ribs
-          // span more link slots than the window holds (runs of links with
-          // few or no ribs) takes further passes, each restaging the window
-          // at the first rib still pending (lanes hold consecutive ribs)
-          const int64_t rf = (r0 - 1 + 64 * k) < 0 ? 0 : (r0 - 1 + 64 * k);
-          const int64_t rl = (r0 - 1 + 64 * k + 63) < R ? (r0 - 1 + 64 * k + 63) : R - 1;
-          bool pending = valid;
-          int64_t rs = rf;
-          bool restage = rf <= rl && (base < 0 || rl >= wend);
-          for (;;) {
-            if (restage) {
-              base = (base < 0) ? l : link_of(A.off, base, lhi, rs);
-              const int64_t idx = (int64_t)base + lane;
-              const long long o_i = (lane <= kWin && idx <= L) ? A.off[idx] : LLONG_MAX;
-              if (lane <= kWin) win.off[lane] = o_i;
-              wend = __shfl(o_i, kWin, 64);
-              // the window's records, copied in coalesced 16-byte pieces
-              const int n_rec = (int)(L - base < kWin ? L - base : kWin);
-              const int4* src = reinterpret_cast<const int4*>(A.rec + base);
-              int4* dst = reinterpret_cast<int4*>(win.rec);
-              for (int c = lane; c < n_rec * (int)(sizeof(LinkRec) / 16); c += 64) dst[c] = src[c];
-            }
-            if (pending && r < wend) {
-              // largest i with off[base + i] <= r, searched in LDS
-              int a = 0, b = kWin - 1;
-              while (a < b) {
-                const int m = (a + b + 1) >> 1;
-                if (win.off[m] <= r) a = m; else b = m - 1;
-              }
-              compute_rib<PREC>(win.rec[a], (int)(r - win.off[a]), A.fix_tol, A.miter_limit, sc_tab, o);
-              pending = false;
-            }
-            const unsigned long long pm = __ballot(pending);
-            if (pm == 0ull) break;
-            rs = r0 - 1 + 64 * k + __builtin_ctzll(pm);
-            restage = true;
-          }
-        } else if (valid) {
-          l = link_of(A.off, l, lhi, r);
-          compute_rib<PREC>(A.rec[l], (int)(r - A.off[l]), A.fix_tol, A.miter_limit, sc_tab, o);
-        }
-        if (valid) {
-          if (WXY && mine) {
-            *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2(o.Nx, o.Px);
-            *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2(o.Ny, o.Py);
-          }
-          fixups += o.fixed ? 1 : 0;
-        }
-        if (WS) {
-          // chord from the previous rib; zero when t decreases
-          const double pgx = wave_shr1(o.gx, cgx), pgy = wave_shr1(o.gy, cgy), pt = wave_shr1(o.t, ct);
-          long long c = 0;
-          if (mine && o.chord_ok && o.t >= pt) {
-            const double dx = o.gx - pgx, dy = o.gy - pgy;
-            c = fix_round(sqrt64(dx * dx + dy * dy) * kFix);
-          }
-          int f = (mine && o.path_start) ? 1 : 0;
-          // inclusive scan across the wave: Hillis-Steele inside each row of
-          // 16 lanes, then the row totals broadcast from lanes 15 and 31
-          if (__ballot(f != 0 || c >= (1ll << 50)) == 0ull) {
-            // no path start among these ribs (the common case) and every
-            // chord below 2^50 units (2^18 px): a plain sum, as two exact
-            // 32-bit scans of the chord's low 24 and high bits, neither of
-            // which can overflow over 64 lanes
-            unsigned lo = (unsigned)c & 0xffffffu, hi = (unsigned)(c >> 24);
-            lo = scan_step_u32<0x111, 0xf>(lo); hi = scan_step_u32<0x111, 0xf>(hi);
-            lo = scan_step_u32<0x112, 0xf>(lo); hi = scan_step_u32<0x112, 0xf>(hi);
-            lo = scan_step_u32<0x114, 0xf>(lo); hi = scan_step_u32<0x114, 0xf>(hi);
-            lo = scan_step_u32<0x118, 0xf>(lo); hi = scan_step_u32<0x118, 0xf>(hi);
-            lo = scan_step_u32<0x142, 0xa>(lo); hi = scan_step_u32<0x142, 0xa>(hi);
-            lo = scan_step_u32<0x143, 0xc>(lo); hi = scan_step_u32<0x143, 0xc>(hi);
-            c = (long long)(((unsigned long long)hi << 24) + lo);
-          } else {
-            // segmented, in 64 bits: a path start resets the sum
-            seg_scan_step<0x111, 0xf>(c, f);   // row_shr:1
-            seg_scan_step<0x112, 0xf>(c, f);   // row_shr:2
-            seg_scan_step<0x114, 0xf>(c, f);   // row_shr:4
-            seg_scan_step<0x118, 0xf>(c, f);   // row_shr:8
-            seg_scan_step<0x142, 0xa>(c, f);   // row_bcast:15 into rows 1, 3
-            seg_scan_step<0x143, 0xc>(c, f);   // row_bcast:31 into rows 2, 3
-          }
-          srel[k * 64 + lane] = f ? c : run + c;
-          if (!(f || seen_start)) need_prefix |= (1u << k);
-          const long long c63 = readlane_i64(c, 63);
-          const int f63 = __builtin_amdgcn_readlane(f, 63);
-          run = f63 ? c63 : run + c63;
-          seen_start = seen_start || (f63 != 0);
-          cgx = readlane_f64(o.gx, 63); cgy = readlane_f64(o.gy, 63); ct = readlane_f64(o.t, 63);
-        }
-      }
-      if (WS) {
-        // Decoupled look-back on one 64-bit word per tile (2 state bits: 1 =
-        // tile sum, 2 = sum since the last path start up to the tile's end; 62
-        // value bits).  A tile holding a path start publishes its inclusive sum
-        // at once, and still looks back when its first ribs continue a path
-        // from earlier tiles.  The whole wave looks back: lane i reads tile
-        // base - i, 64 predecessors per round trip.
-        const unsigned long long agg = (unsigned long long)run & kValMask;
-        const bool any_need = __ballot(need_prefix != 0) != 0ull;
-        if (lane == 0) desc_publish(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg);
-        unsigned long long prefix = 0;
-        if (any_need) {
-          int64_t base = tile - 1;
-          for (;;) {
-            const int64_t Ti = base - lane;
-            // before tile 0 every path has started: an inclusive zero
-            const unsigned long long w = Ti >= 0 ? desc_read(&A.desc[Ti]) : (2ull << 62);
-            const unsigned stt = (unsigned)(w >> 62);
-            const unsigned long long incl = __ballot(stt == 2);
-            const int stop = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive word
-            const unsigned long long upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
-            if (__ballot(stt == 0) & upto) { __builtin_amdgcn_s_sleep(1); continue; }
-            unsigned long long v = lane <= stop ? (w & kValMask) : 0ull;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-            prefix += v;
-            if (stop < 64) break;
-            base -= 64;
-          }
-          if (lane == 0 && !seen_start)
-            desc_publish(&A.desc[tile], (2ull << 62) | ((prefix + agg) & kValMask));
-        }
-        const long long pre = (long long)prefix;
-        for (int k = 0; k < K; ++k) {
-          const int64_t r = r0 - 1 + 64 * k + lane;
-          if (r >= r0 && r < R) {
-            const long long sr = srel[k * 64 + lane];
-            const long long sf = ((need_prefix >> k) & 1u) ? pre + sr : sr;
-            const float s = (float)((double)sf * (1.0 / kFix));
-            *reinterpret_cast<float2*>(A.vs + 2 * r) = make_float2(s, s);
-          }
-        }
-      }
-    }
-  }
-  if (PREC == PS_PREC_FP32_FIXUP) {
-    unsigned long long v = fixups;
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if (lane == 0 && v) atomicAdd(&A.st->fixups, v);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Role-split emit (mapping stage 2).  The same tiles, tickets, look-back and
-// outputs as emit_kernel, but each window of link slots is swept twice: once
-// over its segment ribs, 64 at a time in rib order, then over its pivot ribs.
-// A wavefront never holds both roles, so the t solve and the point run with
-// every lane busy, and pivot ribs cost only their angle, direction and
-// vertices.  Chords join consecutive ribs of one segment, so the arc length
-// is a scan over the segment ribs alone (a path restarts at its first segment
-// rib); a pivot's s is the s of its segment's last rib, or 0 for a start cap.
+constexpr int kWin = 12;
 struct SplitLDS {
   long long off[kWin + 1];
   LinkRec rec[kWin];
@@ -1191,9 +1079,8 @@ __device__ __forceinline__ bool finish_tile(const EmitArgs& A, const TileState& 
 }
 
 template <int K, int PREC, bool WXY, bool WS>
-// 4 wavefronts per SIMD (at most 128 VGPRs, which the FP64 solve fits without
-// spilling once the wave index is known to be wave-uniform); how many are
-// resident is then up to the LDS per workgroup, which K sets.
+// 4 wavefronts per SIMD (at most 128 VGPRs); how many are resident is then up
+// to the LDS per workgroup, which K sets.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 emit_split_kernel(EmitArgs A) {
   extern __shared__ unsigned char smem_raw[];
@@ -1201,6 +1088,7 @@ emit_split_kernel(EmitArgs A) {
   SplitLDS& w = *reinterpret_cast<SplitLDS*>(wave_lds);
   long long* const srel_base = reinterpret_cast<long long*>(wave_lds + sizeof(SplitLDS));   // 2 x (rib - r0)
   __shared__ double2 sc_tab[kSinTab];
+  __shared__ float2 sc_tab32[PREC == PS_PREC_FP32 ? kSinTab : 1];
   const int lane = threadIdx.x & 63;
   const int64_t L = A.n_links;
   const int64_t R = A.off[L];
@@ -1209,18 +1097,23 @@ emit_split_kernel(EmitArgs A) {
   const int64_t n_tiles = (R + TS - 1) / TS;
   if (2 * R > A.capacity || n_tiles > A.max_tiles) return;
   unsigned long long fixups = 0;
-  __shared__ unsigned int group_ticket;
+  __shared__ unsigned int group_ticket[2];
+  TileRounds<WS> rounds;
   const int n_waves = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   TileState parked;
   parked.tile = -1; parked.r0 = parked.r1 = 0; parked.agg = 0;
   parked.seen_start = parked.any_need = false; parked.buf = 0;
   // a workgroup without a tile leaves before filling the sincos table
-  unsigned int ticket = take_group_ticket(&A.st->tile_counter, group_ticket);
+  unsigned int ticket = rounds.first(&A.st->tile_counter, group_ticket);
   if ((int64_t)ticket * n_waves >= n_tiles) return;
   fill_sincos_tab(sc_tab);
+  if (PREC == PS_PREC_FP32) {
+    __syncthreads();
+    fill_sincos_tab32(sc_tab32, sc_tab);
+  }
   __syncthreads();
-  for (;; ticket = take_group_ticket(&A.st->tile_counter, group_ticket)) {
+  for (;; ticket = rounds.next(&A.st->tile_counter, group_ticket)) {
     const int64_t first_tile = (int64_t)ticket * n_waves;
     if (first_tile >= n_tiles) break;
     const int64_t tile = first_tile + wave;
@@ -1282,8 +1175,9 @@ emit_split_kernel(EmitArgs A) {
         for (int q0 = 0; q0 < NS; q0 += 64) {
           const int q = q0 + lane;
           RibOut o;
-          o.gx = o.gy = o.t = 0; o.chord_ok = false; o.seg_path_start = false; o.fixed = false;
+          o.gx = o.gy = o.t = 0; o.fixed = false;
           int rel = -1;   // rib - r0
+          bool chord_ok = false, path_start = false;
           // largest i with segpos[i] <= q (the slot holding q: of equal
           // positions the last one has the ribs); the positions do not
           // decrease, so only the slots from i_lo up to the first one that
@@ -1298,23 +1192,27 @@ emit_split_kernel(EmitArgs A) {
           i_lo = __builtin_amdgcn_readlane(i, 63);
           if (q < NS) {
             const int d = q - w.segpos[i];
+            const int j = w.jfirst[i] + d;
             rel = w.first[i] - 1 + d;
-            compute_rib<PREC, kSegOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, sc_tab, o);
+            const LinkRec& rp = w.rec[i];
+            seg_rib<PREC>(rp, j, rib_ival(rp, j), A.fix_tol, sc_tab, sc_tab32, o);
             if (WXY && rel >= 0) {
               store_pair(vxt, rel, o.Nx, o.Px);
               store_pair(vyt, rel, o.Ny, o.Py);
             }
             fixups += o.fixed ? 1 : 0;
+            chord_ok = j > 0;
+            path_start = (rp.flags & kFirstSegInPath) && j == 0;
           }
           if (WS) {
             const bool mine = q < NS && rel >= 0;
             const double pgx = wave_shr1(o.gx, cgx), pgy = wave_shr1(o.gy, cgy), pt = wave_shr1(o.t, ct);
             long long c = 0;
-            if (mine && o.chord_ok && o.t >= pt) {
+            if (mine && chord_ok && o.t >= pt) {
               const double dx = o.gx - pgx, dy = o.gy - pgy;
               c = fix_round(sqrt64(dx * dx + dy * dy) * kFix);
             }
-            int f = (mine && o.seg_path_start) ? 1 : 0;
+            int f = (mine && path_start) ? 1 : 0;
             if (__ballot(f != 0 || c >= (1ll << 50)) == 0ull) {
               unsigned lo = (unsigned)c & 0xffffffu, hi = (unsigned)(c >> 24);
               lo = scan_step_u32<0x111, 0xf>(lo); hi = scan_step_u32<0x111, 0xf>(hi);
@@ -1364,7 +1262,7 @@ emit_split_kernel(EmitArgs A) {
             const int d = pq - w.pivpos[i];
             const int rel = w.first[i] - 1 + d;   // >= 0: pivots never reach back before r0
             RibOut o;
-            compute_rib<PREC, kPivotOnly>(w.rec[i], w.jfirst[i] + d, A.fix_tol, A.miter_limit, sc_tab, o);
+            piv_rib<PREC>(w.rec[i], w.jfirst[i] + d, A.miter_limit, sc_tab, sc_tab32, o);
             if (WXY) {
               store_pair(vxt, rel, o.Nx, o.Px);
               store_pair(vyt, rel, o.Ny, o.Py);
@@ -1407,6 +1305,191 @@ emit_split_kernel(EmitArgs A) {
   }
 }
 
+// PS_MAP_LINKS: the same tiles of 64*K ribs, tickets, parking and
+// look-back, but a wavefront walks a tile link by link, all 64 lanes on ribs
+// of one link at a time.  The link's header and body are then the same for
+// every lane and come through scalar loads into scalar registers (the loads
+// go through the constant address space), so there is no LDS window, no slot
+// search and no per-lane record; the price is the lanes a link leaves idle
+// in its last 64.  Chords and the arc-length scan are as in the tiles
+// mapping, except that a path can only start at lane 0 (the first rib of its
+// first segment), so the scan never needs the segmented form.
+// A wavefront-uniform load of T at p into scalar registers: the words are
+// read through the constant address space, which the compiler turns into
+// scalar loads when the address is uniform.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  typedef __attribute__((address_space(4))) const unsigned int* CU32;
+  const CU32 q = (CU32)p;
+  unsigned int w[sizeof(T) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+  T v;
+  __builtin_memcpy(&v, w, sizeof(T));
+  return v;
+}
+
+__host__ __device__ constexpr size_t emit_links_lds_per_wave(int K, bool ws) {
+  return ws ? 2 * (size_t)K * 64 * sizeof(long long) : 16;
+}
+
+// inclusive 64-bit sum over the wavefront as two exact 32-bit scans (the
+// low 24 and the high bits of chords below 2^50 units), or as a plain 64-bit
+// scan when a chord is longer
+__device__ __forceinline__ long long wave_sum_incl(long long c) {
+  if (__ballot(c >= (1ll << 50)) == 0ull) {
+    unsigned lo = (unsigned)c & 0xffffffu, hi = (unsigned)(c >> 24);
+    lo = scan_step_u32<0x111, 0xf>(lo); hi = scan_step_u32<0x111, 0xf>(hi);
+    lo = scan_step_u32<0x112, 0xf>(lo); hi = scan_step_u32<0x112, 0xf>(hi);
+    lo = scan_step_u32<0x114, 0xf>(lo); hi = scan_step_u32<0x114, 0xf>(hi);
+    lo = scan_step_u32<0x118, 0xf>(lo); hi = scan_step_u32<0x118, 0xf>(hi);
+    lo = scan_step_u32<0x142, 0xa>(lo); hi = scan_step_u32<0x142, 0xa>(hi);
+    lo = scan_step_u32<0x143, 0xc>(lo); hi = scan_step_u32<0x143, 0xc>(hi);
+    return (long long)(((unsigned long long)hi << 24) + lo);
+  }
+  c += dpp_i64<0x111, 0xf>(c);
+  c += dpp_i64<0x112, 0xf>(c);
+  c += dpp_i64<0x114, 0xf>(c);
+  c += dpp_i64<0x118, 0xf>(c);
+  c += dpp_i64<0x142, 0xa>(c);
+  c += dpp_i64<0x143, 0xc>(c);
+  return c;
+}
+
+template <int K, int PREC, bool WXY, bool WS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+emit_links_kernel(EmitArgs A) {
+  extern __shared__ unsigned char smem_raw[];
+  long long* const srel_base =
+      reinterpret_cast<long long*>(smem_raw + (threadIdx.x >> 6) * emit_links_lds_per_wave(K, WS));
+  __shared__ double2 sc_tab[kSinTab];
+  __shared__ float2 sc_tab32[PREC == PS_PREC_FP32 ? kSinTab : 1];
+  const int lane = threadIdx.x & 63;
+  const int64_t L = A.n_links;
+  const int64_t R = A.off[L];
+  constexpr int TS = 64 * K;
+  constexpr unsigned long long kNeed = 1ull << 63;   // "add the tile's prefix"
+  const int64_t n_tiles = (R + TS - 1) / TS;
+  if (2 * R > A.capacity || n_tiles > A.max_tiles) return;
+  unsigned long long fixups = 0;
+  __shared__ unsigned int group_ticket[2];
+  TileRounds<WS> rounds;
+  const int n_waves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  TileState parked;
+  parked.tile = -1; parked.r0 = parked.r1 = 0; parked.agg = 0;
+  parked.seen_start = parked.any_need = false; parked.buf = 0;
+  unsigned int ticket = rounds.first(&A.st->tile_counter, group_ticket);
+  if ((int64_t)ticket * n_waves >= n_tiles) return;
+  fill_sincos_tab(sc_tab);
+  if (PREC == PS_PREC_FP32) {
+    __syncthreads();
+    fill_sincos_tab32(sc_tab32, sc_tab);
+  }
+  __syncthreads();
+  for (;; ticket = rounds.next(&A.st->tile_counter, group_ticket)) {
+    const int64_t first_tile = (int64_t)ticket * n_waves;
+    if (first_tile >= n_tiles) break;
+    const int64_t tile = first_tile + wave;
+    if (tile < n_tiles) {
+      const int buf = (WS && parked.tile >= 0) ? 1 - parked.buf : 0;
+      long long* const srel = srel_base + (size_t)buf * (64 * K);
+      const int64_t r0 = tile * TS;
+      const int64_t r1 = (r0 + TS < R) ? r0 + TS : R;
+      const uint32_t tile_bytes = (uint32_t)(r1 - r0) * 8u;
+      const __amdgpu_buffer_rsrc_t vxt = tile_rsrc(A.vx + 2 * r0, tile_bytes);
+      const __amdgpu_buffer_rsrc_t vyt = tile_rsrc(A.vy + 2 * r0, tile_bytes);
+      long long run = 0;          // segment chord sum since the tile start or its last path start
+      bool seen_start = false;
+      bool any_need = false;
+      unsigned long long end_val = kNeed;   // s at the last segment rib so far (bit 63: add the prefix)
+      for (int64_t l = __builtin_amdgcn_readfirstlane((int)A.tile_link[tile]); l < L; ++l) {
+        const long long a = load_uniform(A.off + l), b = load_uniform(A.off + l + 1);
+        if (a >= r1) break;
+        if (b <= r0 || b == a) continue;   // no rib in the tile
+        const LinkRec rp = load_uniform(A.rec + l);
+        if (rp.role == ROLE_SEG) {
+          // a segment begun in an earlier tile also gives rib r0 - 1, the
+          // first chord's other end
+          const long long start = a < r0 ? r0 - 1 : a;
+          const long long end = b < r1 ? b : r1;
+          double cgx = 0, cgy = 0, ct = 0;
+          for (long long q0 = start; q0 < end; q0 += 64) {
+            const long long rib = q0 + lane;
+            const bool act = rib < end;
+            const int j = (int)(rib - a);
+            const int rel = (int)(rib - r0);
+            const bool mine = act && rib >= r0;
+            RibOut o;
+            o.gx = o.gy = o.t = 0; o.fixed = false;
+            if (act) seg_rib<PREC>(rp, j, rib_ival_uniform(rp, j), A.fix_tol, sc_tab, sc_tab32, o);
+            if (WXY && mine) {
+              store_pair(vxt, rel, o.Nx, o.Px);
+              store_pair(vyt, rel, o.Ny, o.Py);
+            }
+            fixups += (mine && o.fixed) ? 1 : 0;
+            if (WS) {
+              const double pgx = wave_shr1(o.gx, cgx), pgy = wave_shr1(o.gy, cgy), pt = wave_shr1(o.t, ct);
+              long long c = 0;
+              if (mine && j > 0 && o.t >= pt) {
+                const double dx = o.gx - pgx, dy = o.gy - pgy;
+                c = fix_round(sqrt64(dx * dx + dy * dy) * kFix);
+              }
+              // a path restarts at the first rib of its first segment
+              if (q0 == a && (rp.flags & kFirstSegInPath)) { run = 0; seen_start = true; }
+              c = wave_sum_incl(c);
+              const unsigned long long v = (unsigned long long)(run + c) | (seen_start ? 0ull : kNeed);
+              if (mine) srel[rel] = (long long)v;
+              any_need = any_need || !seen_start;
+              run += readlane_i64(c, 63);
+              const int last = (end - q0 < 64) ? (int)(end - q0) - 1 : 63;
+              if (end == b && q0 + 64 >= end) end_val = (unsigned long long)readlane_i64((long long)v, last);
+              cgx = readlane_f64(o.gx, last); cgy = readlane_f64(o.gy, last); ct = readlane_f64(o.t, last);
+            }
+          }
+        } else {
+          const long long start = a < r0 ? r0 : a;
+          const long long end = b < r1 ? b : r1;
+          // a join or end cap takes its segment's end value, a start cap 0
+          const unsigned long long pv = (rp.role == ROLE_SCAP) ? 0ull : end_val;
+          if (WS && (pv & kNeed)) any_need = true;
+          for (long long q0 = start; q0 < end; q0 += 64) {
+            const long long rib = q0 + lane;
+            if (rib < end) {
+              const int rel = (int)(rib - r0);
+              RibOut o;
+              piv_rib<PREC>(rp, (int)(rib - a), A.miter_limit, sc_tab, sc_tab32, o);
+              if (WXY) {
+                store_pair(vxt, rel, o.Nx, o.Px);
+                store_pair(vyt, rel, o.Ny, o.Py);
+              }
+              if (WS) srel[rel] = (long long)pv;
+            }
+          }
+        }
+      }
+      if (WS) {
+        const unsigned long long agg = (unsigned long long)run & kValMask;
+        if (lane == 0) desc_publish(&A.desc[tile], ((seen_start ? 2ull : 1ull) << 62) | agg);
+        TileState cur;
+        cur.tile = tile; cur.r0 = r0; cur.r1 = r1; cur.agg = agg;
+        cur.seen_start = seen_start; cur.any_need = any_need; cur.buf = buf;
+        if (parked.tile >= 0) {
+          finish_tile<K>(A, parked, srel_base, true);
+          parked.tile = -1;
+        }
+        if (!finish_tile<K>(A, cur, srel_base, false)) parked = cur;
+      }
+    }
+  }
+  if (WS && parked.tile >= 0) finish_tile<K>(A, parked, srel_base, true);
+  if (PREC == PS_PREC_FP32_FIXUP) {
+    unsigned long long v = fixups;
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0 && v) atomicAdd(&A.st->fixups, v);
+  }
+}
+
 // ===========================================================================
 // Uniform parametric baseline and facet statistics (Sec. "Versus Uniform
 // Parametric Tessellation")
@@ -1421,45 +1504,56 @@ struct UniformArgs {
   double miter_limit;
 };
 
-// One thread per link slot: segment ribs at t_j = j/N on Eq. NaiveStroking,
-// joins and caps as the polar emit.
+// largest l with off[l] <= r (the link holding rib r, r < off[n_links])
+__device__ __forceinline__ int64_t rib_link(const int64_t* off, int64_t n_links, int64_t r) {
+  int64_t a = 0, b = n_links - 1;
+  while (a < b) {
+    const int64_t m = (a + b + 1) >> 1;
+    if (off[m] <= r) a = m; else b = m - 1;
+  }
+  return a;
+}
+
+// One thread per rib: segment ribs at t_j = j/N on Eq. NaiveStroking (N + 1
+// ribs; the unit left normal of g'(t_j), taken 2^-20/N further into the
+// segment where g' vanishes), joins and caps as the polar emit.
 __global__ void __launch_bounds__(256) uniform_emit_kernel(UniformArgs A) {
   __shared__ double2 sc_tab[kSinTab];
   fill_sincos_tab(sc_tab);
   __syncthreads();
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= A.n_links || 2 * A.off[A.n_links] > A.capacity) return;
-  const int64_t r0 = A.off[l], n = A.off[l + 1] - r0;
-  if (n <= 0) return;
-  const LinkRec& rp = A.rec[l];
-  if (rp.role != ROLE_SEG) {
-    for (int j = 0; j < (int)n; ++j) {
+  const int64_t R = A.off[A.n_links];
+  if (2 * R > A.capacity) return;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = rib_link(A.off, A.n_links, r);
+    const int j = (int)(r - A.off[l]);
+    const LinkRec& rp = A.rec[l];
+    float2 ox, oy;
+    if (rp.role != ROLE_SEG) {
       RibOut o;
-      compute_rib<PS_PREC_FP64, kPivotOnly>(rp, j, 0.f, A.miter_limit, sc_tab, o);
-      *reinterpret_cast<float2*>(A.vx + 2 * (r0 + j)) = make_float2(o.Nx, o.Px);
-      *reinterpret_cast<float2*>(A.vy + 2 * (r0 + j)) = make_float2(o.Ny, o.Py);
+      piv_rib<PS_PREC_FP64>(rp, j, A.miter_limit, sc_tab, nullptr, o);
+      ox = make_float2(o.Nx, o.Px); oy = make_float2(o.Ny, o.Py);
+    } else {
+      double X[4], Y[4];
+      for (int i = 0; i < 4; ++i) { X[i] = rp.x[i]; Y[i] = rp.y[i]; }
+      const double w = rp.w, rad = rp.r;
+      const Hodo<double> h = hodo_of<double>(rp.kind, X, Y, w);
+      const int N = (int)(A.off[l + 1] - A.off[l]) - 1;   // >= 1: a segment has two ribs or more
+      const double t = (double)j / (double)N;
+      double gx, gy, hx, hy;
+      eval_point(rp.kind, X, Y, w, t, gx, gy);
+      hodo_eval(h, t, hx, hy);   // a positive multiple of g'(t)
+      if (hx == 0.0 && hy == 0.0) {
+        const double d = ldexp(1.0, -20) / N;
+        hodo_eval(h, t < 0.5 ? t + d : t - d, hx, hy);
+      }
+      const double inv = 1.0 / sqrt(hx * hx + hy * hy);
+      const double nx = -hy * inv, ny = hx * inv;
+      ox = make_float2((float)(gx - rad * nx), (float)(gx + rad * nx));
+      oy = make_float2((float)(gy - rad * ny), (float)(gy + rad * ny));
     }
-    return;
-  }
-  double X[4], Y[4];
-  for (int i = 0; i < 4; ++i) { X[i] = rp.x[i]; Y[i] = rp.y[i]; }
-  const double w = rp.w, rad = rp.r;
-  const Hodo<double> h = hodo_of<double>(rp.kind, X, Y, w);
-  const int N = (int)n - 1;
-  for (int j = 0; j <= N; ++j) {
-    const double t = (double)j / (double)N;
-    double gx, gy, hx, hy;
-    eval_point(rp.kind, X, Y, w, t, gx, gy);
-    hodo_eval(h, t, hx, hy);   // a positive multiple of g'(t)
-    if (hx == 0.0 && hy == 0.0) {
-      const double d = ldexp(1.0, -20) / N;
-      hodo_eval(h, t < 0.5 ? t + d : t - d, hx, hy);
-    }
-    const double inv = 1.0 / sqrt(hx * hx + hy * hy);
-    const double nx = -hy * inv, ny = hx * inv;
-    const int64_t r = r0 + j;
-    *reinterpret_cast<float2*>(A.vx + 2 * r) = make_float2((float)(gx - rad * nx), (float)(gx + rad * nx));
-    *reinterpret_cast<float2*>(A.vy + 2 * r) = make_float2((float)(gy - rad * ny), (float)(gy + rad * ny));
+    *reinterpret_cast<float2*>(A.vx + 2 * r) = ox;
+    *reinterpret_cast<float2*>(A.vy + 2 * r) = oy;
   }
 }
 
@@ -2060,16 +2154,26 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(PS_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+// An emit mapping: PS_MAP_TILES (K ribs per lane) or PS_MAP_LINKS, and the
+// wavefronts per workgroup.
 struct EmitConfig {
+  int map = PS_MAP_TILES;
   int K = 7;
   int waves = 4;
-  int stage = 2;   // 0 rib-major (global records), 1 rib-major (LDS records), 2 role-split
 };
-EmitConfig g_cfg;
-bool g_autotune = true;
-std::mutex g_mu;
 
 int64_t n_links_of(const ps_batch* b) { return 2 * (int64_t)b->n_segs + b->n_paths; }
+
+bool valid_k(int K) { return K == 4 || K == 6 || K == 7 || K == 8 || K == 16; }
+
+// The mapping of an unplanned call (or of a plan told its mapping).
+EmitConfig config_of(const ps_params* p) {
+  EmitConfig c;
+  if (p->emit_mapping == PS_MAP_LINKS) c.map = PS_MAP_LINKS;
+  if (p->emit_ribs_per_lane) c.K = p->emit_ribs_per_lane;
+  if (p->emit_waves) c.waves = p->emit_waves;
+  return c;
+}
 
 int check_batch(const ps_batch* b) {
   if (!b) return fail(PS_E_ARG, "batch is NULL");
@@ -2092,6 +2196,12 @@ int check_params(const ps_params* p) {
     return fail(PS_E_ARG, "unknown precision mode %d", p->precision);
   if (!(p->miter_limit >= 1.0) || !std::isfinite(p->miter_limit))
     return fail(PS_E_ARG, "miter_limit must be finite and >= 1 (got %g)", p->miter_limit);
+  if (p->emit_mapping < PS_MAP_DEFAULT || p->emit_mapping > PS_MAP_LINKS)
+    return fail(PS_E_ARG, "unknown emit mapping %d", p->emit_mapping);
+  if (p->emit_ribs_per_lane != 0 && !valid_k(p->emit_ribs_per_lane))
+    return fail(PS_E_ARG, "emit_ribs_per_lane must be 0, 4, 6, 7, 8 or 16");
+  if (p->emit_waves < 0 || p->emit_waves > 4)
+    return fail(PS_E_ARG, "emit_waves must be in [0, 4] (at most 256 threads per workgroup)");
   if (p->n_dash != 0) {
     if (p->n_dash < 2 || (p->n_dash & 1) || p->n_dash > kMaxDash)
       return fail(PS_E_ARG, "dash pattern needs an even count in [2, %d]", kMaxDash);
@@ -2180,13 +2290,13 @@ int do_scan_i32(const int32_t* in, int64_t n_max, const int64_t* n_dev, int64_t*
   return PS_OK;
 }
 
-// Emit mappings: 0 rib-major with records read from global memory, 1
-// rib-major with records staged in LDS, 2 role-split (records in LDS).
-template <int K, int PREC, bool WXY, bool WS, int MAP>
+// PS_MAP_TILES (the role-split walk of rib tiles) and PS_MAP_LINKS (one link
+// per wavefront iteration), both over tiles of 64*K ribs.
+template <int MAP, int K, int PREC, bool WXY, bool WS>
 void emit_launcher(EmitArgs a, int grid, int block, hipStream_t s) {
   // above 64 KiB of dynamic LDS a kernel has to be allowed it once (every
   // configuration is first launched eagerly, before any graph capture)
-  if constexpr (MAP == 2) {
+  if constexpr (MAP == PS_MAP_TILES) {
     const size_t lds = (size_t)(block / 64) * emit_split_lds_per_wave(K, WS);
     static const hipError_t allowed = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&emit_split_kernel<K, PREC, WXY, WS>),
@@ -2194,56 +2304,49 @@ void emit_launcher(EmitArgs a, int grid, int block, hipStream_t s) {
     (void)allowed;
     hipLaunchKernelGGL((emit_split_kernel<K, PREC, WXY, WS>), dim3(grid), dim3(block), lds, s, a);
   } else {
-    constexpr bool STAGE = MAP == 1;
-    const size_t lds = (size_t)(block / 64) * emit_lds_per_wave(K, WS, STAGE);
+    const size_t lds = (size_t)(block / 64) * emit_links_lds_per_wave(K, WS);
     static const hipError_t allowed = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&emit_kernel<K, PREC, WXY, WS, STAGE>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * emit_lds_per_wave(K, WS, STAGE)));
+        reinterpret_cast<const void*>(&emit_links_kernel<K, PREC, WXY, WS>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * emit_links_lds_per_wave(K, WS)));
     (void)allowed;
-    hipLaunchKernelGGL((emit_kernel<K, PREC, WXY, WS, STAGE>), dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((emit_links_kernel<K, PREC, WXY, WS>), dim3(grid), dim3(block), lds, s, a);
   }
 }
 
 using EmitLaunch = void (*)(EmitArgs, int, int, hipStream_t);
 
-template <int PREC, bool WXY, bool WS, int MAP>
+template <int MAP, int PREC, bool WXY, bool WS>
 EmitLaunch pick_k(int K) {
   switch (K) {
-    case 4: return emit_launcher<4, PREC, WXY, WS, MAP>;
-    case 6: return emit_launcher<6, PREC, WXY, WS, MAP>;
-    case 7: return emit_launcher<7, PREC, WXY, WS, MAP>;
-    case 8: return emit_launcher<8, PREC, WXY, WS, MAP>;
-    case 16: return emit_launcher<16, PREC, WXY, WS, MAP>;
+    case 4: return emit_launcher<MAP, 4, PREC, WXY, WS>;
+    case 6: return emit_launcher<MAP, 6, PREC, WXY, WS>;
+    case 7: return emit_launcher<MAP, 7, PREC, WXY, WS>;
+    case 8: return emit_launcher<MAP, 8, PREC, WXY, WS>;
+    case 16: return emit_launcher<MAP, 16, PREC, WXY, WS>;
     default: return nullptr;
   }
 }
 
-template <bool WXY, bool WS, int MAP>
+template <int MAP, bool WXY, bool WS>
 EmitLaunch pick_prec(int prec, int K) {
   switch (prec) {
-    case PS_PREC_FP32: return pick_k<PS_PREC_FP32, WXY, WS, MAP>(K);
-    case PS_PREC_FP32_FIXUP: return pick_k<PS_PREC_FP32_FIXUP, WXY, WS, MAP>(K);
-    default: return pick_k<PS_PREC_FP64, WXY, WS, MAP>(K);
+    case PS_PREC_FP32: return pick_k<MAP, PS_PREC_FP32, WXY, WS>(K);
+    case PS_PREC_FP32_FIXUP: return pick_k<MAP, PS_PREC_FP32_FIXUP, WXY, WS>(K);
+    default: return pick_k<MAP, PS_PREC_FP64, WXY, WS>(K);
   }
 }
 
 template <int MAP>
 EmitLaunch pick_mode(int prec, int K, bool wxy, bool ws) {
-  if (wxy && ws) return pick_prec<true, true, MAP>(prec, K);
-  if (wxy) return pick_prec<true, false, MAP>(prec, K);
-  return pick_prec<false, true, MAP>(prec, K);
+  if (wxy && ws) return pick_prec<MAP, true, true>(prec, K);
+  if (wxy) return pick_prec<MAP, true, false>(prec, K);
+  return pick_prec<MAP, false, true>(prec, K);
 }
 
-EmitLaunch pick_emit(int prec, int K, bool wxy, bool ws, int map) {
-  switch (map) {
-    case 0: return pick_mode<0>(prec, K, wxy, ws);
-    case 1: return pick_mode<1>(prec, K, wxy, ws);
-    case 2: return pick_mode<2>(prec, K, wxy, ws);
-    default: return nullptr;
-  }
+EmitLaunch pick_emit(int map, int prec, int K, bool wxy, bool ws) {
+  if (map == PS_MAP_LINKS) return pick_mode<PS_MAP_LINKS>(prec, K, wxy, ws);
+  return pick_mode<PS_MAP_TILES>(prec, K, wxy, ws);
 }
-
-bool valid_k(int K) { return K == 4 || K == 6 || K == 7 || K == 8 || K == 16; }
 
 // Largest Newton step (in t) accepted when polishing an FP32 root in FP64;
 // a larger step means the FP32 root was ill-conditioned and the rib is
@@ -2272,24 +2375,24 @@ int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, cons
 }
 
 int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float* vx, float* vy,
-                float* vs, int64_t cap, const WsView& v, const WsLayout& w, int K, int waves,
-                int stage, hipStream_t s) {
+                float* vs, int64_t cap, const WsView& v, const WsLayout& w, const EmitConfig& c,
+                hipStream_t s) {
   const int64_t L = n_links_of(b);
-  const int TS = (stage == 2) ? 64 * K : 64 * K - 1;   // the role-split tile has no overlap lane
-  EmitLaunch fn = pick_emit(p->precision, K, vx != nullptr, vs != nullptr, stage);
-  if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", K);
+  const int TS = 64 * c.K;
+  EmitLaunch fn = pick_emit(c.map, p->precision, c.K, vx != nullptr, vs != nullptr);
+  if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", c.K);
+  if (c.waves < 1 || c.waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
   const unsigned prep_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (L + 255) / 256), 8192);
   hipLaunchKernelGGL(emit_prepare_kernel, dim3(prep_grid), dim3(256), 0, s, off, L, TS, v.tile_link,
                      v.desc, v.st, cap, w.max_tiles);
   EmitArgs a;
-  a.B = *b; a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
+  a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
   a.max_tiles = w.max_tiles;
   a.fix_tol = fixup_tolerance();
   a.miter_limit = p->miter_limit;
-  if (waves < 1 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
-  const int block = 64 * waves;   // never above the kernel's launch bound of 256
-  const int grid = num_cus() * (16 / waves);
+  const int block = 64 * c.waves;   // never above the kernel's launch bound of 256
+  const int grid = num_cus() * (16 / c.waves);
   fn(a, grid, block, s);
   PS_HIP(hipGetLastError());
   return PS_OK;
@@ -2343,10 +2446,6 @@ int static_scratch(void** out) {
   return PS_OK;
 }
 
-EmitConfig current_cfg() {
-  std::lock_guard<std::mutex> lk(g_mu);
-  return g_cfg;
-}
 
 }  // namespace
 
@@ -2366,7 +2465,7 @@ struct ps_plan {
   int64_t dash_rib_cap, dash_cap;
   void* ws;
   WsLayout w;
-  int K, waves, stage;
+  EmitConfig cfg;
   // graph[0]: count -> scan -> emit (-> dash).  graph[1]: the same chain with
   // an event-record node between scan and emit and one after the emit; the
   // nodes record the plan's own events unless a timed launch points them at
@@ -2392,8 +2491,7 @@ int enqueue_count(ps_plan* P, hipStream_t s) {
 int enqueue_emit(ps_plan* P, hipStream_t s) {
   const WsView v = ws_view(P->ws, P->w);
   int rc;
-  if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->K, P->waves,
-                        P->stage, s)))
+  if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->cfg, s)))
     return rc;
   if (P->p.n_dash > 0) {
     if ((rc = launch_dash(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->dx, P->dy, P->ds, P->range,
@@ -2441,16 +2539,16 @@ int capture_plan(ps_plan* P, int timed) {
   return PS_OK;
 }
 
-int time_emit(ps_plan* P, int K, int waves, int stage, hipStream_t s, float* ms) {
+int time_emit(ps_plan* P, const EmitConfig& c, hipStream_t s, float* ms) {
   const WsView v = ws_view(P->ws, P->w);
   hipEvent_t e0, e1;
   PS_HIP(hipEventCreate(&e0));
   PS_HIP(hipEventCreate(&e1));
-  int rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, stage, s);
+  int rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, c, s);
   float best = 1e30f;
   for (int rep = 0; rep < 3 && rc == PS_OK; ++rep) {
     (void)hipEventRecord(e0, s);
-    rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, K, waves, stage, s);
+    rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, c, s);
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float t = 0;
@@ -2485,24 +2583,6 @@ size_t ps_workspace_bytes(const ps_batch* b, const ps_params* p, int64_t vertex_
   return ws_layout(n_links_of(b), std::max<int64_t>(0, vertex_capacity), nd).total;
 }
 
-int ps_set_emit_config(int32_t K, int32_t waves, int32_t stage) {
-  if (K != 0 && !valid_k(K)) return fail(PS_E_ARG, "ribs_per_lane must be 4, 6, 7, 8 or 16");
-  if (waves < 0 || waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
-  if (stage < -1 || stage > 2) return fail(PS_E_ARG, "stage must be -1 (keep), 0, 1 or 2");
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (K) g_cfg.K = K;
-  if (waves) g_cfg.waves = waves;
-  if (stage >= 0) g_cfg.stage = stage;
-  return PS_OK;
-}
-
-int ps_set_plan_autotune(int32_t on) {
-  if (on != 0 && on != 1) return fail(PS_E_ARG, "autotune must be 0 or 1");
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_autotune = on != 0;
-  return PS_OK;
-}
-
 int ps_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, void* ws, size_t ws_bytes,
              void* stream) {
   int rc;
@@ -2532,9 +2612,7 @@ int ps_emit(const ps_batch* b, const ps_params* p, const int64_t* offsets, float
   if (cap < 0) return fail(PS_E_ARG, "negative capacity");
   const WsLayout w = ws_layout(n_links_of(b), cap, 0);
   if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
-  const EmitConfig c = current_cfg();
-  return launch_emit(b, p, offsets, vx, vy, vs, cap, ws_view(ws, w), w, c.K, c.waves, c.stage,
-                     (hipStream_t)stream);
+  return launch_emit(b, p, offsets, vx, vy, vs, cap, ws_view(ws, w), w, config_of(p), (hipStream_t)stream);
 }
 
 int ps_arclen(const ps_batch* b, const ps_params* p, const int64_t* offsets, float* vs, int64_t cap,
@@ -2545,9 +2623,8 @@ int ps_arclen(const ps_batch* b, const ps_params* p, const int64_t* offsets, flo
   if (cap < 0) return fail(PS_E_ARG, "negative capacity");
   const WsLayout w = ws_layout(n_links_of(b), cap, 0);
   if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
-  const EmitConfig c = current_cfg();
-  return launch_emit(b, p, offsets, nullptr, nullptr, vs, cap, ws_view(ws, w), w, c.K, c.waves,
-                     c.stage, (hipStream_t)stream);
+  return launch_emit(b, p, offsets, nullptr, nullptr, vs, cap, ws_view(ws, w), w, config_of(p),
+                     (hipStream_t)stream);
 }
 
 int ps_emit_uniform(const ps_batch* b, const ps_params* p, const int64_t* offsets, float* vx,
@@ -2563,7 +2640,7 @@ int ps_emit_uniform(const ps_batch* b, const ps_params* p, const int64_t* offset
   a.rec = v.rec; a.off = offsets; a.n_links = n_links_of(b); a.vx = vx; a.vy = vy;
   a.capacity = cap; a.miter_limit = p->miter_limit;
   if (a.n_links > 0)
-    hipLaunchKernelGGL(uniform_emit_kernel, dim3(grid_for(a.n_links, 256)), dim3(256), 0,
+    hipLaunchKernelGGL(uniform_emit_kernel, dim3(num_cus() * 8), dim3(256), 0,
                        (hipStream_t)stream, a);
   PS_HIP(hipGetLastError());
   return PS_OK;
@@ -2643,10 +2720,9 @@ int ps_stroke_static(const ps_batch* b, const ps_params* p, int32_t* link_ribs, 
   if ((rc = static_scratch(&base))) return rc;
   const hipStream_t s = (hipStream_t)stream;
   const WsView v = ws_view(base, w);
-  const EmitConfig c = current_cfg();
   if ((rc = launch_count(b, p, link_ribs, v, s))) return rc;
   if ((rc = do_scan_i32(link_ribs, n_links_of(b), nullptr, offsets, v.scan, &v.st->total_ribs, s))) return rc;
-  if ((rc = launch_emit(b, p, offsets, vx, vy, vs, cap, v, w, c.K, c.waves, c.stage, s))) return rc;
+  if ((rc = launch_emit(b, p, offsets, vx, vy, vs, cap, v, w, config_of(p), s))) return rc;
   if (status_flags) hipLaunchKernelGGL(copy_status_flags_kernel, dim3(1), dim3(64), 0, s, v.st, status_flags);
   PS_HIP(hipGetLastError());
   return PS_OK;
@@ -2691,31 +2767,28 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   P->graph[0] = P->graph[1] = nullptr; P->exec[0] = P->exec[1] = nullptr;
   P->ev_node[0] = P->ev_node[1] = nullptr; P->ev_own[0] = P->ev_own[1] = nullptr;
   hipStream_t s = (hipStream_t)stream;
-  // autotune the emit mapping on this batch: ribs per lane K, waves per
-  // workgroup, and whether link records are staged in LDS
-  const EmitConfig c0 = current_cfg();
-  P->K = c0.K; P->waves = c0.waves; P->stage = c0.stage;
+  // the emit mapping: the one given, or the fastest on this batch
+  P->cfg = config_of(p);
   const WsView v = ws_view(ws, w);
   if ((rc = launch_count(b, &P->p, link_ribs, v, s)) ||
       (rc = do_scan_i32(link_ribs, n_links_of(b), nullptr, offsets, v.scan, &v.st->total_ribs, s))) {
     delete P;
     return rc;
   }
-  bool tune;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    tune = g_autotune;
-  }
-  float best = 1e30f;
-  const int Ks[5] = {4, 6, 7, 8, 16};
-  const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
-  for (int st = 2; tune && st >= 0; --st)
+  if (p->emit_mapping == PS_MAP_DEFAULT) {
+    float best = 1e30f;
+    const int Ks[5] = {4, 6, 7, 8, 16};
+    const int Ws[3] = {1, 2, 4};   // at most 256 threads: the emit kernel's launch bound
+    for (int mi = 0; mi < 2; ++mi)
     for (int ki = 0; ki < 5; ++ki)
       for (int wi = 0; wi < 3; ++wi) {
+        EmitConfig c;
+        c.map = mi ? PS_MAP_LINKS : PS_MAP_TILES; c.K = Ks[ki]; c.waves = Ws[wi];
         float ms = 0;
-        if ((rc = time_emit(P, Ks[ki], Ws[wi], st, s, &ms))) { delete P; return rc; }
-        if (ms < best) { best = ms; P->K = Ks[ki]; P->waves = Ws[wi]; P->stage = st; }
+        if ((rc = time_emit(P, c, s, &ms))) { delete P; return rc; }
+        if (ms < best) { best = ms; P->cfg = c; }
       }
+  }
   // capture the chain twice: plain, and with the emit's event-record nodes
   if (hipStreamSynchronize(s) != hipSuccess) { delete P; return fail(PS_E_HIP, "stream synchronize failed"); }
   for (int k = 0; k < 2; ++k)
@@ -2757,11 +2830,11 @@ int ps_plan_destroy(ps_plan* P) {
   return PS_OK;
 }
 
-int ps_plan_config(const ps_plan* P, int32_t* K, int32_t* waves, int32_t* stage) {
+int ps_plan_config(const ps_plan* P, int32_t* mapping, int32_t* K, int32_t* waves) {
   if (!P) return fail(PS_E_ARG, "invalid plan");
-  if (K) *K = P->K;
-  if (waves) *waves = P->waves;
-  if (stage) *stage = P->stage;
+  if (mapping) *mapping = P->cfg.map;
+  if (K) *K = P->cfg.K;
+  if (waves) *waves = P->cfg.waves;
   return PS_OK;
 }
 

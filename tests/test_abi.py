@@ -93,20 +93,21 @@ def test_dash_phase_beyond_2_40_periods_rejected():
     assert b"2^40" in lib.ps_last_error()
 
 
-def test_bad_precision_and_emit_config_rejected():
+def test_bad_precision_and_emit_mapping_rejected():
     lib = ps.load()
     b = _batch()
-    p = ps.make_params(0.1, precision=7)
-    assert lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(3, 4, -1) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(8, 99, -1) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(8, 5, -1) == ps.PS_E_ARG   # above the 256-thread launch bound
-    assert lib.ps_set_emit_config(8, 4, 3) == ps.PS_E_ARG
-    assert lib.ps_set_emit_config(7, 4, 2) == ps.PS_OK
-    assert lib.ps_set_emit_config(0, 0, -1) == ps.PS_OK
-    assert lib.ps_set_plan_autotune(2) == ps.PS_E_ARG
-    assert lib.ps_set_plan_autotune(-1) == ps.PS_E_ARG
-    assert lib.ps_set_plan_autotune(1) == ps.PS_OK
+    call = lambda p: lib.ps_count(ctypes.byref(b), ctypes.byref(p), 0x1000, 0x1000, 1 << 30, None)
+    assert call(ps.make_params(0.1, precision=7)) == ps.PS_E_ARG
+    for emit, ok in [((ps.PS_MAP_TILES, 3, 4), False), ((ps.PS_MAP_TILES, 8, 99), False),
+                     ((ps.PS_MAP_TILES, 8, 5), False),      # above the 256-thread launch bound
+                     ((3, 8, 4), False), ((-1, 0, 0), False),
+                     ((ps.PS_MAP_TILES, 7, 4), True), ((ps.PS_MAP_DEFAULT, 0, 0), True),
+                     ((ps.PS_MAP_LINKS, 0, 2), True)]:
+        rc = call(ps.make_params(0.1, emit=emit))
+        if ok:
+            assert rc != ps.PS_E_ARG or b"emit" not in lib.ps_last_error(), emit
+        else:
+            assert rc == ps.PS_E_ARG and b"emit" in lib.ps_last_error(), emit
 
 
 @pytest.mark.parametrize("limit", [0.0, 0.999, float("nan"), float("inf")])
@@ -128,6 +129,7 @@ def test_plan_rejects_null_buffers():
     assert rc == ps.PS_E_ARG and not h.value
     assert lib.ps_plan_launch(None, None) == ps.PS_E_ARG
     assert lib.ps_plan_launch_timed(None, None, None, None) == ps.PS_E_ARG
+    assert lib.ps_plan_config(None, None, None, None) == ps.PS_E_ARG
     assert lib.ps_plan_destroy(None) == ps.PS_OK
 
 

@@ -62,9 +62,9 @@ def _check_arc(vs_gpu, ref_s, k, what=""):
     return float(err.max()) if err.size else 0.0
 
 
-def _compare(b, precision=ps.PS_PREC_FP64, vertex_tol=VERTEX_TOL, check_s=True):
+def _compare(b, precision=ps.PS_PREC_FP64, vertex_tol=VERTEX_TOL, check_s=True, emit=(ps.PS_MAP_DEFAULT, 0, 0)):
     ref = oracle.stroke(b)
-    db, out = _gpu(b, precision)
+    db, out = _gpu(b, precision, emit=emit)
     st = out["status"]
     assert st.flags == 0, st.flags
     np.testing.assert_array_equal(_np(out["link_ribs"]), ref["link_ribs"])
@@ -94,6 +94,11 @@ def test_config1_full():
 @pytest.mark.parametrize("prec", [ps.PS_PREC_FP32_FIXUP, ps.PS_PREC_FP64])
 def test_config2_reduced(prec):
     _compare(W.config2(n_paths=96, max_segs=64), precision=prec)
+
+
+@pytest.mark.parametrize("prec", [ps.PS_PREC_FP32_FIXUP, ps.PS_PREC_FP64])
+def test_config2_reduced_link_mapping(prec):
+    _compare(W.config2(n_paths=96, max_segs=64), precision=prec, emit=(ps.PS_MAP_LINKS, 7, 4))
 
 
 def test_config2_full_in_the_bench_mapping():
@@ -330,19 +335,17 @@ def test_nonfinite_and_bad_values_flagged():
 
 
 # ------------------------------------------------------ mapping / determinism
+MAPPINGS = [(m, K, w) for m in (ps.PS_MAP_TILES, ps.PS_MAP_LINKS) for K in (4, 6, 7, 8, 16) for w in (1, 2, 4)]
+
+
 def test_mappings_agree_and_are_deterministic():
-    import torch
+    # every emit mapping gives the same bits: vertices from per-rib arithmetic
+    # that does not look at the neighbours, arc length from integer sums
     b = W.config2(n_paths=48, max_segs=96)
     outs = []
-    try:
-        for stage in (2, 1, 0):
-            for K in (4, 6, 7, 8, 16):
-                for waves in (1, 4):
-                    ps.ps_set_emit_config(K, waves, stage)
-                    _, o = _gpu(b)
-                    outs.append(((K, waves, stage), _np(o["vx"]), _np(o["vy"]), _np(o["vs"])))
-    finally:
-        ps.ps_set_emit_config(7, 4, 2)   # the default mapping
+    for emit in MAPPINGS:
+        _, o = _gpu(b, emit=emit)
+        outs.append((emit, _np(o["vx"]), _np(o["vy"]), _np(o["vs"])))
     for cfg, vx, vy, vs in outs[1:]:
         assert np.array_equal(vx, outs[0][1]) and np.array_equal(vy, outs[0][2]), cfg
         assert np.array_equal(vs, outs[0][3]), cfg
