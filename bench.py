@@ -72,6 +72,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp64", choices=["fp32", "fp32_fixup", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-per-path", action="store_true", help="skip the per-path form")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 2^20-segment leg at q = pi/256")
     ap.add_argument("--profile", action="store_true", help="few steps, no oracle (for rocprofv3)")
     ap.add_argument("--emit-config", default=None, metavar="M,K,W",
                     help="fixed emit mapping (PS_MAP_* mapping, ribs per lane, waves per group) "
@@ -91,6 +92,7 @@ def main() -> int:
     if args.profile:
         args.no_cpu = True
         args.no_per_path = True
+        args.no_c5 = True
 
     import torch
     import paper_2007_00308_amd as ps
@@ -238,6 +240,16 @@ def main() -> int:
         log(f"errors: {errors}")
         del ref
 
+    c5 = None
+    if not args.no_c5:
+        # the largest configuration: same chain, 2^20 segments, the finest q
+        plan.close()
+        del db
+        torch.cuda.empty_cache()
+        log("C5 at q = pi/256 ...")
+        c5 = c5_leg(torch, ps, W, dev, 256, args.steps, args.warmup)
+        log(f"C5: {c5}")
+
     result = {
         "metric": "stroke vertices/s & % HBM peak, batched vs per-path, <=2e-3 px vs FP64 oracle",
         "value": vps,
@@ -265,6 +277,7 @@ def main() -> int:
         "per_path": per_path,
         "cpu_baseline": cpu,
         "errors": errors,
+        "c5": c5,
     }
     plan.close()
     print(json.dumps(result), flush=True)
@@ -334,44 +347,69 @@ def study_c3(args, torch, ps, W, dev):
     return 0
 
 
+def c5_leg(torch, ps, W, dev, qn: int, steps: int, warmup: int, fixed=(1, 8, 4)) -> dict:
+    """C5 at q = pi/qn: 2^20 segments over 65,536 Zipf(1.2) paths.  The whole
+    step through an autotuned plan (wall clock over `steps` replays) and its
+    emit from the graph's own events, then the emit call alone with the
+    autotuned and with a fixed mapping."""
+    q = math.pi / qn
+    b = W.config5(q=q)
+    db = ps.DeviceBatch(b, device=dev)
+    first = ps.stroke(db, q)
+    R = first["total_ribs"]
+    del first
+    V = 2 * R
+    plan = ps.Plan(db, q, vertex_capacity=V)
+    cfg = plan.config()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, c in ev:
+        a.record(stream); c.record(stream)
+    for _ in range(warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for a, c in ev:
+        plan.launch_timed(a, c)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / steps
+    st = plan.status()
+    assert st.flags == 0 and st.total_ribs == R, f"C5 status flags {st.flags}"
+    emit_ms = sum(a.elapsed_time(c) for a, c in ev) / steps
+    B = algorithmic_bytes(V, b.n_segs, b.n_paths)
+    # the emit call alone: the autotuned mapping vs a fixed one
+    call_ms = {}
+    for name, emit in (("autotuned", cfg), ("fixed", fixed)):
+        pp = ps.make_params(q, emit=emit)
+        for _ in range(2):
+            ps.ps_emit(db, pp, plan.offsets, plan.vx, plan.vy, plan.vs, V, plan.ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            ps.ps_emit(db, pp, plan.offsets, plan.vx, plan.vy, plan.vs, V, plan.ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        call_ms[name] = e0.elapsed_time(e1) / steps
+    plan.close()
+    del db
+    torch.cuda.empty_cache()
+    return {"workload": b.name, "q": f"pi/{qn}", "segments": b.n_segs, "paths": b.n_paths,
+            "ribs": R, "vertices": V, "ms_per_step": ms, "vertices_per_s": V / (ms * 1e-3),
+            "gb_per_s": B / (ms * 1e-3) / 1e9, "emit_ms": emit_ms,
+            "emit_frac": B / (emit_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "autotuned": {"mapping": cfg[0], "K": cfg[1], "waves": cfg[2]},
+            "emit_call_ms_autotuned": call_ms["autotuned"],
+            "fixed": {"mapping": fixed[0], "K": fixed[1], "waves": fixed[2]},
+            "emit_call_ms_fixed": call_ms["fixed"]}
+
+
 def study_c5(args, torch, ps, W, dev):
     """2^20 segments over 65,536 Zipf(1.2) paths at three q; autotuned vs fixed mapping."""
     rows = []
     for qn in (16, 64, 256):
-        q = math.pi / qn
-        b = W.config5(q=q)
-        db = ps.DeviceBatch(b, device=dev)
-        first = ps.stroke(db, q)
-        R = first["total_ribs"]
-        del first
-        plan = ps.Plan(db, q, vertex_capacity=2 * R)
-        cfg = plan.config()
-        ms = _time_plan(torch, plan, args.steps, args.warmup)
-        # the emit call alone: the autotuned mapping vs a fixed one (tiles, K=8, 4 waves)
-        stream = torch.cuda.current_stream()
-        emit_ms = {}
-        for name, emit in (("autotuned", cfg), ("fixed", (ps.PS_MAP_TILES, 8, 4))):
-            pp = ps.make_params(q, emit=emit)
-            for _ in range(2):
-                ps.ps_emit(db, pp, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.steps):
-                ps.ps_emit(db, pp, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            emit_ms[name] = e0.elapsed_time(e1) / args.steps
-        plan.close()
-        V = 2 * R
-        row = {"q": f"pi/{qn}", "ribs": R, "vertices": V, "ms_per_step": ms,
-               "vertices_per_s": V / (ms * 1e-3),
-               "gb_per_s": algorithmic_bytes(V, b.n_segs, b.n_paths) / (ms * 1e-3) / 1e9,
-               "autotuned": {"mapping": cfg[0], "K": cfg[1], "waves": cfg[2]},
-               "emit_ms_autotuned": emit_ms["autotuned"], "emit_ms_fixed_tiles_K8_w4": emit_ms["fixed"]}
+        row = c5_leg(torch, ps, W, dev, qn, args.steps, args.warmup)
         rows.append(row)
         log(str(row))
-        del db
-        torch.cuda.empty_cache()
     print(json.dumps({"study": "c5", "rows": rows}), flush=True)
     return 0
 

@@ -56,7 +56,7 @@ struct DevStatus {
   unsigned long long dash_count;
   unsigned long long tile_counter;
   unsigned long long dash_tile_counter;
-  unsigned long long reserved[1];
+  unsigned long long scan_ticket;   // block order of the one-pass link scan
 };
 
 // ---------------------------------------------------------------------------

@@ -93,6 +93,8 @@ struct CountArgs {
   double2* seg_ang;
   uint8_t* seg_ok;
   DevStatus* st;
+  unsigned long long* scan_desc;   // look-back words of the one-pass link scan, cleared here
+  int64_t scan_nb;
 };
 
 __device__ __forceinline__ void set_flag(DevStatus* st, unsigned f) { atomicOr(&st->flags, f); }
@@ -122,11 +124,21 @@ __device__ inline bool seg_usable(const ps_batch& B, int i, DevStatus* st, bool 
 
 #pragma clang fp contract(off)
 
+// Intervals split at their middle angle (at most two per segment): the
+// interval index, the angle and the parameter range of the solve that gives
+// the split's parameter.  The solve runs after the record is stored (nothing
+// else depends on it), so its registers are never live beside the record's.
+struct SplitSolves {
+  int n = 0, idx0 = 0, idx1 = 0;
+  double psi0 = 0, psi1 = 0, lo0 = 0, lo1 = 0, hi0 = 0, hi1 = 0;
+};
+
 // Intervals of one usable segment, written into rec, from its start and end
 // tangent angles.  Returns the step count N (the segment has N+1 ribs), or -1
-// if it needs more than kMaxIv intervals.
+// if it needs more than kMaxIv intervals.  The parameters of split intervals
+// are left to finish_splits.
 __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_start, double psi_end,
-                             LinkRec& rec, DevStatus* st) {
+                             LinkRec& rec, SplitSolves& sp, DevStatus* st) {
   const Seg s = load_seg(B, i);
   float X[4], Y[4];
   const int64_t S = B.n_segs;
@@ -233,14 +245,13 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
     if (sigma != 0 && d != 0 && sgn_d(d) != sigma && fabs(d) > kUnwrapGuard) d += kTwoPi * sigma;
     if (fabs(d) >= kPi) {
       if (n + 2 > kMaxIv) { set_flag(st, PS_STATUS_INTERVALS); rec.n_iv = 0; return -1; }
-      // split at the middle angle; its parameter from the FP64 solve
+      // split at the middle angle
       const double psi_s = psi_run + 0.5 * d;
-      const Hodo<double> h = hodo_of<double>(s.kind, X, Y, s.w);
-      double sn, cs;
-      sincos(psi_s, &sn, &cs);
-      const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, pr[k - 1], pr[k]);
+      if (sp.n == 0) { sp.idx0 = n; sp.psi0 = psi_s; sp.lo0 = pr[k - 1]; sp.hi0 = pr[k]; }
+      else { sp.idx1 = n; sp.psi1 = psi_s; sp.lo1 = pr[k - 1]; sp.hi1 = pr[k]; }
+      ++sp.n;
       const int half = steps_of(fabs(0.5 * d), q);
-      N += half; put_at(rec.dsum, n, N); put_at(rec.p, n, so.t); put_at(rec.psi, n + 1, psi_s); ++n;
+      N += half; put_at(rec.dsum, n, N); put_at(rec.psi, n + 1, psi_s); ++n;
       N += half; put_at(rec.dsum, n, N); if (k < M) put_at(rec.p, n, pr[k]);
       psi_run = psi_s + 0.5 * d; put_at(rec.psi, n + 1, psi_run); ++n;
     } else {
@@ -251,6 +262,26 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
   }
   rec.n_iv = (uint8_t)n;
   return N;
+}
+
+// The parameter of each split interval of segment i: the FP64 solve at its
+// middle angle, stored into the record already written at *out.
+__device__ void finish_splits(const ps_batch& B, int i, const SplitSolves& sp, LinkRec* out) {
+  const Seg s = load_seg(B, i);
+  float X[4], Y[4];
+  const int64_t S = B.n_segs;
+  for (int k = 0; k < 4; ++k) {
+    const int kk = k < s.npts ? k : s.npts - 1;
+    X[k] = B.cx[kk * S + i];
+    Y[k] = B.cy[kk * S + i];
+  }
+  const Hodo<double> h = hodo_of<double>(s.kind, X, Y, s.w);
+  for (int m = 0; m < sp.n; ++m) {
+    double sn, cs;
+    sincos(m ? sp.psi1 : sp.psi0, &sn, &cs);
+    const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, m ? sp.lo1 : sp.lo0, m ? sp.hi1 : sp.hi0);
+    out->p[m ? sp.idx1 : sp.idx0] = so.t;
+  }
 }
 
 __device__ int join_steps(int style, double delta, double q) {
@@ -272,22 +303,31 @@ __device__ int cap_steps(int style, double q) {
   return 0;
 }
 
-// First count pass, one thread per segment: whether it is usable and its
-// start and end tangent angles (Eq. Psi at t = 0 and 1, through the end
-// gradients and their fallbacks).  Reports bad or non-finite segments.
-__global__ void __launch_bounds__(256) count_angles_kernel(CountArgs A) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.B.n_segs) return;
-  const bool ok = seg_usable(A.B, (int)i, A.st, true);
-  double2 ang = make_double2(0.0, 0.0);
+// Whether segment k is usable, and its start and end tangent angles (Eq.
+// Psi at t = 0 and 1, through the end gradients and their fallbacks);
+// `report` flags bad or non-finite values (each segment reports once).
+__device__ inline void seg_angles(const ps_batch& B, int k, DevStatus* st, bool report, bool& ok,
+                                  double2& ang) {
+  ok = seg_usable(B, k, st, report);
+  ang = make_double2(0.0, 0.0);
   if (ok) {
-    const Seg s = load_seg(A.B, (int)i);
+    const Seg s = load_seg(B, k);
     double sx, sy, ex, ey;
     start_dir(s, sx, sy);
     end_dir(s, ex, ey);
     ang.x = unit_angle(sx, sy);
     ang.y = unit_angle(ex, ey);
   }
+}
+
+// First count pass, one thread per segment: whether it is usable and its
+// start and end tangent angles.  Reports bad or non-finite segments.
+__global__ void __launch_bounds__(256) count_angles_kernel(CountArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.B.n_segs) return;
+  bool ok;
+  double2 ang;
+  seg_angles(A.B, (int)i, A.st, true, ok, ang);
   A.seg_ang[i] = ang;
   A.seg_ok[i] = ok ? 1 : 0;
 }
@@ -303,7 +343,8 @@ __device__ inline void clear_rec(LinkRec& r) {
 }
 
 // A pivot link (join or cap) with J steps from psi0 through psi0 + delta;
-// `cap` is the cap style of a cap and the join style of a join.
+// `cap` is the cap style of a cap and the join style of a join.  Records are
+// built in registers and stored whole (nine 16-byte stores).
 __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slot, uint8_t role,
                                    double psi0, double delta, int J, float px, float py,
                                    uint8_t cap, float half_w, bool first) {
@@ -326,12 +367,21 @@ __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slo
   link_ribs[slot] = J > 0 ? J + 1 : 0;
 }
 
+// Second count pass, one thread per segment and then one per path.  A
+// segment's thread writes its record and step count (Eqs. p-value, Psi,
+// continuous-delta, Delta_i) and the join or end cap after it; a path's
+// thread writes its start cap.  Link slots: path p's start cap at 2 b + p,
+// segment i at 2 i + p + 1, the link after it at 2 i + p + 2 (b: the path's
+// first segment).
 __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
   const ps_batch& B = A.B;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int S = B.n_segs, P = B.n_paths;
+  if (tid < A.scan_nb) A.scan_desc[tid] = 0ull;   // scan_nb <= S + P threads
   if (tid < S) {
     const int i = (int)tid;
+    const bool ok_i = A.seg_ok[i];
+    const double2 ang = A.seg_ang[i];
     const int p = path_of_seg(B.seg_begin, P, i);
     const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
     const int64_t slot = 2 * (int64_t)i + p + 1;
@@ -341,17 +391,17 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     const bool closed = B.closed && B.closed[p];
     if (!isfinite(wd)) set_flag(A.st, PS_STATUS_NONFINITE);
     else if (!wok || !sok) set_flag(A.st, PS_STATUS_BAD_VALUE);
-    const bool usable = wok && sok && A.seg_ok[i];   // segment problems: reported by the angles pass
+    const bool usable = wok && sok && ok_i;
     const float half_w = 0.5f * wd;
     LinkRec r;
     clear_rec(r);
     r.kind = B.kind[i];
     r.r = half_w;
     int ribs = 0;
-    const double2 ang = A.seg_ang[i];
     const double psi_e = ang.y;
+    SplitSolves sp;
     if (usable) {
-      const int N = segment_setup(B, i, A.q, ang.x, ang.y, r, A.st);
+      const int N = segment_setup(B, i, A.q, ang.x, ang.y, r, sp, A.st);
       if (N > 0) {
         ribs = N + 1;
         r.role = ROLE_SEG;
@@ -372,6 +422,7 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     }
     A.rec[slot] = r;
     A.link_ribs[slot] = ribs;
+    if (sp.n > 0 && ribs > 0) finish_splits(B, i, sp, A.rec + slot);
     // the join after this segment, or the end cap
     const int64_t jslot = slot + 1;
     if (!usable) {
@@ -435,7 +486,7 @@ __global__ void copy_status_flags_kernel(const DevStatus* st, uint32_t* out) {
 __global__ void reset_status_kernel(DevStatus* st) {
   if (threadIdx.x == 0) {
     st->flags = 0; st->total_ribs = 0; st->fixups = 0; st->dash_ribs = 0; st->dash_count = 0;
-    st->tile_counter = 0; st->dash_tile_counter = 0;
+    st->tile_counter = 0; st->dash_tile_counter = 0; st->scan_ticket = 0;
   }
 }
 
@@ -549,6 +600,149 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const TIn* in,
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + k;
     if (i < n) out[i] = ex;
+    ex += v[k];
+  }
+}
+
+// Look-back words are published with a device-scope atomic swap and read
+// with device-scope relaxed atomic loads.  At device scope both reach the
+// point where the XCDs' L2 caches are coherent, so a word published on one
+// XCD is seen on every other one without whole-cache write-backs or
+// invalidations (which release/acquire ordering would add per tile); the
+// data the words describe needs no ordering with them.
+__device__ __forceinline__ void desc_publish(unsigned long long* p, unsigned long long w) {
+  (void)__hip_atomic_exchange(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long desc_read(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The sum of the values of look-back words before word `first` (exclusive of
+// it) up to the nearest inclusive one, read by one wavefront 64 words at a
+// time.  Word: 2 state bits (0 not ready, 1 the unit's own sum, 2 the sum of
+// everything up to and including the unit) and 62 value bits.  Without
+// `block`, gives up (returns false) when a needed word is not ready.
+__device__ __forceinline__ bool look_back(const unsigned long long* desc, int64_t first, bool block,
+                                          unsigned long long& prefix) {
+  const int lane = threadIdx.x & 63;
+  int64_t bT = first - 1;
+  prefix = 0;
+  for (;;) {
+    const int64_t Ti = bT - lane;
+    const unsigned long long wd = Ti >= 0 ? desc_read(&desc[Ti]) : (2ull << 62);
+    const unsigned stt = (unsigned)(wd >> 62);
+    const unsigned long long incl = __ballot(stt == 2);
+    const int stop = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive word
+    const unsigned long long upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
+    if (__ballot(stt == 0) & upto) {
+      if (!block) return false;
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    unsigned long long v = lane <= stop ? (wd & kValMask) : 0ull;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    prefix += v;
+    if (stop < 64) return true;
+    bT -= 64;
+  }
+}
+
+// The link-rib scan in one pass: blocks of kScanTile links take tickets in
+// order, publish their sums and look back for their prefixes, so each link's
+// offset is written once with no second pass.  With TS > 0 it also writes
+// the tile table of an emit of TS-rib tiles (the tile_link entries and
+// cleared look-back words that emit_prepare_kernel writes): each link writes
+// the tiles whose first-read rib it holds, so the table needs no total.  The
+// thread that owns position n_links writes offset[n_links] = R, the rib
+// total, and the emit's overflow flag.  The look-back words (one per block)
+// and the ticket are cleared by the count kernel and the status reset.
+struct LinkScanArgs {
+  const int32_t* link_ribs;
+  int64_t n;
+  int64_t* off;
+  unsigned long long* desc;
+  DevStatus* st;
+  int TS;
+  int32_t* tile_link;
+  unsigned long long* tile_desc;
+  int64_t capacity, max_tiles;
+};
+
+__global__ void __launch_bounds__(kScanThreads) link_scan_kernel(LinkScanArgs A) {
+  __shared__ unsigned int blk_sh;
+  __shared__ long long wsum[kScanThreads / 64];
+  __shared__ long long pre_sh;
+  if (threadIdx.x == 0) blk_sh = (unsigned)atomicAdd(&A.st->scan_ticket, 1ull);
+  __syncthreads();
+  const int64_t blk = blk_sh;
+  const int64_t n = A.n;
+  const int64_t i0 = blk * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  long long s = 0;
+  if (i0 + kScanItems <= n && ((uintptr_t)A.link_ribs & 15) == 0) {
+    const int4* src = reinterpret_cast<const int4*>(A.link_ribs + i0);
+#pragma unroll
+    for (int c = 0; c < kScanItems / 4; ++c) {
+      const int4 q = src[c];
+      v[4 * c] = q.x; v[4 * c + 1] = q.y; v[4 * c + 2] = q.z; v[4 * c + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = i0 + k < n ? A.link_ribs[i0 + k] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) s += v[k];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long incl = wave_incl_scan(s);
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  long long before = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    before += k < wv ? wsum[k] : 0;
+    total += wsum[k];
+  }
+  if (wv == 0) {
+    unsigned long long prefix = 0;
+    if (blk > 0) {
+      if (lane == 0) desc_publish(&A.desc[blk], (1ull << 62) | ((unsigned long long)total & kValMask));
+      look_back(A.desc, blk, true, prefix);
+    }
+    if (lane == 0) {
+      desc_publish(&A.desc[blk], (2ull << 62) | ((prefix + (unsigned long long)total) & kValMask));
+      pre_sh = (long long)prefix;
+    }
+  }
+  __syncthreads();
+  long long ex = pre_sh + before + incl - s;
+  const int TS = A.TS;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = i0 + k;
+    if (i < n) {
+      A.off[i] = ex;
+      if (TS > 0 && v[k] > 0) {
+        // tiles T with T*TS in [a + 1, b], and tile 0 for the link holding rib 0
+        const int64_t a = ex, b = ex + v[k];
+        const int64_t t0 = (a == 0) ? 0 : (a + TS) / TS;
+        const int64_t t1 = b / TS < A.max_tiles ? b / TS : A.max_tiles;
+        for (int64_t T = t0; T <= t1; ++T) {
+          A.tile_link[T] = (int32_t)i;
+          if (T < A.max_tiles) A.tile_desc[T] = 0ull;
+        }
+      }
+    } else if (i == n) {
+      A.off[n] = ex;
+      A.st->total_ribs = (unsigned long long)ex;
+      if (TS > 0) {
+        const int64_t n_tiles = (ex + TS - 1) / TS;
+        if (ex == 0) A.tile_link[0] = 0;
+        A.st->tile_counter = 0;
+        atomicAnd(&A.st->flags, ~(unsigned)PS_STATUS_OVERFLOW);
+        if (2 * ex > A.capacity || n_tiles > A.max_tiles) atomicOr(&A.st->flags, (unsigned)PS_STATUS_OVERFLOW);
+      }
+    }
     ex += v[k];
   }
 }
@@ -877,19 +1071,6 @@ __device__ __forceinline__ void piv_rib(const LinkRec& rp, int j, double miter_l
   }
 }
 
-// Look-back words are published with a device-scope atomic swap and read
-// with device-scope relaxed atomic loads.  At device scope both reach the
-// point where the XCDs' L2 caches are coherent, so a word published on one
-// XCD is seen on every other one without whole-cache write-backs or
-// invalidations (which release/acquire ordering would add per tile); the
-// vertex data needs no ordering with the words.
-__device__ __forceinline__ void desc_publish(unsigned long long* p, unsigned long long w) {
-  (void)__hip_atomic_exchange(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long desc_read(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // round(x) to int64 for 0 <= x < 2^63 (ties to even, as llrint), with no
 // branch: the rounded value split at 2^32 (both parts exact in FP64) and each
 // half converted on its own.
@@ -1038,26 +1219,7 @@ __device__ __forceinline__ bool finish_tile(const EmitArgs& A, const TileState& 
   const int lane = threadIdx.x & 63;
   unsigned long long prefix = 0;
   if (T.any_need) {
-    int64_t bT = T.tile - 1;
-    for (;;) {
-      const int64_t Ti = bT - lane;
-      const unsigned long long wd = Ti >= 0 ? desc_read(&A.desc[Ti]) : (2ull << 62);
-      const unsigned stt = (unsigned)(wd >> 62);
-      const unsigned long long incl = __ballot(stt == 2);
-      const int stop = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive word
-      const unsigned long long upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
-      if (__ballot(stt == 0) & upto) {
-        if (!block) return false;
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      unsigned long long v = lane <= stop ? (wd & kValMask) : 0ull;
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-      prefix += v;
-      if (stop < 64) break;
-      bT -= 64;
-    }
+    if (!look_back(A.desc, T.tile, block, prefix)) return false;
     if (lane == 0 && !T.seen_start)
       desc_publish(&A.desc[T.tile], (2ull << 62) | ((prefix + T.agg) & kValMask));
   }
@@ -1139,7 +1301,10 @@ emit_split_kernel(EmitArgs A) {
         if (lane <= kWin) w.off[lane] = o_i;
         const long long o_n = __shfl(o_i, lane + 1 < 64 ? lane + 1 : 63, 64);
         {
-          const int n_rec = (int)(L - base < kWin ? L - base : kWin);
+          // only the slots that start before the tile's end (a prefix: the
+          // offsets do not decrease) have ribs in it; the others keep stale
+          // records, which nothing reads
+          const int n_rec = __popcll(__ballot(lane < kWin && idx < L && o_i < r1));
           const int4* src = reinterpret_cast<const int4*>(A.rec + base);
           int4* dst = reinterpret_cast<int4*>(w.rec);
           for (int c = lane; c < n_rec * (int)(sizeof(LinkRec) / 16); c += 64) dst[c] = src[c];
@@ -2278,6 +2443,24 @@ int num_cus() {
   return cus;
 }
 
+// blocks of the one-pass link scan: one per kScanTile links, plus the one
+// that owns position n_links
+int64_t link_scan_blocks(int64_t n_links) { return n_links / kScanTile + 1; }
+
+// The one-pass link scan of a count -> scan -> emit chain (after the count
+// kernel, which clears its look-back words), with the tile table of the
+// emit of configuration c when c.K > 0.
+int do_link_scan(const int32_t* link_ribs, int64_t L, int64_t* off, const WsView& v, const WsLayout& w,
+                 int64_t cap, int K, hipStream_t s) {
+  LinkScanArgs a;
+  a.link_ribs = link_ribs; a.n = L; a.off = off; a.desc = (unsigned long long*)v.scan; a.st = v.st;
+  a.TS = 64 * K; a.tile_link = v.tile_link; a.tile_desc = v.desc; a.capacity = cap;
+  a.max_tiles = w.max_tiles;
+  hipLaunchKernelGGL(link_scan_kernel, dim3((unsigned)link_scan_blocks(L)), dim3(kScanThreads), 0, s, a);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
 int do_scan_i32(const int32_t* in, int64_t n_max, const int64_t* n_dev, int64_t* out,
                 long long* scratch, unsigned long long* total, hipStream_t s) {
   const int64_t nb = std::max<int64_t>(1, (n_max + kScanTile - 1) / kScanTile);
@@ -2365,26 +2548,31 @@ int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, cons
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, v.st);
   const int64_t n = (int64_t)b->n_segs + b->n_paths;
   if (n > 0) {
-    CountArgs a{*b, p->q, link_ribs, v.rec, v.seg_ang, v.seg_ok, v.st};
+    CountArgs a{*b, p->q, link_ribs, v.rec, v.seg_ang, v.seg_ok, v.st, (unsigned long long*)v.scan,
+                link_scan_blocks(n_links_of(b))};
     if (b->n_segs > 0)
-      hipLaunchKernelGGL(count_angles_kernel, dim3(grid_for(b->n_segs, 256)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(count_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(count_angles_kernel, dim3((unsigned)((b->n_segs + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   }
   PS_HIP(hipGetLastError());
   return PS_OK;
 }
 
+// `prepared`: the tile table of configuration c is already written (by the
+// one-pass link scan of the same chain).
 int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float* vx, float* vy,
                 float* vs, int64_t cap, const WsView& v, const WsLayout& w, const EmitConfig& c,
-                hipStream_t s) {
+                hipStream_t s, bool prepared = false) {
   const int64_t L = n_links_of(b);
   const int TS = 64 * c.K;
   EmitLaunch fn = pick_emit(c.map, p->precision, c.K, vx != nullptr, vs != nullptr);
   if (!fn) return fail(PS_E_ARG, "unsupported emit configuration K=%d", c.K);
   if (c.waves < 1 || c.waves > 4) return fail(PS_E_ARG, "waves_per_group must be in [1,4]");
-  const unsigned prep_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (L + 255) / 256), 8192);
-  hipLaunchKernelGGL(emit_prepare_kernel, dim3(prep_grid), dim3(256), 0, s, off, L, TS, v.tile_link,
-                     v.desc, v.st, cap, w.max_tiles);
+  if (!prepared) {
+    const unsigned prep_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (L + 255) / 256), 8192);
+    hipLaunchKernelGGL(emit_prepare_kernel, dim3(prep_grid), dim3(256), 0, s, off, L, TS, v.tile_link,
+                       v.desc, v.st, cap, w.max_tiles);
+  }
   EmitArgs a;
   a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
@@ -2483,15 +2671,13 @@ int enqueue_count(ps_plan* P, hipStream_t s) {
   const WsView v = ws_view(P->ws, P->w);
   int rc;
   if ((rc = launch_count(&P->b, &P->p, P->link_ribs, v, s))) return rc;
-  if ((rc = do_scan_i32(P->link_ribs, n_links_of(&P->b), nullptr, P->off, v.scan, &v.st->total_ribs, s)))
-    return rc;
-  return PS_OK;
+  return do_link_scan(P->link_ribs, n_links_of(&P->b), P->off, v, P->w, P->cap, P->cfg.K, s);
 }
 
 int enqueue_emit(ps_plan* P, hipStream_t s) {
   const WsView v = ws_view(P->ws, P->w);
   int rc;
-  if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->cfg, s)))
+  if ((rc = launch_emit(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->cap, v, P->w, P->cfg, s, true)))
     return rc;
   if (P->p.n_dash > 0) {
     if ((rc = launch_dash(&P->b, &P->p, P->off, P->vx, P->vy, P->vs, P->dx, P->dy, P->ds, P->range,
@@ -2720,9 +2906,10 @@ int ps_stroke_static(const ps_batch* b, const ps_params* p, int32_t* link_ribs, 
   if ((rc = static_scratch(&base))) return rc;
   const hipStream_t s = (hipStream_t)stream;
   const WsView v = ws_view(base, w);
+  const EmitConfig c = config_of(p);
   if ((rc = launch_count(b, p, link_ribs, v, s))) return rc;
-  if ((rc = do_scan_i32(link_ribs, n_links_of(b), nullptr, offsets, v.scan, &v.st->total_ribs, s))) return rc;
-  if ((rc = launch_emit(b, p, offsets, vx, vy, vs, cap, v, w, config_of(p), s))) return rc;
+  if ((rc = do_link_scan(link_ribs, n_links_of(b), offsets, v, w, cap, c.K, s))) return rc;
+  if ((rc = launch_emit(b, p, offsets, vx, vy, vs, cap, v, w, c, s, true))) return rc;
   if (status_flags) hipLaunchKernelGGL(copy_status_flags_kernel, dim3(1), dim3(64), 0, s, v.st, status_flags);
   PS_HIP(hipGetLastError());
   return PS_OK;
@@ -2771,7 +2958,7 @@ int ps_plan_create(const ps_batch* b, const ps_params* p, int32_t* link_ribs, in
   P->cfg = config_of(p);
   const WsView v = ws_view(ws, w);
   if ((rc = launch_count(b, &P->p, link_ribs, v, s)) ||
-      (rc = do_scan_i32(link_ribs, n_links_of(b), nullptr, offsets, v.scan, &v.st->total_ribs, s))) {
+      (rc = do_link_scan(link_ribs, n_links_of(b), offsets, v, w, cap, 0, s))) {
     delete P;
     return rc;
   }
