@@ -295,32 +295,85 @@ def _time_plan(torch, plan, steps, warmup):
     return 1e3 * (time.perf_counter() - t) / steps
 
 
+def matching_ribs(lr_a, off_a, lr_b, off_b):
+    """Rib indices (into a and into b) of the links whose rib counts agree, in
+    link order; and the mask of links that agree."""
+    same = lr_a == lr_b
+    n = lr_a[same].astype(np.int64)
+    first_a = off_a[:-1][same]
+    first_b = off_b[:-1][same]
+    rep = np.repeat(np.arange(n.size), n)
+    within = np.arange(int(n.sum()), dtype=np.int64) - np.repeat(np.cumsum(n) - n, n)
+    return first_a[rep] + within, first_b[rep] + within, same
+
+
 def study_precision(args, torch, ps, W, dev):
-    """Near-degenerate shapes: FP32 only and FP32 + FP64 polish against the FP64
-    path (which the GPU parity tests hold to the oracle): count mismatches, worst
-    vertex and arc-length differences, ribs re-solved in FP64."""
+    """The three precision modes against the FP64 oracle on the full
+    near-degenerate configuration (C4): link count mismatches; on the links
+    whose counts agree, the largest vertex distance; on the paths whose links
+    all agree, the largest arc-length difference; ribs re-solved in FP64.  Then
+    each mode's step and emit time on the benchmark batch (C2)."""
+    import oracle
     b = W.config4()
     db = ps.DeviceBatch(b, device=dev)
-    ref = ps.stroke(db, b.q, precision=ps.PS_PREC_FP64)
-    R64 = ref["total_ribs"]
-    rx, ry = ref["vx"][:2 * R64].cpu().numpy(), ref["vy"][:2 * R64].cpu().numpy()
-    rs = ref["vs"][:2 * R64].cpu().numpy()[0::2]
-    rl = ref["link_ribs"].cpu().numpy()
+    threads = len(os.sched_getaffinity(0))
+    ref = oracle.stroke(b, nthreads=threads)
+    lr_o, off_o = ref["link_ribs"], ref["offsets"]
+    P = b.n_paths
+    path_of_link = np.repeat(np.arange(P), 2 * np.diff(b.seg_begin.astype(np.int64)) + 1)
     rows = {}
-    for name, prec in (("fp32", ps.PS_PREC_FP32), ("fp32_fixup", ps.PS_PREC_FP32_FIXUP)):
+    modes = (("fp64", ps.PS_PREC_FP64), ("fp32_fixup", ps.PS_PREC_FP32_FIXUP), ("fp32", ps.PS_PREC_FP32))
+    for name, prec in modes:
         out = ps.stroke(db, b.q, precision=prec)
-        R = out["total_ribs"]
-        mism = int(np.sum(out["link_ribs"].cpu().numpy() != rl))
-        row = {"count_mismatches": mism, "total_ribs": R, "fixups": int(out["status"].fixups)}
-        if R == R64:
-            verr = np.hypot(out["vx"][:2 * R].cpu().numpy() - rx, out["vy"][:2 * R].cpu().numpy() - ry)
-            serr = np.abs(out["vs"][:2 * R].cpu().numpy()[0::2] - rs)
-            row.update(max_vertex_diff_px=float(verr.max()), p999_vertex_diff_px=float(np.quantile(verr, 0.999)),
-                       max_arclen_diff_px=float(serr.max()))
-        rows[name] = row
-        log(f"{name}: {row}")
-    print(json.dumps({"study": "precision", "workload": b.name, "segments": b.n_segs, "ribs": R64,
-                      "reference": "the FP64 path", "meta": b.meta, "modes": rows}), flush=True)
+        lr = out["link_ribs"].cpu().numpy()
+        off = out["offsets"].cpu().numpy()
+        ia, ib, same = matching_ribs(lr, off, lr_o, off_o)
+        vx, vy, vs = (out[k].cpu().numpy() for k in ("vx", "vy", "vs"))
+        # vertex 2r and 2r+1 belong to rib r
+        va = np.concatenate([2 * ia, 2 * ia + 1]); vb = np.concatenate([2 * ib, 2 * ib + 1])
+        verr = np.hypot(vx[va] - ref["vx"][vb], vy[va] - ref["vy"][vb])
+        bad_path = np.zeros(P, bool)
+        bad_path[path_of_link[~same]] = True
+        rib_path_a = np.repeat(path_of_link, lr.astype(np.int64))
+        ok = ~bad_path[rib_path_a[ia]]
+        serr = np.abs(vs[2 * ia[ok]] - ref["vs"][ib[ok]])
+        rows[name] = {"count_mismatches": int((~same).sum()), "links": int(same.size),
+                      "paths_with_a_mismatch": int(bad_path.sum()),
+                      "max_vertex_err_px": float(verr.max()) if verr.size else 0.0,
+                      "p999_vertex_err_px": float(np.quantile(verr, 0.999)) if verr.size else 0.0,
+                      "max_arclen_err_px": float(serr.max()) if serr.size else 0.0,
+                      "fixup_ribs": int(out["status"].fixups), "ribs": int(out["total_ribs"])}
+        log(f"C4 {name}: {rows[name]}")
+        del out
+    del db
+    # speed of each mode on the benchmark batch
+    b2 = W.config2_fast()
+    db2 = ps.DeviceBatch(b2, device=dev)
+    stream = torch.cuda.current_stream()
+    for name, prec in modes:
+        first = ps.stroke(db2, b2.q, precision=prec)
+        R = first["total_ribs"]
+        del first
+        plan = ps.Plan(db2, b2.q, vertex_capacity=2 * R, precision=prec, emit=(ps.PS_MAP_TILES, 7, 4))
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for a, c in ev:
+            a.record(stream); c.record(stream)
+        for _ in range(args.warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a, c in ev:
+            plan.launch_timed(a, c)
+        torch.cuda.synchronize()
+        rows[name]["c2_ms_per_step"] = 1e3 * (time.perf_counter() - t) / args.steps
+        rows[name]["c2_emit_ms"] = sum(a.elapsed_time(c) for a, c in ev) / args.steps
+        rows[name]["c2_ribs"] = R
+        plan.close()
+        log(f"C2 {name}: step {rows[name]['c2_ms_per_step']:.3f} ms, emit {rows[name]['c2_emit_ms']:.3f} ms")
+    print(json.dumps({"study": "precision", "workload": b.name, "segments": b.n_segs,
+                      "reference": "the FP64 oracle", "meta": b.meta,
+                      "timing": "C2 batch, tiles mapping K=7, 4 waves per group", "modes": rows}), flush=True)
     return 0
 
 

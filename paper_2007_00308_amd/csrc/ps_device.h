@@ -62,30 +62,35 @@ struct DevStatus {
 // ---------------------------------------------------------------------------
 // Segments in FP64 (inputs are FP32 and taken as exact)
 // ---------------------------------------------------------------------------
-struct Seg {
+template <typename F>
+struct SegT {
   int kind;
   int npts;
-  double x[4], y[4];
-  double w;
+  F x[4], y[4];
+  F w;
 };
+using Seg = SegT<double>;
 
 __device__ __forceinline__ int npts_of(int kind) {
   return kind == PS_KIND_CUBIC ? 4 : (kind == PS_KIND_LINE ? 2 : 3);
 }
 
-__device__ inline Seg load_seg(const ps_batch& B, int i) {
-  Seg s;
+// Segment i in the arithmetic F of the setup (the FP32 inputs convert exactly
+// to either).
+template <typename F = double>
+__device__ inline SegT<F> load_seg(const ps_batch& B, int i) {
+  SegT<F> s;
   s.kind = B.kind[i];
   s.npts = npts_of(s.kind);
   const int64_t S = B.n_segs;
   // points past the last one repeat it (constant indices only)
-  s.x[0] = (double)B.cx[i];         s.y[0] = (double)B.cy[i];
-  s.x[1] = (double)B.cx[S + i];     s.y[1] = (double)B.cy[S + i];
-  s.x[2] = s.npts > 2 ? (double)B.cx[2 * S + i] : s.x[1];
-  s.y[2] = s.npts > 2 ? (double)B.cy[2 * S + i] : s.y[1];
-  s.x[3] = s.npts > 3 ? (double)B.cx[3 * S + i] : s.x[2];
-  s.y[3] = s.npts > 3 ? (double)B.cy[3 * S + i] : s.y[2];
-  s.w = (s.kind == PS_KIND_CONIC) ? (double)B.conic_w[i] : 1.0;
+  s.x[0] = (F)B.cx[i];         s.y[0] = (F)B.cy[i];
+  s.x[1] = (F)B.cx[S + i];     s.y[1] = (F)B.cy[S + i];
+  s.x[2] = s.npts > 2 ? (F)B.cx[2 * S + i] : s.x[1];
+  s.y[2] = s.npts > 2 ? (F)B.cy[2 * S + i] : s.y[1];
+  s.x[3] = s.npts > 3 ? (F)B.cx[3 * S + i] : s.x[2];
+  s.y[3] = s.npts > 3 ? (F)B.cy[3 * S + i] : s.y[2];
+  s.w = (s.kind == PS_KIND_CONIC) ? (F)B.conic_w[i] : (F)1;
   return s;
 }
 
@@ -106,21 +111,26 @@ __device__ __forceinline__ bool seg_finite(const Seg& s) {
   return ok;
 }
 
-__device__ __forceinline__ double sgn_d(double v) { return (double)((v > 0) - (v < 0)); }
+template <typename F>
+__device__ __forceinline__ F sgn(F v) { return (F)((v > 0) - (v < 0)); }
+__device__ __forceinline__ double sgn_d(double v) { return sgn(v); }
 
 // ===========================================================================
-// Setup arithmetic (count kernel).  FMA contraction is off so the step counts
-// come out of plain IEEE operations.
+// Setup arithmetic (count kernel), in FP64 (F = double) or, for the
+// single-precision study mode, in FP32.  FMA contraction is off so the step
+// counts come out of plain IEEE operations.
 // ===========================================================================
 #pragma clang fp contract(off)
 
-__device__ __forceinline__ double crs(double ax, double ay, double bx, double by) {
+template <typename F>
+__device__ __forceinline__ F crs(F ax, F ay, F bx, F by) {
   return ax * by - ay * bx;
 }
 
 // Start / end gradient directions (unnormalised) by the fallbacks of the table
 // of segment forms: difference successive control points until nonzero.
-__device__ inline void start_dir(const Seg& s, double& dx, double& dy) {
+template <typename F>
+__device__ inline void start_dir(const SegT<F>& s, F& dx, F& dy) {
   dx = s.x[1] - s.x[0]; dy = s.y[1] - s.y[0];
   if (s.kind == PS_KIND_CUBIC) {
     if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
@@ -129,12 +139,13 @@ __device__ inline void start_dir(const Seg& s, double& dx, double& dy) {
     if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
   } else if (s.kind == PS_KIND_CONIC) {
     // g'(0) = 2 w_B (P1 - P0): a negative weight starts backwards
-    if ((dx == 0 && dy == 0) || s.w == 0.0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
-    else if (s.w < 0.0) { dx = -dx; dy = -dy; }
+    if ((dx == 0 && dy == 0) || s.w == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+    else if (s.w < 0) { dx = -dx; dy = -dy; }
   }
 }
 
-__device__ inline void end_dir(const Seg& s, double& dx, double& dy) {
+template <typename F>
+__device__ inline void end_dir(const SegT<F>& s, F& dx, F& dy) {
   if (s.kind == PS_KIND_LINE) { dx = s.x[1] - s.x[0]; dy = s.y[1] - s.y[0]; return; }
   // last point minus the one before it (x[3] repeats the last point)
   const bool cub = s.kind == PS_KIND_CUBIC;
@@ -144,45 +155,49 @@ __device__ inline void end_dir(const Seg& s, double& dx, double& dy) {
     if (dx == 0 && dy == 0) { dx = s.x[3] - s.x[0]; dy = s.y[3] - s.y[0]; }
   } else if (s.kind == PS_KIND_CONIC) {
     // g'(1) = 2 w_B (P2 - P1)
-    if ((dx == 0 && dy == 0) || s.w == 0.0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
-    else if (s.w < 0.0) { dx = -dx; dy = -dy; }
+    if ((dx == 0 && dy == 0) || s.w == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
+    else if (s.w < 0) { dx = -dx; dy = -dy; }
   } else {
     if (dx == 0 && dy == 0) { dx = s.x[2] - s.x[0]; dy = s.y[2] - s.y[0]; }
   }
 }
 
-__device__ __forceinline__ double unit_angle(double dx, double dy) {
+template <typename F>
+__device__ __forceinline__ F unit_angle(F dx, F dy) {
   // the direction of (dx,dy) after normalisation (Eq. Psi uses tan^-1 of the
   // normalised gradient)
-  const double inv = 1.0 / sqrt(dx * dx + dy * dy);
+  const F inv = (F)1 / sqrt(dx * dx + dy * dy);
   return atan2(inv * dy, inv * dx);
 }
 
 // relative angle difference (-)
-__device__ __forceinline__ double adiff(double a, double b) {
-  double d = a - b;
-  if (d > kPi) return d - kTwoPi;
-  if (d < -kPi) return d + kTwoPi;
+template <typename F>
+__device__ __forceinline__ F adiff(F a, F b) {
+  F d = a - b;
+  if (d > (F)kPi) return d - (F)kTwoPi;
+  if (d < -(F)kPi) return d + (F)kTwoPi;
   return d;
 }
 
-__device__ __forceinline__ int steps_of(double abs_turn, double q) {
-  double x = ceil(abs_turn / q - kCountEps);
-  return x < 1.0 ? 1 : (int)x;
+template <typename F>
+__device__ __forceinline__ int steps_of(F abs_turn, F q) {
+  F x = ceil(abs_turn / q - (F)kCountEps);
+  return x < (F)1 ? 1 : (int)x;
 }
 
 // Simple real roots in (0,1) of A t^2 + B1 t + C, sorted, distinct.  A double
 // root is not returned (it is no sign change).
-__device__ inline int simple_roots01(double A, double B1, double C, double r[2]) {
+template <typename F>
+__device__ inline int simple_roots01(F A, F B1, F C, F r[2]) {
   int n = 0;
-  double t0 = 0, t1 = 0;
-  if (A == 0.0) {
-    if (B1 != 0.0) { t0 = -C / B1; n = 1; }
+  F t0 = 0, t1 = 0;
+  if (A == (F)0) {
+    if (B1 != (F)0) { t0 = -C / B1; n = 1; }
   } else {
-    double disc = B1 * B1 - 4 * A * C;
+    F disc = B1 * B1 - 4 * A * C;
     if (disc > 0) {
-      double sq = sqrt(disc);
-      double qq = -0.5 * (B1 + (B1 >= 0 ? sq : -sq));
+      F sq = sqrt(disc);
+      F qq = (F)-0.5 * (B1 + (B1 >= 0 ? sq : -sq));
       t0 = qq / A;
       t1 = C / qq;
       n = 2;
@@ -203,16 +218,17 @@ __device__ inline int simple_roots01(double A, double B1, double C, double r[2])
 
 // a[n] = v for a run-time n, as a chain of selections over constant indices
 // (a dynamically indexed private array would live in scratch memory)
-template <int NMAX, typename T>
-__device__ __forceinline__ void put_at(T (&a)[NMAX], int n, T v) {
+template <int NMAX, typename T, typename V>
+__device__ __forceinline__ void put_at(T (&a)[NMAX], int n, V v) {
 #pragma unroll
   for (int m = 0; m < NMAX; ++m)
-    if (m == n) a[m] = v;
+    if (m == n) a[m] = (T)v;
 }
 
 // Cubic curvature sign: g' x g'' ~ (1-t)^2 X + (1-t) t Y + t^2 Z.
-__device__ __forceinline__ double cubic_curv(double X, double Y, double Z, double t) {
-  double u = 1 - t;
+template <typename F>
+__device__ __forceinline__ F cubic_curv(F X, F Y, F Z, F t) {
+  F u = 1 - t;
   return u * u * X + u * t * Y + t * t * Z;
 }
 

@@ -128,18 +128,21 @@ __device__ inline bool seg_usable(const ps_batch& B, int i, DevStatus* st, bool 
 // interval index, the angle and the parameter range of the solve that gives
 // the split's parameter.  The solve runs after the record is stored (nothing
 // else depends on it), so its registers are never live beside the record's.
+template <typename F>
 struct SplitSolves {
   int n = 0, idx0 = 0, idx1 = 0;
-  double psi0 = 0, psi1 = 0, lo0 = 0, lo1 = 0, hi0 = 0, hi1 = 0;
+  F psi0 = 0, psi1 = 0, lo0 = 0, lo1 = 0, hi0 = 0, hi1 = 0;
 };
 
 // Intervals of one usable segment, written into rec, from its start and end
 // tangent angles.  Returns the step count N (the segment has N+1 ribs), or -1
 // if it needs more than kMaxIv intervals.  The parameters of split intervals
-// are left to finish_splits.
-__device__ int segment_setup(const ps_batch& B, int i, double q, double psi_start, double psi_end,
-                             LinkRec& rec, SplitSolves& sp, DevStatus* st) {
-  const Seg s = load_seg(B, i);
+// are left to finish_splits.  F is the arithmetic: double, or float for the
+// single-precision study mode.
+template <typename F>
+__device__ int segment_setup(const ps_batch& B, int i, F q, F psi_start, F psi_end,
+                             LinkRec& rec, SplitSolves<F>& sp, DevStatus* st) {
+  const SegT<F> s = load_seg<F>(B, i);
   float X[4], Y[4];
   const int64_t S = B.n_segs;
   for (int k = 0; k < 4; ++k) {
@@ -147,14 +150,14 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
     X[k] = B.cx[kk * S + i];
     Y[k] = B.cy[kk * S + i];
   }
-  double sx, sy;
+  F sx, sy;
   start_dir(s, sx, sy);
-  const double psi0 = psi_start;   // unit_angle(sx, sy), computed by the angles kernel
-  const double ax = s.x[1] - s.x[0], ay = s.y[1] - s.y[0];
-  const double bx = s.x[2] - s.x[1], by = s.y[2] - s.y[1];
-  const double cx = s.x[3] - s.x[2], cy = s.y[3] - s.y[2];
+  const F psi0 = psi_start;   // unit_angle(sx, sy), computed by the angles kernel
+  const F ax = s.x[1] - s.x[0], ay = s.y[1] - s.y[0];
+  const F bx = s.x[2] - s.x[1], by = s.y[2] - s.y[1];
+  const F cx = s.x[3] - s.x[2], cy = s.y[3] - s.y[2];
   bool collinear;
-  double X3 = 0, Y3 = 0, Z3 = 0;
+  F X3 = 0, Y3 = 0, Z3 = 0;
   if (s.kind == PS_KIND_LINE) {
     collinear = true;
   } else if (s.kind == PS_KIND_CUBIC) {
@@ -162,40 +165,40 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
     collinear = (X3 == 0 && Y3 == 0 && Z3 == 0);
   } else {
     // a conic of weight 0 is the chord P0 P2
-    collinear = crs(ax, ay, bx, by) == 0 || (s.kind == PS_KIND_CONIC && s.w == 0.0);
+    collinear = crs(ax, ay, bx, by) == 0 || (s.kind == PS_KIND_CONIC && s.w == 0);
   }
 
   // interval n gets dsum[n], its end parameter p[n] and end angle psi[n+1];
   // loops run to their constant maxima so every private array keeps constant
   // indices (and stays in registers)
   int n = 0, N = 0;
-  double psi_run = psi0;
+  F psi_run = psi0;
   rec.psi[0] = psi0;
   if (collinear) {
     // flat pieces of one step, split by +pi pivots at the simple roots of
     // g'(t).d where the segment reverses along its line (a cusp)
-    const double inv = 1.0 / sqrt(sx * sx + sy * sy);
-    const double dx = inv * sx, dy = inv * sy;
-    double A = 0, B1 = 0, C = 0;
+    const F inv = (F)1 / sqrt(sx * sx + sy * sy);
+    const F dx = inv * sx, dy = inv * sy;
+    F A = 0, B1 = 0, C = 0;
     if (s.kind == PS_KIND_CUBIC) {
-      const double al = ax * dx + ay * dy, be = bx * dx + by * dy, ga = cx * dx + cy * dy;
+      const F al = ax * dx + ay * dy, be = bx * dx + by * dy, ga = cx * dx + cy * dy;
       A = al - 2 * be + ga; B1 = 2 * (be - al); C = al;
     } else if (s.kind == PS_KIND_QUAD) {
-      const double al = ax * dx + ay * dy, be = bx * dx + by * dy;
+      const F al = ax * dx + ay * dy, be = bx * dx + by * dy;
       B1 = be - al; C = al;
     } else if (s.kind == PS_KIND_CONIC) {
-      const double al = ax * dx + ay * dy, be = bx * dx + by * dy, w = s.w;
+      const F al = ax * dx + ay * dy, be = bx * dx + by * dy, w = s.w;
       A = w * al - (al + be) + w * be; B1 = (al + be) - 2 * w * al; C = w * al;
     }
-    double f[2] = {0, 0};
+    F f[2] = {0, 0};
     const int nf = (s.kind == PS_KIND_LINE) ? 0 : simple_roots01(A, B1, C, f);
-    const int flat = steps_of(0.0, q), fold = steps_of(kPi, q);
+    const int flat = steps_of((F)0, q), fold = steps_of((F)kPi, q);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (k < nf) {
         N += flat; put_at(rec.dsum, n, N); put_at(rec.p, n, f[k]); put_at(rec.psi, n + 1, psi_run); ++n;
         N += fold; put_at(rec.dsum, n, N); put_at(rec.p, n, f[k]);
-        psi_run = psi_run + kPi; put_at(rec.psi, n + 1, psi_run); ++n;
+        psi_run = psi_run + (F)kPi; put_at(rec.psi, n + 1, psi_run); ++n;
       }
     }
     N += flat; put_at(rec.dsum, n, N); put_at(rec.psi, n + 1, psi_run); ++n;
@@ -205,55 +208,55 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
 
   // reversal parameters: simple roots of the cubic curvature sign;
   // pr[0..M] = 0, the roots, 1 (M <= 3)
-  double pr[4] = {0.0, 1.0, 1.0, 1.0};
+  F pr[4] = {0, 1, 1, 1};
   int M = 1;
   if (s.kind == PS_KIND_CUBIC) {
-    double r[2] = {0, 0};
+    F r[2] = {0, 0};
     const int nr = simple_roots01(X3 - Y3 + Z3, Y3 - 2 * X3, X3, r);
     M = 1 + nr;
-    pr[1] = nr >= 1 ? r[0] : 1.0;
-    pr[2] = nr >= 2 ? r[1] : 1.0;
+    pr[1] = nr >= 1 ? r[0] : (F)1;
+    pr[2] = nr >= 2 ? r[1] : (F)1;
   }
-  double Psi[4];
+  F Psi[4];
   Psi[0] = psi0;
 #pragma unroll
   for (int k = 1; k < 3; ++k) {
-    const double t = pr[k], u = 1 - t;
-    const double gx = u * u * ax + 2 * u * t * bx + t * t * cx;
-    const double gy = u * u * ay + 2 * u * t * by + t * t * cy;
-    Psi[k] = (k < M) ? atan2(gy, gx) : 0.0;
+    const F t = pr[k], u = 1 - t;
+    const F gx = u * u * ax + 2 * u * t * bx + t * t * cx;
+    const F gy = u * u * ay + 2 * u * t * by + t * t * cy;
+    Psi[k] = (k < M) ? atan2(gy, gx) : (F)0;
   }
   put_at(Psi, M, psi_end);
-  const double crsQ = crs(ax, ay, bx, by);
+  const F crsQ = crs(ax, ay, bx, by);
 #pragma unroll
   for (int k = 1; k <= 3; ++k) {
     if (k > M) break;
-    double d = adiff(Psi[k], Psi[k - 1]);   // the short way round
-    double sigma = 0;                       // rotation sense of the interval
+    F d = adiff(Psi[k], Psi[k - 1]);   // the short way round
+    F sigma = 0;                       // rotation sense of the interval
     if (s.kind == PS_KIND_CUBIC) {
       // the middle of the interval, then its quarter points (an exact cusp
       // makes the curvature vanish at a single point)
-      const double w = pr[k] - pr[k - 1];
-      sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.5 * w));
-      if (sigma == 0) sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.25 * w));
-      if (sigma == 0) sigma = sgn_d(cubic_curv(X3, Y3, Z3, pr[k - 1] + 0.75 * w));
+      const F w = pr[k] - pr[k - 1];
+      sigma = sgn(cubic_curv(X3, Y3, Z3, pr[k - 1] + (F)0.5 * w));
+      if (sigma == 0) sigma = sgn(cubic_curv(X3, Y3, Z3, pr[k - 1] + (F)0.25 * w));
+      if (sigma == 0) sigma = sgn(cubic_curv(X3, Y3, Z3, pr[k - 1] + (F)0.75 * w));
     } else {
       // conics: g' x g'' = 4 w_B (a x b) / D^3 with D > 0, so a negative
       // weight (an external ellipse) turns the other way, the long way round
-      sigma = sgn_d(crsQ) * (s.kind == PS_KIND_CONIC ? sgn_d(s.w) : 1.0);
+      sigma = sgn(crsQ) * (s.kind == PS_KIND_CONIC ? sgn(s.w) : (F)1);
     }
-    if (sigma != 0 && d != 0 && sgn_d(d) != sigma && fabs(d) > kUnwrapGuard) d += kTwoPi * sigma;
-    if (fabs(d) >= kPi) {
+    if (sigma != 0 && d != 0 && sgn(d) != sigma && fabs(d) > (F)kUnwrapGuard) d += (F)kTwoPi * sigma;
+    if (fabs(d) >= (F)kPi) {
       if (n + 2 > kMaxIv) { set_flag(st, PS_STATUS_INTERVALS); rec.n_iv = 0; return -1; }
       // split at the middle angle
-      const double psi_s = psi_run + 0.5 * d;
+      const F psi_s = psi_run + (F)0.5 * d;
       if (sp.n == 0) { sp.idx0 = n; sp.psi0 = psi_s; sp.lo0 = pr[k - 1]; sp.hi0 = pr[k]; }
       else { sp.idx1 = n; sp.psi1 = psi_s; sp.lo1 = pr[k - 1]; sp.hi1 = pr[k]; }
       ++sp.n;
-      const int half = steps_of(fabs(0.5 * d), q);
+      const int half = steps_of(fabs((F)0.5 * d), q);
       N += half; put_at(rec.dsum, n, N); put_at(rec.psi, n + 1, psi_s); ++n;
       N += half; put_at(rec.dsum, n, N); if (k < M) put_at(rec.p, n, pr[k]);
-      psi_run = psi_s + 0.5 * d; put_at(rec.psi, n + 1, psi_run); ++n;
+      psi_run = psi_s + (F)0.5 * d; put_at(rec.psi, n + 1, psi_run); ++n;
     } else {
       if (n + 1 > kMaxIv) { set_flag(st, PS_STATUS_INTERVALS); rec.n_iv = 0; return -1; }
       N += steps_of(fabs(d), q); put_at(rec.dsum, n, N); if (k < M) put_at(rec.p, n, pr[k]);
@@ -264,10 +267,11 @@ __device__ int segment_setup(const ps_batch& B, int i, double q, double psi_star
   return N;
 }
 
-// The parameter of each split interval of segment i: the FP64 solve at its
+// The parameter of each split interval of segment i: the solve (in F) at its
 // middle angle, stored into the record already written at *out.
-__device__ void finish_splits(const ps_batch& B, int i, const SplitSolves& sp, LinkRec* out) {
-  const Seg s = load_seg(B, i);
+template <typename F>
+__device__ void finish_splits(const ps_batch& B, int i, const SplitSolves<F>& sp, LinkRec* out) {
+  const SegT<F> s = load_seg<F>(B, i);
   float X[4], Y[4];
   const int64_t S = B.n_segs;
   for (int k = 0; k < 4; ++k) {
@@ -275,59 +279,64 @@ __device__ void finish_splits(const ps_batch& B, int i, const SplitSolves& sp, L
     X[k] = B.cx[kk * S + i];
     Y[k] = B.cy[kk * S + i];
   }
-  const Hodo<double> h = hodo_of<double>(s.kind, X, Y, s.w);
+  const Hodo<F> h = hodo_of<F>(s.kind, X, Y, s.w);
   for (int m = 0; m < sp.n; ++m) {
-    double sn, cs;
-    sincos(m ? sp.psi1 : sp.psi0, &sn, &cs);
-    const SolveOut<double> so = solve_t<double>(h, -sn, cs, cs, sn, m ? sp.lo1 : sp.lo0, m ? sp.hi1 : sp.hi0);
-    out->p[m ? sp.idx1 : sp.idx0] = so.t;
+    F sn, cs;
+    if constexpr (sizeof(F) == 8) sincos(m ? sp.psi1 : sp.psi0, &sn, &cs);
+    else sincosf(m ? sp.psi1 : sp.psi0, &sn, &cs);
+    const SolveOut<F> so = solve_t<F>(h, -sn, cs, cs, sn, m ? sp.lo1 : sp.lo0, m ? sp.hi1 : sp.hi0);
+    out->p[m ? sp.idx1 : sp.idx0] = (double)so.t;
   }
 }
 
-__device__ int join_steps(int style, double delta, double q) {
-  if (delta == 0.0) return 0;
+template <typename F>
+__device__ int join_steps(int style, F delta, F q) {
+  if (delta == 0) return 0;
   if (style == PS_JOIN_BEVEL) return 1;
   if (style == PS_JOIN_TRIANGLE) return 2;
   if (style == PS_JOIN_MITER || style == PS_JOIN_MITER_CLIP) return 3;   // Sec. "Harder Joins"
   if (style == PS_JOIN_ROUND) {
-    const double x = ceil(fabs(delta) / q - kCountEps);
+    const F x = ceil(fabs(delta) / q - (F)kCountEps);
     return x < 0 ? 0 : (int)x;
   }
   return 0;
 }
 
-__device__ int cap_steps(int style, double q) {
+template <typename F>
+__device__ int cap_steps(int style, F q) {
   if (style == PS_CAP_TRIANGLE) return 2;
   if (style == PS_CAP_SQUARE) return 4;
-  if (style == PS_CAP_ROUND) return (int)ceil(kPi / q - kCountEps);
+  if (style == PS_CAP_ROUND) return (int)ceil((F)kPi / q - (F)kCountEps);
   return 0;
 }
 
-// Whether segment k is usable, and its start and end tangent angles (Eq.
-// Psi at t = 0 and 1, through the end gradients and their fallbacks);
-// `report` flags bad or non-finite values (each segment reports once).
+// Whether segment k is usable (decided on the exact inputs), and its start
+// and end tangent angles in F (Eq. Psi at t = 0 and 1, through the end
+// gradients and their fallbacks); `report` flags bad or non-finite values.
+template <typename F>
 __device__ inline void seg_angles(const ps_batch& B, int k, DevStatus* st, bool report, bool& ok,
                                   double2& ang) {
   ok = seg_usable(B, k, st, report);
   ang = make_double2(0.0, 0.0);
   if (ok) {
-    const Seg s = load_seg(B, k);
-    double sx, sy, ex, ey;
+    const SegT<F> s = load_seg<F>(B, k);
+    F sx, sy, ex, ey;
     start_dir(s, sx, sy);
     end_dir(s, ex, ey);
-    ang.x = unit_angle(sx, sy);
-    ang.y = unit_angle(ex, ey);
+    ang.x = (double)unit_angle(sx, sy);
+    ang.y = (double)unit_angle(ex, ey);
   }
 }
 
 // First count pass, one thread per segment: whether it is usable and its
 // start and end tangent angles.  Reports bad or non-finite segments.
+template <typename F>
 __global__ void __launch_bounds__(256) count_angles_kernel(CountArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.B.n_segs) return;
   bool ok;
   double2 ang;
-  seg_angles(A.B, (int)i, A.st, true, ok, ang);
+  seg_angles<F>(A.B, (int)i, A.st, true, ok, ang);
   A.seg_ang[i] = ang;
   A.seg_ok[i] = ok ? 1 : 0;
 }
@@ -342,11 +351,11 @@ __device__ inline void clear_rec(LinkRec& r) {
   for (int k = 0; k <= kMaxIv; ++k) r.psi[k] = 0;
 }
 
-// A pivot link (join or cap) with J steps from psi0 through psi0 + delta;
+// A pivot link (join or cap) with J steps from psi0 through psi1 = psi0 + delta;
 // `cap` is the cap style of a cap and the join style of a join.  Records are
 // built in registers and stored whole (nine 16-byte stores).
 __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slot, uint8_t role,
-                                   double psi0, double delta, int J, float px, float py,
+                                   double psi0, double psi1, int J, float px, float py,
                                    uint8_t cap, float half_w, bool first) {
   LinkRec r;
   clear_rec(r);
@@ -354,13 +363,13 @@ __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slo
   r.n_iv = 1;
   r.flags = (uint8_t)((cap << 4) | ((first && J > 0) ? kFirstInPath : 0));
   r.r = half_w;
-  r.dsum[0] = J; r.psi[0] = psi0; r.psi[1] = psi0 + delta;
+  r.dsum[0] = J; r.psi[0] = psi0; r.psi[1] = psi1;
   r.x[0] = px; r.y[0] = py;
   if (role == ROLE_JOIN && (cap == PS_JOIN_MITER || cap == PS_JOIN_MITER_CLIP)) {
     // unit normals n = (-sin, cos) at both ends, for the miter vertices
     double s0, c0, s1, c1;
     sincos(psi0, &s0, &c0);
-    sincos(psi0 + delta, &s1, &c1);
+    sincos(psi1, &s1, &c1);
     r.p[0] = -s0; r.p[1] = c0; r.p[2] = -s1; r.p[3] = c1;
   }
   rec[slot] = r;
@@ -373,6 +382,7 @@ __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slo
 // thread writes its start cap.  Link slots: path p's start cap at 2 b + p,
 // segment i at 2 i + p + 1, the link after it at 2 i + p + 2 (b: the path's
 // first segment).
+template <typename F>
 __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
   const ps_batch& B = A.B;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,7 +391,7 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
   if (tid < S) {
     const int i = (int)tid;
     const bool ok_i = A.seg_ok[i];
-    const double2 ang = A.seg_ang[i];
+    const double2 ang = A.seg_ang[i];   // F values
     const int p = path_of_seg(B.seg_begin, P, i);
     const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
     const int64_t slot = 2 * (int64_t)i + p + 1;
@@ -398,10 +408,11 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     r.kind = B.kind[i];
     r.r = half_w;
     int ribs = 0;
-    const double psi_e = ang.y;
-    SplitSolves sp;
+    const F q = (F)A.q;
+    const F psi_e = (F)ang.y;
+    SplitSolves<F> sp;
     if (usable) {
-      const int N = segment_setup(B, i, A.q, ang.x, ang.y, r, sp, A.st);
+      const int N = segment_setup<F>(B, i, q, (F)ang.x, psi_e, r, sp, A.st);
       if (N > 0) {
         ribs = N + 1;
         r.role = ROLE_SEG;
@@ -417,12 +428,12 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
         bool first_seg = true;
         for (int k = i - 1; first_seg && k >= b; --k) first_seg = !A.seg_ok[k];
         if (first_seg) r.flags |= kFirstSegInPath;
-        if (first_seg && (closed || cap_steps(B.cap[p], A.q) == 0)) r.flags |= kFirstInPath;
+        if (first_seg && (closed || cap_steps<F>(B.cap[p], q) == 0)) r.flags |= kFirstInPath;
       }
     }
     A.rec[slot] = r;
     A.link_ribs[slot] = ribs;
-    if (sp.n > 0 && ribs > 0) finish_splits(B, i, sp, A.rec + slot);
+    if (sp.n > 0 && ribs > 0) finish_splits<F>(B, i, sp, A.rec + slot);
     // the join after this segment, or the end cap
     const int64_t jslot = slot + 1;
     if (!usable) {
@@ -439,14 +450,14 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     for (int k = b; k <= i && next < 0 && closed; ++k)
       if (A.seg_ok[k]) next = k;
     if (next >= 0) {
-      double d = adiff(A.seg_ang[next].x, psi_e);
-      if (d == -kPi) d = kPi;   // antiparallel: turn +pi
-      const int J = join_steps(B.join[p], d, A.q);
-      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, psi_e, d, J, ex, ey, B.join[p], half_w, false);
+      F d = adiff((F)A.seg_ang[next].x, psi_e);
+      if (d == -(F)kPi) d = (F)kPi;   // antiparallel: turn +pi
+      const int J = join_steps<F>(B.join[p], d, q);
+      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, psi_e, psi_e + d, J, ex, ey, B.join[p], half_w, false);
       return;
     }
-    const int J = cap_steps(B.cap[p], A.q);
-    write_pivot(A.rec, A.link_ribs, jslot, ROLE_ECAP, psi_e, -kPi, J, ex, ey, B.cap[p], half_w, false);
+    const int J = cap_steps<F>(B.cap[p], q);
+    write_pivot(A.rec, A.link_ribs, jslot, ROLE_ECAP, psi_e, psi_e - (F)kPi, J, ex, ey, B.cap[p], half_w, false);
     return;
   }
   if (tid < (int64_t)S + P) {
@@ -459,10 +470,12 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     if (ok && !(B.closed && B.closed[p])) {   // a closed contour has no caps
       for (int k = b; k < e; ++k) {
         if (!A.seg_ok[k]) continue;
-        const double psi_s = A.seg_ang[k].x;
-        const int J = cap_steps(B.cap[p], A.q);
+        const F psi_s = (F)A.seg_ang[k].x;
+        const F q = (F)A.q;
+        const int J = cap_steps<F>(B.cap[p], q);
         // start cap: from the reversed start tangent, +pi round to it
-        write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, psi_s - kPi, kPi, J, B.cx[k], B.cy[k],
+        const F c0 = psi_s - (F)kPi;
+        write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, c0, c0 + (F)kPi, J, B.cx[k], B.cy[k],
                     B.cap[p], 0.5f * wd, true);
         return;
       }
@@ -669,6 +682,15 @@ struct LinkScanArgs {
   int64_t capacity, max_tiles;
 };
 
+// floor(a / d) for 0 <= a < 2^52 and 0 < d < 2^20 from an FP64 estimate and
+// one correction each way (a 64-bit integer division is a long sequence)
+__device__ __forceinline__ int64_t div_small(int64_t a, int64_t d, double inv_d) {
+  int64_t q = (int64_t)((double)a * inv_d);
+  q -= (q * d > a) ? 1 : 0;
+  q += ((q + 1) * d <= a) ? 1 : 0;
+  return q;
+}
+
 __global__ void __launch_bounds__(kScanThreads) link_scan_kernel(LinkScanArgs A) {
   __shared__ unsigned int blk_sh;
   __shared__ long long wsum[kScanThreads / 64];
@@ -717,6 +739,7 @@ __global__ void __launch_bounds__(kScanThreads) link_scan_kernel(LinkScanArgs A)
   __syncthreads();
   long long ex = pre_sh + before + incl - s;
   const int TS = A.TS;
+  const double inv_ts = TS > 0 ? 1.0 / TS : 0.0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = i0 + k;
@@ -725,8 +748,9 @@ __global__ void __launch_bounds__(kScanThreads) link_scan_kernel(LinkScanArgs A)
       if (TS > 0 && v[k] > 0) {
         // tiles T with T*TS in [a + 1, b], and tile 0 for the link holding rib 0
         const int64_t a = ex, b = ex + v[k];
-        const int64_t t0 = (a == 0) ? 0 : (a + TS) / TS;
-        const int64_t t1 = b / TS < A.max_tiles ? b / TS : A.max_tiles;
+        const int64_t t0 = (a == 0) ? 0 : div_small(a + TS, TS, inv_ts);
+        const int64_t bt = div_small(b, TS, inv_ts);
+        const int64_t t1 = bt < A.max_tiles ? bt : A.max_tiles;
         for (int64_t T = t0; T <= t1; ++T) {
           A.tile_link[T] = (int32_t)i;
           if (T < A.max_tiles) A.tile_desc[T] = 0ull;
@@ -886,24 +910,31 @@ __device__ __forceinline__ void sincos_tab32(const float2* tab, float x, float* 
   *c = fmaf(-t.x, sy, fmaf(t.y, cm1, t.y));
 }
 
-// g(t) in FP32 (the single-precision mode): the same forms as eval_point.
+// g(t) in FP32 (the single-precision mode), relative to P0: the Bernstein
+// weights of the other points times their offsets from P0, added to P0 once
+// at the end, so only that last addition rounds at the size of the
+// coordinates.
 __device__ __forceinline__ void eval_point32(int kind, const float* X, const float* Y, float w, float t,
                                              float& gx, float& gy) {
   const float u = 1.0f - t;
+  const float x1 = X[1] - X[0], y1 = Y[1] - Y[0];
+  float ox, oy;
   if (kind == PS_KIND_CUBIC) {
-    const float b0 = u * u * u, b1 = 3.0f * u * u * t, b2 = 3.0f * u * t * t, b3 = t * t * t;
-    gx = b0 * X[0] + b1 * X[1] + b2 * X[2] + b3 * X[3];
-    gy = b0 * Y[0] + b1 * Y[1] + b2 * Y[2] + b3 * Y[3];
+    const float b1 = 3.0f * u * u * t, b2 = 3.0f * u * t * t, b3 = t * t * t;
+    ox = b1 * x1 + b2 * (X[2] - X[0]) + b3 * (X[3] - X[0]);
+    oy = b1 * y1 + b2 * (Y[2] - Y[0]) + b3 * (Y[3] - Y[0]);
   } else if (kind == PS_KIND_LINE) {
-    gx = u * X[0] + t * X[1];
-    gy = u * Y[0] + t * Y[1];
+    ox = t * x1;
+    oy = t * y1;
   } else {
     const float ww = (kind == PS_KIND_CONIC) ? w : 1.0f;
-    const float b0 = u * u, b1 = 2.0f * u * t * ww, b2 = t * t;
-    const float inv = __builtin_amdgcn_rcpf(b0 + b1 + b2);
-    gx = (b0 * X[0] + b1 * X[1] + b2 * X[2]) * inv;
-    gy = (b0 * Y[0] + b1 * Y[1] + b2 * Y[2]) * inv;
+    const float b1 = 2.0f * u * t * ww, b2 = t * t;
+    const float inv = __builtin_amdgcn_rcpf(u * u + b1 + b2);
+    ox = (b1 * x1 + b2 * (X[2] - X[0])) * inv;
+    oy = (b1 * y1 + b2 * (Y[2] - Y[0])) * inv;
   }
+  gx = X[0] + ox;
+  gy = Y[0] + oy;
 }
 
 // Segment rib j of interval v (Eqs. func_t, func_N): the tangent angle
@@ -2550,9 +2581,13 @@ int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, cons
   if (n > 0) {
     CountArgs a{*b, p->q, link_ribs, v.rec, v.seg_ang, v.seg_ok, v.st, (unsigned long long*)v.scan,
                 link_scan_blocks(n_links_of(b))};
+    // the setup in FP64, or in FP32 for the single-precision study mode
+    const bool f32 = p->precision == PS_PREC_FP32;
     if (b->n_segs > 0)
-      hipLaunchKernelGGL(count_angles_kernel, dim3((unsigned)((b->n_segs + 255) / 256)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(count_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(f32 ? count_angles_kernel<float> : count_angles_kernel<double>,
+                         dim3((unsigned)((b->n_segs + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(f32 ? count_kernel<float> : count_kernel<double>, dim3((unsigned)((n + 255) / 256)),
+                       dim3(256), 0, s, a);
   }
   PS_HIP(hipGetLastError());
   return PS_OK;

@@ -264,14 +264,31 @@ def test_unbounded_conics_flagged():
         assert lr[2 * i + p + 1] == 0
 
 
+def _matching_ribs(lr_a, off_a, lr_b, off_b):
+    # rib indices (into a and into b) of the links whose counts agree
+    same = lr_a == lr_b
+    n = lr_a[same].astype(np.int64)
+    rep = np.repeat(np.arange(n.size), n)
+    within = np.arange(int(n.sum()), dtype=np.int64) - np.repeat(np.cumsum(n) - n, n)
+    return off_a[:-1][same][rep] + within, off_b[:-1][same][rep] + within, same
+
+
 def test_fp32_only_is_reported():
-    # single precision alone is allowed a looser bound; it is not the default
+    # single precision throughout (setup, count and emit) is a study mode with
+    # a looser bound: its counts may differ from the FP64 oracle's where a
+    # turn over q lands within FP32 rounding of an integer (the FP64 count's
+    # epsilon is below FP32 resolution); on these random curves at most 1 % of
+    # the links differ, and the links that agree are close
     b = W.config2(n_paths=64, max_segs=32)
     ref = oracle.stroke(b)
     _, out = _gpu(b, ps.PS_PREC_FP32)
-    np.testing.assert_array_equal(_np(out["link_ribs"]), ref["link_ribs"])
-    err = np.hypot(_np(out["vx"]) - ref["vx"], _np(out["vy"]) - ref["vy"])
-    assert err.max() < 0.5
+    lr = _np(out["link_ribs"])
+    ia, ib, same = _matching_ribs(lr, _np(out["offsets"]), ref["link_ribs"], ref["offsets"])
+    assert (~same).sum() <= same.size // 100, (~same).sum()
+    vx, vy = _np(out["vx"]), _np(out["vy"])
+    va = np.concatenate([2 * ia, 2 * ia + 1]); vb = np.concatenate([2 * ib, 2 * ib + 1])
+    err = np.hypot(vx[va] - ref["vx"][vb], vy[va] - ref["vy"][vb])
+    assert err.max() < 0.05, err.max()
 
 
 # --------------------------------------------------------------------- edge cases
