@@ -244,11 +244,13 @@ __device__ __forceinline__ double rcp64(double x) {
   return fma(y, e, y);
 }
 
-// sqrt(x) in FP64 for x >= 0: from the hardware 1/sqrt estimate, one coupled
-// Newton step on (sqrt x, 1/(2 sqrt x)) and two residual corrections
-// x - g^2.  x below 2^-960 (and 0) gives 0: the uses here (squared chords in
-// px^2, discriminants of tangent equations) cannot tell roots below 2^-480
-// from 0, and a select costs less than a branch to the library routine.
+// sqrt(x) in FP64 for x >= 0: from the hardware 1/sqrt estimate (relative
+// error about 2^-23), one coupled Newton step on (sqrt x, 1/(2 sqrt x)),
+// which squares it to about 2^-46, and one residual correction x - g^2,
+// which leaves an error of an ulp or so.  x below 2^-960 (and 0, and
+// negative x) gives 0: the uses here (squared chords in px^2, discriminants
+// of tangent equations) cannot tell roots below 2^-480 from 0, and a select
+// costs less than a branch to the library routine.
 __device__ __forceinline__ double sqrt64(double x) {
   const bool tiny = !(x >= 0x1p-960);
   x = tiny ? 1.0 : x;
@@ -257,9 +259,7 @@ __device__ __forceinline__ double sqrt64(double x) {
   const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
-  double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  d = fma(-g, g, x);
+  const double d = fma(-g, g, x);
   return tiny ? 0.0 : fma(d, h, g);
 }
 

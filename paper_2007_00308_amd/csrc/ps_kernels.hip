@@ -937,6 +937,47 @@ __device__ __forceinline__ void eval_point32(int kind, const float* X, const flo
   gy = Y[0] + oy;
 }
 
+// The parameter of an interior segment rib in FP64: the root of h(t).n = 0
+// (Eq. angle2t; h is the hodograph in Bernstein form, a positive multiple of
+// g') inside [lo, hi], by the rules of solve_t: with two roots inside, the
+// one whose h points along T = (n.y, -n.x) (r0 on a tie); with none, the end
+// with the smaller |h.n|.  Written for the emit's lanes: quadratics (A = 0,
+// the equation linear) take the same instructions as cubics (qq = -B, and
+// r1 = C/qq is the root), one reciprocal serves both roots (r0 = qq/A =
+// qq^2/(A qq), r1 = C/qq = C A/(A qq)), and a zero or negative discriminant
+// or a zero denominator gives roots that no interval holds.
+__device__ __forceinline__ double emit_solve64(const Hodo<double>& h, double nx, double ny, double lo,
+                                               double hi) {
+  const double al = h.e0x * nx + h.e0y * ny;
+  const double be = h.e1x * nx + h.e1y * ny;
+  const double ga = h.e2x * nx + h.e2y * ny;
+  const double A = al - 2.0 * be + ga, B = 2.0 * (be - al), C = al;
+  const bool quad = A == 0.0;
+  const double disc = fma(B, B, -4.0 * A * C);
+  const double sq = quad ? fabs(B) : sqrt64(disc);   // sqrt64 gives 0 below 2^-960
+  const double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+  const double inv = rcp64(quad ? qq : A * qq);
+  const bool real = disc >= 0.0;
+  const double r1 = real ? (quad ? C : C * A) * inv : -1.0;
+  const double r0 = real ? (quad ? r1 : qq * qq * inv) : -1.0;
+  const bool in0 = r0 >= lo && r0 <= hi;
+  const bool in1 = r1 >= lo && r1 <= hi && r1 != r0;
+  double t = in0 ? r0 : (in1 ? r1 : hi);
+  if (__ballot(in0 && in1)) {
+    // scores h(t).T in power form: T-components of the Bernstein coefficients
+    const double tx = ny, ty = -nx;
+    const double a0 = h.e0x * tx + h.e0y * ty, b0 = h.e1x * tx + h.e1y * ty, c0 = h.e2x * tx + h.e2y * ty;
+    const double aT = a0 - 2.0 * b0 + c0, bT = 2.0 * (b0 - a0);
+    const double s0 = fma(fma(aT, r0, bT), r0, a0), s1 = fma(fma(aT, r1, bT), r1, a0);
+    if (in0 && in1 && s1 > s0) t = r1;
+  }
+  if (__ballot(!(in0 || in1))) {
+    const double hl = fma(fma(A, lo, B), lo, C), hh = fma(fma(A, hi, B), hi, C);
+    if (!(in0 || in1)) t = (fabs(hl) < fabs(hh)) ? lo : hi;
+  }
+  return t;
+}
+
 // Segment rib j of interval v (Eqs. func_t, func_N): the tangent angle
 // psi_j = psi_{k-1} + (j - Delta_Sigma(k-1)) delta_k / Delta_k (the boundary
 // angles exactly at the interval ends), n(psi) = (-sin psi, cos psi), t from
@@ -1016,7 +1057,7 @@ __device__ __forceinline__ void seg_rib(const LinkRec& rp, int j, const RibIval&
       }
       if (need64) {
         const Hodo<double> h = hodo_of<double>(kind, Xd, Yd, (double)rp.w);
-        t = solve_t<double>(h, nx, ny, ny, -nx, v.lo, v.hi).t;
+        t = emit_solve64(h, nx, ny, v.lo, v.hi);
       }
     }
     eval_point(kind, Xd, Yd, (double)rp.w, t, o.gx, o.gy);
