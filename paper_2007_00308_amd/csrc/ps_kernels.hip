@@ -99,6 +99,11 @@ struct CountArgs {
 
 __device__ __forceinline__ void set_flag(DevStatus* st, unsigned f) { atomicOr(&st->flags, f); }
 
+__device__ __forceinline__ void reset_status(DevStatus* st) {
+  st->flags = 0; st->total_ribs = 0; st->fixups = 0; st->dash_ribs = 0; st->dash_count = 0;
+  st->tile_counter = 0; st->dash_tile_counter = 0; st->scan_ticket = 0;
+}
+
 __device__ __forceinline__ int path_of_seg(const int32_t* seg_begin, int n_paths, int i) {
   // largest p with seg_begin[p] <= i (the path that owns segment i)
   int a = 0, b = n_paths - 1;
@@ -111,15 +116,19 @@ __device__ __forceinline__ int path_of_seg(const int32_t* seg_begin, int n_paths
 
 // A segment contributes ribs if its values are finite and valid and it is
 // not a single point (a zero-length segment strokes nothing).
-__device__ inline bool seg_usable(const ps_batch& B, int i, DevStatus* st, bool report) {
+// Segment states: usable, or the status bit its problem raises (the count
+// kernel raises it, so the angles pass, which runs first, may reset the
+// status word).
+constexpr uint8_t kSegUsable = 1, kSegBadValue = 2, kSegNonFinite = 4;
+__device__ inline uint8_t seg_state(const ps_batch& B, int i) {
   const int k = B.kind[i];
-  if (k > PS_KIND_CUBIC) { if (report) set_flag(st, PS_STATUS_BAD_VALUE); return false; }
+  if (k > PS_KIND_CUBIC) return kSegBadValue;
   const Seg s = load_seg(B, i);
-  if (!seg_finite(s)) { if (report) set_flag(st, PS_STATUS_NONFINITE); return false; }
+  if (!seg_finite(s)) return kSegNonFinite;
   // w_B <= -1 puts a root of the conic's denominator in [0,1]: the curve runs
   // through a point at infinity and its stroke is unbounded
-  if (k == PS_KIND_CONIC && !(s.w > -1.0)) { if (report) set_flag(st, PS_STATUS_BAD_VALUE); return false; }
-  return !seg_is_point(s);
+  if (k == PS_KIND_CONIC && !(s.w > -1.0)) return kSegBadValue;
+  return seg_is_point(s) ? 0 : kSegUsable;
 }
 
 #pragma clang fp contract(off)
@@ -310,15 +319,14 @@ __device__ int cap_steps(int style, F q) {
   return 0;
 }
 
-// Whether segment k is usable (decided on the exact inputs), and its start
-// and end tangent angles in F (Eq. Psi at t = 0 and 1, through the end
-// gradients and their fallbacks); `report` flags bad or non-finite values.
+// The state of segment k (decided on the exact inputs), and for a usable
+// one its start and end tangent angles in F (Eq. Psi at t = 0 and 1, through
+// the end gradients and their fallbacks).
 template <typename F>
-__device__ inline void seg_angles(const ps_batch& B, int k, DevStatus* st, bool report, bool& ok,
-                                  double2& ang) {
-  ok = seg_usable(B, k, st, report);
+__device__ inline void seg_angles(const ps_batch& B, int k, uint8_t& state, double2& ang) {
+  state = seg_state(B, k);
   ang = make_double2(0.0, 0.0);
-  if (ok) {
+  if (state & kSegUsable) {
     const SegT<F> s = load_seg<F>(B, k);
     F sx, sy, ex, ey;
     start_dir(s, sx, sy);
@@ -328,17 +336,19 @@ __device__ inline void seg_angles(const ps_batch& B, int k, DevStatus* st, bool 
   }
 }
 
-// First count pass, one thread per segment: whether it is usable and its
-// start and end tangent angles.  Reports bad or non-finite segments.
+// First count pass, one thread per segment: its state and its start and
+// end tangent angles.  The chain's first kernel, so its first thread resets
+// the status word (problems found here are raised by the count kernel).
 template <typename F>
 __global__ void __launch_bounds__(256) count_angles_kernel(CountArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) reset_status(A.st);
   if (i >= A.B.n_segs) return;
-  bool ok;
+  uint8_t state;
   double2 ang;
-  seg_angles<F>(A.B, (int)i, A.st, true, ok, ang);
+  seg_angles<F>(A.B, (int)i, state, ang);
   A.seg_ang[i] = ang;
-  A.seg_ok[i] = ok ? 1 : 0;
+  A.seg_ok[i] = state;
 }
 
 #pragma clang fp contract(on)
@@ -390,7 +400,10 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
   if (tid < A.scan_nb) A.scan_desc[tid] = 0ull;   // scan_nb <= S + P threads
   if (tid < S) {
     const int i = (int)tid;
-    const bool ok_i = A.seg_ok[i];
+    const uint8_t state = A.seg_ok[i];
+    if (state & kSegBadValue) set_flag(A.st, PS_STATUS_BAD_VALUE);
+    if (state & kSegNonFinite) set_flag(A.st, PS_STATUS_NONFINITE);
+    const bool ok_i = state & kSegUsable;
     const double2 ang = A.seg_ang[i];   // F values
     const int p = path_of_seg(B.seg_begin, P, i);
     const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
@@ -426,7 +439,7 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
         // the first segment with ribs of the path (no usable segment before
         // it), and the first link with ribs (also no start cap ribs)
         bool first_seg = true;
-        for (int k = i - 1; first_seg && k >= b; --k) first_seg = !A.seg_ok[k];
+        for (int k = i - 1; first_seg && k >= b; --k) first_seg = !(A.seg_ok[k] & kSegUsable);
         if (first_seg) r.flags |= kFirstSegInPath;
         if (first_seg && (closed || cap_steps<F>(B.cap[p], q) == 0)) r.flags |= kFirstInPath;
       }
@@ -446,9 +459,9 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     // back to its first
     int next = -1;
     for (int k = i + 1; k < e && next < 0; ++k)
-      if (A.seg_ok[k]) next = k;
+      if (A.seg_ok[k] & kSegUsable) next = k;
     for (int k = b; k <= i && next < 0 && closed; ++k)
-      if (A.seg_ok[k]) next = k;
+      if (A.seg_ok[k] & kSegUsable) next = k;
     if (next >= 0) {
       F d = adiff((F)A.seg_ang[next].x, psi_e);
       if (d == -(F)kPi) d = (F)kPi;   // antiparallel: turn +pi
@@ -469,7 +482,7 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
                     B.join[p] <= PS_JOIN_MITER_CLIP;
     if (ok && !(B.closed && B.closed[p])) {   // a closed contour has no caps
       for (int k = b; k < e; ++k) {
-        if (!A.seg_ok[k]) continue;
+        if (!(A.seg_ok[k] & kSegUsable)) continue;
         const F psi_s = (F)A.seg_ang[k].x;
         const F q = (F)A.q;
         const int J = cap_steps<F>(B.cap[p], q);
@@ -497,10 +510,7 @@ __global__ void copy_status_flags_kernel(const DevStatus* st, uint32_t* out) {
 }
 
 __global__ void reset_status_kernel(DevStatus* st) {
-  if (threadIdx.x == 0) {
-    st->flags = 0; st->total_ribs = 0; st->fixups = 0; st->dash_ribs = 0; st->dash_count = 0;
-    st->tile_counter = 0; st->dash_tile_counter = 0; st->scan_ticket = 0;
-  }
+  if (threadIdx.x == 0) reset_status(st);
 }
 
 // ===========================================================================
@@ -661,7 +671,7 @@ __device__ __forceinline__ bool look_back(const unsigned long long* desc, int64_
   }
 }
 
-// The link-rib scan in one pass: blocks of kScanTile links take tickets in
+// The link-rib scan in one pass: blocks of kLinkScanTile links take tickets in
 // order, publish their sums and look back for their prefixes, so each link's
 // offset is written once with no second pass.  With TS > 0 it also writes
 // the tile table of an emit of TS-rib tiles (the tile_link entries and
@@ -670,6 +680,12 @@ __device__ __forceinline__ bool look_back(const unsigned long long* desc, int64_
 // thread that owns position n_links writes offset[n_links] = R, the rib
 // total, and the emit's overflow flag.  The look-back words (one per block)
 // and the ticket are cleared by the count kernel and the status reset.
+// 256 threads of 16 links per block (measured on the 4096-path batch, 166
+// blocks: 11.3 us; 1024-thread blocks, whose look-backs all end within one
+// 64-word read, 14.8 us: fewer blocks leave most CUs idle)
+constexpr int kLinkScanThreads = 256;
+constexpr int kLinkScanTile = kLinkScanThreads * kScanItems;
+
 struct LinkScanArgs {
   const int32_t* link_ribs;
   int64_t n;
@@ -691,15 +707,15 @@ __device__ __forceinline__ int64_t div_small(int64_t a, int64_t d, double inv_d)
   return q;
 }
 
-__global__ void __launch_bounds__(kScanThreads) link_scan_kernel(LinkScanArgs A) {
+__global__ void __launch_bounds__(kLinkScanThreads) link_scan_kernel(LinkScanArgs A) {
   __shared__ unsigned int blk_sh;
-  __shared__ long long wsum[kScanThreads / 64];
+  __shared__ long long wsum[kLinkScanThreads / 64];
   __shared__ long long pre_sh;
   if (threadIdx.x == 0) blk_sh = (unsigned)atomicAdd(&A.st->scan_ticket, 1ull);
   __syncthreads();
   const int64_t blk = blk_sh;
   const int64_t n = A.n;
-  const int64_t i0 = blk * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int64_t i0 = blk * kLinkScanTile + (int64_t)threadIdx.x * kScanItems;
   int v[kScanItems];
   long long s = 0;
   if (i0 + kScanItems <= n && ((uintptr_t)A.link_ribs & 15) == 0) {
@@ -721,7 +737,7 @@ __global__ void __launch_bounds__(kScanThreads) link_scan_kernel(LinkScanArgs A)
   __syncthreads();
   long long before = 0, total = 0;
 #pragma unroll
-  for (int k = 0; k < kScanThreads / 64; ++k) {
+  for (int k = 0; k < kLinkScanThreads / 64; ++k) {
     before += k < wv ? wsum[k] : 0;
     total += wsum[k];
   }
@@ -737,37 +753,67 @@ __global__ void __launch_bounds__(kScanThreads) link_scan_kernel(LinkScanArgs A)
     }
   }
   __syncthreads();
-  long long ex = pre_sh + before + incl - s;
-  const int TS = A.TS;
-  const double inv_ts = TS > 0 ? 1.0 / TS : 0.0;
+  const long long ex0 = pre_sh + before + incl - s;
+  // offsets: 16-byte stores when the thread's 16 items are whole and aligned
+  if (i0 + kScanItems <= n && ((uintptr_t)(A.off + i0) & 15) == 0) {
+    long long e = ex0;
+    longlong2* dst = reinterpret_cast<longlong2*>(A.off + i0);
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = i0 + k;
-    if (i < n) {
-      A.off[i] = ex;
-      if (TS > 0 && v[k] > 0) {
-        // tiles T with T*TS in [a + 1, b], and tile 0 for the link holding rib 0
-        const int64_t a = ex, b = ex + v[k];
-        const int64_t t0 = (a == 0) ? 0 : div_small(a + TS, TS, inv_ts);
-        const int64_t bt = div_small(b, TS, inv_ts);
-        const int64_t t1 = bt < A.max_tiles ? bt : A.max_tiles;
-        for (int64_t T = t0; T <= t1; ++T) {
+    for (int c = 0; c < kScanItems / 2; ++c) {
+      longlong2 w;
+      w.x = e; e += v[2 * c];
+      w.y = e; e += v[2 * c + 1];
+      dst[c] = w;
+    }
+  } else {
+    long long e = ex0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (i0 + k < n) A.off[i0 + k] = e;
+      e += v[k];
+    }
+  }
+  if (i0 <= n && n < i0 + kScanItems) {
+    // the thread that owns position n: the total, and the emit's flags
+    long long e = ex0;
+    for (int k = 0; k < kScanItems; ++k) e += (i0 + k < n) ? v[k] : 0;
+    A.off[n] = e;
+    A.st->total_ribs = (unsigned long long)e;
+    if (A.TS > 0) {
+      const int64_t n_tiles = (e + A.TS - 1) / A.TS;
+      if (e == 0) A.tile_link[0] = 0;
+      A.st->tile_counter = 0;
+      atomicAnd(&A.st->flags, ~(unsigned)PS_STATUS_OVERFLOW);
+      if (2 * e > A.capacity || n_tiles > A.max_tiles) atomicOr(&A.st->flags, (unsigned)PS_STATUS_OVERFLOW);
+    }
+  }
+  if (A.TS > 0) {
+    // the tile table: tile T (T >= 1) first reads rib T*TS - 1, held by the
+    // link [a, b) with T*TS in [a + 1, b]; tile 0 by the first link with
+    // ribs.  The thread walks its links with the next tile start past its
+    // first offset (one division per thread).
+    const int64_t TS = A.TS;
+    int64_t T = div_small(ex0, TS, 1.0 / (double)TS) + 1;
+    int64_t next = T * TS;
+    long long a = ex0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = i0 + k;
+      const long long b = a + v[k];
+      if (i < n && v[k] > 0) {
+        if (a == 0) {
+          A.tile_link[0] = (int32_t)i;
+          A.tile_desc[0] = 0ull;
+        }
+        while (next <= b && T <= A.max_tiles) {
           A.tile_link[T] = (int32_t)i;
           if (T < A.max_tiles) A.tile_desc[T] = 0ull;
+          ++T;
+          next += TS;
         }
       }
-    } else if (i == n) {
-      A.off[n] = ex;
-      A.st->total_ribs = (unsigned long long)ex;
-      if (TS > 0) {
-        const int64_t n_tiles = (ex + TS - 1) / TS;
-        if (ex == 0) A.tile_link[0] = 0;
-        A.st->tile_counter = 0;
-        atomicAnd(&A.st->flags, ~(unsigned)PS_STATUS_OVERFLOW);
-        if (2 * ex > A.capacity || n_tiles > A.max_tiles) atomicOr(&A.st->flags, (unsigned)PS_STATUS_OVERFLOW);
-      }
+      a = b;
     }
-    ex += v[k];
   }
 }
 
@@ -2469,7 +2515,7 @@ struct WsView {
   DevStatus* st;
   LinkRec* rec;
   double2* seg_ang;   // per segment: start and end tangent angles (usable segments)
-  uint8_t* seg_ok;    // per segment: usable (finite, valid, not a single point)
+  uint8_t* seg_ok;    // per segment: state (usable, or the status bit its problem raises)
   long long* scan;
   int32_t* tile_link;
   unsigned long long* desc;
@@ -2515,9 +2561,9 @@ int num_cus() {
   return cus;
 }
 
-// blocks of the one-pass link scan: one per kScanTile links, plus the one
+// blocks of the one-pass link scan: one per kLinkScanTile links, plus the one
 // that owns position n_links
-int64_t link_scan_blocks(int64_t n_links) { return n_links / kScanTile + 1; }
+int64_t link_scan_blocks(int64_t n_links) { return n_links / kLinkScanTile + 1; }
 
 // The one-pass link scan of a count -> scan -> emit chain (after the count
 // kernel, which clears its look-back words), with the tile table of the
@@ -2528,7 +2574,7 @@ int do_link_scan(const int32_t* link_ribs, int64_t L, int64_t* off, const WsView
   a.link_ribs = link_ribs; a.n = L; a.off = off; a.desc = (unsigned long long*)v.scan; a.st = v.st;
   a.TS = 64 * K; a.tile_link = v.tile_link; a.tile_desc = v.desc; a.capacity = cap;
   a.max_tiles = w.max_tiles;
-  hipLaunchKernelGGL(link_scan_kernel, dim3((unsigned)link_scan_blocks(L)), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(link_scan_kernel, dim3((unsigned)link_scan_blocks(L)), dim3(kLinkScanThreads), 0, s, a);
   PS_HIP(hipGetLastError());
   return PS_OK;
 }
@@ -2617,7 +2663,8 @@ float fixup_tolerance() {
 
 int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, const WsView& v,
                  hipStream_t s) {
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, v.st);
+  // the angles pass resets the status word; without segments a kernel of its own does
+  if (b->n_segs == 0) hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, v.st);
   const int64_t n = (int64_t)b->n_segs + b->n_paths;
   if (n > 0) {
     CountArgs a{*b, p->q, link_ribs, v.rec, v.seg_ang, v.seg_ok, v.st, (unsigned long long*)v.scan,

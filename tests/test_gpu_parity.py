@@ -153,6 +153,19 @@ def test_config5_full_sampled():
         assert err.max() <= VERTEX_TOL, (p, err.max())
         vs = _np(out["vs"][2 * a:2 * e:2]).astype(np.float64)
         _check_arc(vs, ref["vs"][ra:re], np.arange(re - ra), f"path {p}")
+    # the same batch through an autotuned plan, as bench.py times it (its
+    # one-pass link scan spans 529 blocks here, so look-backs read several
+    # windows of 64 words): bits identical to the checked run
+    R = out["total_ribs"]
+    plan = ps.Plan(db, b.q, vertex_capacity=2 * R)
+    plan.launch()
+    torch.cuda.synchronize()
+    st = plan.status()
+    assert st.flags == 0 and st.total_ribs == R
+    assert torch.equal(plan.offsets, out["offsets"])
+    for k in ("vx", "vy", "vs"):
+        assert torch.equal(getattr(plan, k)[:2 * R], out[k][:2 * R]), k
+    plan.close()
 
 
 def test_config3_full_path():
