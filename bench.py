@@ -79,7 +79,8 @@ def main() -> int:
                          "instead of the plan's autotuning, e.g. for profiles of one mapping")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit", "c1", "facets", "coverage"], default=None,
+    ap.add_argument("--study", choices=["precision", "c3", "c5", "emit", "c1", "facets", "coverage", "mappings"],
+                    default=None,
                     help="secondary measurements: the near-degenerate precision study, the long "
                          "dashed path, or the stress configuration at q in {pi/16, pi/64, pi/256}")
     args = ap.parse_args()
@@ -272,7 +273,8 @@ def main() -> int:
         "gb_per_s": B_alg / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": emit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": emit_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(f"{mapping},{K},{waves}"),
-                     "kernel": "emit (prepare + persistent emit, one ps_emit call)",
+                     "kernel": "emit (the persistent emit kernel of the plan's graph, between its event nodes; "
+                               "its tile table comes from the link scan)",
                      "ms_per_launch": emit_ms, "algorithmic_bytes_per_launch": emit_bytes},
         "per_path": per_path,
         "cpu_baseline": cpu,
@@ -510,6 +512,54 @@ def study_emit(args, torch, ps, W, dev):
     return 0
 
 
+def study_mappings(args, torch, ps, W, dev):
+    """Every emit mapping (tiles and links) x K x wavefronts per group on each
+    configuration: C1, C3, C2 and C5 at q = pi/16, pi/64, pi/256; ms per
+    unplanned ps_emit with arc length, the best of each mapping, and what a
+    plan picks."""
+    configs = [(m, K, w_) for m in (ps.PS_MAP_TILES, ps.PS_MAP_LINKS) for K in (4, 6, 7, 8, 16)
+               for w_ in (1, 2, 4)]
+    cases = [("C1", W.config1), ("C3", W.config3), ("C2", W.config2_fast)] + \
+            [(f"C5 q=pi/{qn}", (lambda qn=qn: W.config5(q=math.pi / qn))) for qn in (16, 64, 256)]
+    stream = torch.cuda.current_stream()
+    out = []
+    for name, make in cases:
+        b = make()
+        db = ps.DeviceBatch(b, device=dev)
+        first = ps.stroke(db, b.q)
+        R = first["total_ribs"]
+        del first
+        plan = ps.Plan(db, b.q, vertex_capacity=2 * R)
+        picked = plan.config()
+        reps = 20 if R < 10_000_000 else 5
+        times = {}
+        for emit in configs:
+            P = ps.make_params(b.q, emit=emit)
+            for _ in range(2):
+                ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                ps.ps_emit(db, P, plan.offsets, plan.vx, plan.vy, plan.vs, 2 * R, plan.ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[emit] = e0.elapsed_time(e1) / reps
+        plan.close()
+        best = {}
+        for m, label in ((ps.PS_MAP_TILES, "tiles"), (ps.PS_MAP_LINKS, "links")):
+            c = min((k for k in times if k[0] == m), key=lambda k: times[k])
+            best[label] = {"K": c[1], "waves": c[2], "ms": times[c]}
+        row = {"workload": name, "ribs": R, "plan_picks": {"mapping": picked[0], "K": picked[1], "waves": picked[2]},
+               "plan_pick_ms": times.get(tuple(picked)), "best": best,
+               "all_ms": {f"{k[0]},{k[1]},{k[2]}": round(v, 4) for k, v in times.items()}}
+        out.append(row)
+        log(f"{name}: ribs {R}, plan picks {picked}, best {best}")
+        del db
+        torch.cuda.empty_cache()
+    print(json.dumps({"study": "mappings", "rows": out}), flush=True)
+    return 0
+
+
 def study_c1(args, torch, ps, W, dev):
     """C1, one path of 64 cubics: latency of the whole chain per path (one plan
     replay, and the three unplanned calls) and its vertices/s."""
@@ -639,6 +689,7 @@ def study_coverage(args, torch, ps, W, dev):
 
 
 STUDIES = {"precision": study_precision, "c3": study_c3, "c5": study_c5, "emit": study_emit, "c1": study_c1,
+           "mappings": study_mappings,
            "facets": study_facets, "coverage": study_coverage}
 
 
