@@ -481,7 +481,7 @@ def study_emit(args, torch, ps, W, dev):
     plan = ps.Plan(db, b.q, vertex_capacity=2 * R)
     stream = torch.cuda.current_stream()
 
-    def timed(fn, reps=10):
+    def timed(fn, reps=10 if not args.emit_config else 40):
         for _ in range(2):
             fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -494,8 +494,10 @@ def study_emit(args, torch, ps, W, dev):
 
     cap, ws = 2 * R, plan.ws
     rows = []
-    configs = [(m, K, w_) for m in (ps.PS_MAP_TILES, ps.PS_MAP_LINKS) for K in (4, 5, 6, 7, 8, 16)
+    configs = [(m, K, w_) for m in (ps.PS_MAP_TILES, ps.PS_MAP_LINKS) for K in (4, 6, 7, 8, 16)
                for w_ in (1, 2, 4)]
+    if args.emit_config:   # one mapping only
+        configs = [tuple(int(x) for x in args.emit_config.split(","))]
     for emit in configs:
         P = ps.make_params(b.q, emit=emit)
         try:

@@ -1310,13 +1310,16 @@ __host__ __device__ constexpr size_t emit_split_lds_per_wave(int K, bool ws) {
 // Stores of a tile's vertex pairs through a buffer resource that spans only
 // the tile's own bytes: 32-bit offsets from the tile start instead of 64-bit
 // addresses per lane, and a store outside the tile is dropped by the hardware.
+// The stores are non-temporal (the output is not read again by the emit):
+// measured 0.424 against 0.448 ms per emit on the 4096-path batch.
 typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+constexpr int kStoreNT = 2;   // cache-policy operand: the nt (non-temporal) bit
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(float* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);   // raw dwords (gfx9)
 }
 __device__ __forceinline__ void store_pair(__amdgpu_buffer_rsrc_t r, int rel, float a, float b) {
   const v2u32 d = {__float_as_uint(a), __float_as_uint(b)};
-  __builtin_amdgcn_raw_buffer_store_b64(d, r, rel * 8, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(d, r, rel * 8, 0, kStoreNT);
 }
 
 // A computed tile whose arc length still needs its prefix.
