@@ -641,18 +641,25 @@ __device__ __forceinline__ unsigned long long desc_read(const unsigned long long
 }
 
 // The sum of the values of look-back words before word `first` (exclusive of
-// it) up to the nearest inclusive one, read by one wavefront 64 words at a
-// time.  Word: 2 state bits (0 not ready, 1 the unit's own sum, 2 the sum of
-// everything up to and including the unit) and 62 value bits.  Without
-// `block`, gives up (returns false) when a needed word is not ready.
+// it) up to the nearest inclusive one, read by one wavefront.  Word: 2 state
+// bits (0 not ready, 1 the unit's own sum, 2 the sum of everything up to and
+// including the unit) and 62 value bits.  The first read takes the 16 words
+// before `first` (one 128-byte line; the nearest inclusive word is usually
+// among them), later ones 64 at a time: these reads are device-coherent, so
+// they go past the XCD's L2, and reading 64 words per try made up about half
+// of the emit's reads.  Without `block`, gives up (returns false) when a
+// needed word is not ready.
 __device__ __forceinline__ bool look_back(const unsigned long long* desc, int64_t first, bool block,
                                           unsigned long long& prefix) {
   const int lane = threadIdx.x & 63;
   int64_t bT = first - 1;
+  int span = 16;
   prefix = 0;
   for (;;) {
     const int64_t Ti = bT - lane;
-    const unsigned long long wd = Ti >= 0 ? desc_read(&desc[Ti]) : (2ull << 62);
+    // lanes past this read's span act as empty aggregates
+    unsigned long long wd = 1ull << 62;
+    if (lane < span) wd = Ti >= 0 ? desc_read(&desc[Ti]) : (2ull << 62);
     const unsigned stt = (unsigned)(wd >> 62);
     const unsigned long long incl = __ballot(stt == 2);
     const int stop = incl ? __builtin_ctzll(incl) : 64;   // nearest inclusive word
@@ -667,7 +674,8 @@ __device__ __forceinline__ bool look_back(const unsigned long long* desc, int64_
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     prefix += v;
     if (stop < 64) return true;
-    bT -= 64;
+    bT -= span;
+    span = 64;
   }
 }
 
@@ -956,6 +964,19 @@ __device__ __forceinline__ void sincos_tab32(const float2* tab, float x, float* 
   *c = fmaf(-t.x, sy, fmaf(t.y, cm1, t.y));
 }
 
+// The same from the FP64 table, its entries rounded to FP32 as they are read.
+__device__ __forceinline__ void sincos_tab32d(const double2* tab, float x, float* s, float* c) {
+  const float k = rintf(x * (float)(kSinTab / kTwoPi));
+  const float y = fmaf(-k, kTab32Lo, fmaf(-k, kTab32Hi, x));
+  const float z = y * y;
+  const float sy = fmaf(y * z, -1.0f / 6, y);
+  const float cm1 = z * fmaf(z, 1.0f / 24, -0.5f);
+  const double2 t = tab[(int)k & (kSinTab - 1)];
+  const float tx = (float)t.x, ty = (float)t.y;
+  *s = fmaf(ty, sy, fmaf(tx, cm1, tx));
+  *c = fmaf(-tx, sy, fmaf(ty, cm1, ty));
+}
+
 // g(t) in FP32 (the single-precision mode), relative to P0: the Bernstein
 // weights of the other points times their offsets from P0, added to P0 once
 // at the end, so only that last addition rounds at the size of the
@@ -1154,33 +1175,34 @@ __device__ __forceinline__ void miter_vertex(const LinkRec& rp, int j, int style
 // Approach for Caps and Joins"), psi_j = psi_0 + j delta / J (exact at both
 // ends); only the side away from the turn keeps its radius; the square cap's
 // ribs 1 and 3 reach r sqrt 2; miter joins replace the outer vertex of ribs
-// 1 and 2.
+// 1 and 2.  The direction is FP32 in every mode: the pivot point is exact and
+// a rib's vertex is at most r sqrt 2 from it, so an angle error of 1e-6 rad
+// (the FP32 rounding of psi within a few turns) moves it by under 1e-4 px at
+// r = 64, below the FP32 rounding of the coordinates; nothing downstream
+// depends on a pivot's direction (pivots add no arc length).  The miter
+// vertices stay FP64.
 template <int PREC>
 __device__ __forceinline__ void piv_rib(const LinkRec& rp, int j, double miter_limit, const double2* tab,
                                         const float2* tab32, RibOut& o) {
   const int style = rp.flags >> 4;
   const int J = rp.dsum[0];
   const double psa = rp.psi[0], psb = rp.psi[1];
-  const double psi = j == 0 ? psa : (j == J ? psb : psa + (psb - psa) * ((double)j * rcp64((double)J)));
-  double nx, ny;
-  if constexpr (PREC == PS_PREC_FP32) {
-    float s32, c32;
-    sincos_tab32(tab32, (float)psi, &s32, &c32);
-    nx = -s32; ny = c32;
-  } else {
-    double sn, cs;
-    sincos_tab(tab, psi, &sn, &cs);
-    nx = -sn; ny = cs;
-  }
-  double rout = rp.r;
+  const float psa32 = (float)psa;
+  const float psi = j == 0 ? psa32
+                  : (j == J ? (float)psb : fmaf((float)(psb - psa), (float)j * __builtin_amdgcn_rcpf((float)J), psa32));
+  float sn, cs;
+  if constexpr (PREC == PS_PREC_FP32) sincos_tab32(tab32, psi, &sn, &cs);
+  else sincos_tab32d(tab, psi, &sn, &cs);
+  const float nx = -sn, ny = cs;
+  float rout = rp.r;
   if ((rp.role == ROLE_SCAP || rp.role == ROLE_ECAP) && style == PS_CAP_SQUARE && (j == 1 || j == 3))
-    rout *= 1.41421356237309504880;
+    rout *= 1.41421356f;
   const bool left_turn = (psb - psa) > 0;
-  const double rN = left_turn ? rout : 0.0, rP = left_turn ? 0.0 : rout;
-  const double cx = rp.x[0], cy = rp.y[0];
+  const float rN = left_turn ? rout : 0.0f, rP = left_turn ? 0.0f : rout;
+  const float cx = rp.x[0], cy = rp.y[0];
   o.gx = cx; o.gy = cy; o.t = 0.0; o.fixed = false;
-  o.Nx = (float)(cx - rN * nx); o.Ny = (float)(cy - rN * ny);
-  o.Px = (float)(cx + rP * nx); o.Py = (float)(cy + rP * ny);
+  o.Nx = fmaf(-rN, nx, cx); o.Ny = fmaf(-rN, ny, cy);
+  o.Px = fmaf(rP, nx, cx); o.Py = fmaf(rP, ny, cy);
   if (rp.role == ROLE_JOIN && (j == 1 || j == 2) && (style == PS_JOIN_MITER || style == PS_JOIN_MITER_CLIP)) {
     double vx, vy;
     miter_vertex(rp, j, style, miter_limit, vx, vy);
@@ -1317,9 +1339,10 @@ constexpr int kStoreNT = 2;   // cache-policy operand: the nt (non-temporal) bit
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(float* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);   // raw dwords (gfx9)
 }
+template <int POLICY = kStoreNT>
 __device__ __forceinline__ void store_pair(__amdgpu_buffer_rsrc_t r, int rel, float a, float b) {
   const v2u32 d = {__float_as_uint(a), __float_as_uint(b)};
-  __builtin_amdgcn_raw_buffer_store_b64(d, r, rel * 8, 0, kStoreNT);
+  __builtin_amdgcn_raw_buffer_store_b64(d, r, rel * 8, 0, POLICY);
 }
 
 // A computed tile whose arc length still needs its prefix.
