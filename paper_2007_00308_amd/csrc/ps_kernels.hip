@@ -398,8 +398,36 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int S = B.n_segs, P = B.n_paths;
   if (tid < A.scan_nb) A.scan_desc[tid] = 0ull;   // scan_nb <= S + P threads
-  if (tid < S) {
-    const int i = (int)tid;
+  // The workgroup's segments are handed to its threads grouped by form
+  // (unusable, line, quadratic, conic, cubic), so that a wavefront mostly
+  // runs one form's setup instead of all of them one after another.  Which
+  // thread takes a segment changes nothing in what is written.
+  __shared__ int form_count[8];
+  __shared__ int form_order[256];
+  const int i0 = (int)blockIdx.x * 256;
+  const int nseg = S - i0 < 256 ? S - i0 : 256;   // <= 0 in the path workgroups
+  int seg = -1;
+  if (nseg > 0) {
+    if (threadIdx.x < 8) form_count[threadIdx.x] = 0;
+    __syncthreads();
+    int form = -1, rank = 0;
+    if ((int)threadIdx.x < nseg) {
+      const int k = B.kind[i0 + threadIdx.x];
+      form = !(A.seg_ok[i0 + threadIdx.x] & kSegUsable) ? 0
+           : (k == PS_KIND_CUBIC ? 4 : (k == PS_KIND_CONIC ? 3 : (k == PS_KIND_QUAD ? 2 : 1)));
+      rank = atomicAdd(&form_count[form], 1);
+    }
+    __syncthreads();
+    if (form >= 0) {
+      int at = rank;
+      for (int f = 0; f < form; ++f) at += form_count[f];
+      form_order[at] = (int)threadIdx.x;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nseg) seg = i0 + form_order[threadIdx.x];
+  }
+  if (seg >= 0) {
+    const int i = seg;
     const uint8_t state = A.seg_ok[i];
     if (state & kSegBadValue) set_flag(A.st, PS_STATUS_BAD_VALUE);
     if (state & kSegNonFinite) set_flag(A.st, PS_STATUS_NONFINITE);
