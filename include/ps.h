@@ -52,15 +52,21 @@ enum { PS_JOIN_NONE = 0, PS_JOIN_BEVEL = 1, PS_JOIN_ROUND = 2, PS_JOIN_TRIANGLE 
        PS_JOIN_MITER = 4, PS_JOIN_MITER_CLIP = 5 };
 /* Cap styles (Secs. "Easy Caps", "Harder Caps"): J = 0, ceil(pi/q), 4, 2. */
 enum { PS_CAP_BUTT = 0, PS_CAP_ROUND = 1, PS_CAP_SQUARE = 2, PS_CAP_TRIANGLE = 3 };
-/* Arithmetic of the per-rib direction and tangent-angle solve (Eq. angle2t);
- * the setup (ps_count), the point evaluation and the arc length are FP64 in
- * every mode:
- *   FP32        single precision direction and solve (studies only);
- *   FP32_FIXUP  FP64 direction, FP32 root isolation polished by one FP64
- *               Newton step, re-solved in FP64 where that is ill-conditioned;
- *   FP64        double precision for every rib (recommended: on gfx950 the
- *               FP64 vector rate equals the unpacked FP32 rate, and it is the
- *               shortest instruction path). */
+/* Arithmetic of the segment ribs' direction and tangent-angle solve (Eq.
+ * angle2t):
+ *   FP32        single precision throughout: setup and counts (ps_count),
+ *               direction, solve, point; a study mode, whose counts can
+ *               differ from the FP64 ones and whose vertices can be far off
+ *               on near-degenerate segments;
+ *   FP32_FIXUP  FP64 setup, direction and point; FP32 root isolation
+ *               polished by one FP64 Newton step, re-solved in FP64 where
+ *               that is ill-conditioned;
+ *   FP64        double precision for every segment rib (recommended: exact
+ *               counts, vertices within the FP32 rounding of the FP64 result,
+ *               and the fastest of the two modes that are).
+ * Join and cap ribs take an FP32 direction in every mode (their vertices lie
+ * within r sqrt 2 of an exact pivot point); the arc length is FP64 chords
+ * summed in 64-bit fixed point. */
 enum { PS_PREC_FP32 = 0, PS_PREC_FP32_FIXUP = 1, PS_PREC_FP64 = 2 };
 
 enum {
@@ -115,15 +121,14 @@ typedef struct {
 } ps_batch;
 
 /* Emit mappings (how ribs are spread over wavefronts; the output bits do not
- * depend on it):
+ * depend on it).  Both run persistent wavefronts over tiles of 64*K
+ * consecutive ribs, K = emit_ribs_per_lane in {4, 6, 7, 8, 16}:
  *   PS_MAP_DEFAULT  unplanned calls: PS_MAP_TILES with K = 7, 4 wavefronts;
  *                   ps_plan_create: the fastest mapping on the batch, timed
- *   PS_MAP_TILES    persistent wavefronts over tiles of 64*K consecutive ribs,
- *                   each tile's segment ribs and join/cap ribs swept apart,
- *                   K = emit_ribs_per_lane in {4, 6, 7, 8, 16}
- *   PS_MAP_LINKS    persistent wavefronts over groups of consecutive links,
- *                   one link at a time: all 64 lanes take ribs of the same
- *                   link, whose data the wavefront holds once */
+ *   PS_MAP_TILES    each tile's links staged in LDS, its segment ribs and
+ *                   join/cap ribs swept apart, 64 at a time
+ *   PS_MAP_LINKS    each tile walked link by link: all 64 lanes take ribs of
+ *                   the same link, whose record the wavefront holds once */
 enum { PS_MAP_DEFAULT = 0, PS_MAP_TILES = 1, PS_MAP_LINKS = 2 };
 
 /*
@@ -134,9 +139,9 @@ enum { PS_MAP_DEFAULT = 0, PS_MAP_TILES = 1, PS_MAP_LINKS = 2 };
  * dash_phase >= 0 at arc length 0 of every path (at most 2^40 periods);
  * n_dash = 0 disables it.  miter_limit >= 1 bounds the miter ratio of the
  * miter joins (4 is the usual default of path-rendering standards).
- * emit_mapping is PS_MAP_*; emit_ribs_per_lane (K of PS_MAP_TILES) and
- * emit_waves (wavefronts per workgroup, 1..4) choose its shape, 0 for the
- * default.  These only affect speed.
+ * emit_mapping is PS_MAP_*; emit_ribs_per_lane (K) and emit_waves
+ * (wavefronts per workgroup, 1..4) choose its shape, 0 for the default.
+ * These only affect speed.
  */
 typedef struct {
   double q;
@@ -355,8 +360,8 @@ int ps_plan_create(const ps_batch* batch, const ps_params* params, int32_t* link
 int ps_plan_launch(ps_plan* plan, void* stream);
 int ps_plan_launch_timed(ps_plan* plan, void* stream, void* emit_begin, void* emit_end);
 int ps_plan_destroy(ps_plan* plan);
-/* The emit mapping a plan runs: PS_MAP_TILES or PS_MAP_LINKS, K (0 for
- * PS_MAP_LINKS) and wavefronts per workgroup. */
+/* The emit mapping a plan runs: PS_MAP_TILES or PS_MAP_LINKS, K and
+ * wavefronts per workgroup. */
 int ps_plan_config(const ps_plan* plan, int32_t* mapping, int32_t* ribs_per_lane,
                    int32_t* waves_per_group);
 
