@@ -28,23 +28,40 @@ constexpr int kMaxIv = 5;              // intervals per segment (collinear: 3 fl
 enum Role : uint8_t { ROLE_SEG = 0, ROLE_JOIN = 1, ROLE_SCAP = 2, ROLE_ECAP = 3, ROLE_EMPTY = 255 };
 
 // Per-link record, written by the count kernel and read by emit: everything
-// a rib of the link needs, so the emit kernel stages it in LDS with one load.
+// a rib of the link needs, as the emit kernels hold it (in LDS or registers).
+// In memory it is kept in two parts, so that most links cost 64 bytes to
+// write and to read instead of 144: a head that every link has (header,
+// control points or pivot, the first two angles: the 16-byte pieces 0, 2, 3
+// and 4 of the record) and a tail (pieces 1, 5, 6, 7, 8: the further interval
+// ends, angles and parameters of a segment with several intervals, a miter
+// join's normals) that only links flagged kHasTail have.  A reader without
+// the tail takes dsum[1..4] = INT_MAX and never reads psi[2..5] or p.
 struct alignas(16) LinkRec {
   uint8_t role;           // Role
   uint8_t n_iv;           // intervals (segments); 1 for pivots
   uint8_t kind;           // segment form (segments)
-  uint8_t flags;          // kFirstInPath, kFirstSegInPath; bits 4..7: cap style
+  uint8_t flags;          // kFirstInPath, kFirstSegInPath, kHasTail; bits 4..7: cap or join style
   float r;                // half the stroke width
-  int32_t dsum[kMaxIv];   // cumulative steps Delta_Sigma(1..n_iv); pivots: dsum[0] = J
   float w;                // conic weight (conics)
+  int32_t dsum[kMaxIv];   // cumulative steps Delta_Sigma(1..n_iv), INT_MAX past the last; pivots: dsum[0] = J
   float x[4], y[4];       // control points (segments); x[0], y[0]: pivot (joins, caps)
-  double p[kMaxIv - 1];   // interior interval boundaries p_1..p_{n_iv-1}
   double psi[kMaxIv + 1]; // unwrapped Psi_0..Psi_{n_iv}; pivots psi[0], psi[1] = psi[0] + delta
+  double p[kMaxIv - 1];   // interior interval boundaries p_1..p_{n_iv-1}; miter joins: unit normals
 };
 static_assert(sizeof(LinkRec) == 144, "LinkRec must stay 144 bytes");
+static_assert(__builtin_offsetof(LinkRec, dsum) == 12 && __builtin_offsetof(LinkRec, x) == 32 &&
+                  __builtin_offsetof(LinkRec, psi) == 64 && __builtin_offsetof(LinkRec, p) == 112,
+              "the head and tail pieces of LinkRec assume this layout");
+
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+constexpr int kRecPieces = 9, kHeadPieces = 4, kTailPieces = 5;
+// the record piece held by head piece k, and by tail piece k
+__host__ __device__ constexpr int head_piece(int k) { return k == 0 ? 0 : k + 1; }
+__host__ __device__ constexpr int tail_piece(int k) { return k == 0 ? 1 : k + 4; }
 
 constexpr uint8_t kFirstInPath = 1;     // first link with ribs of its path
 constexpr uint8_t kFirstSegInPath = 2;  // first segment with ribs of its path
+constexpr uint8_t kHasTail = 4;         // the link's record has a tail
 
 // Device status word kept at the start of the workspace.
 struct DevStatus {

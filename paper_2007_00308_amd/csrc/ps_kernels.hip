@@ -47,7 +47,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Workspace
 // ===========================================================================
 struct WsLayout {
-  size_t status, rec, seg_ang, seg_ok, scan, tile_link, desc, dash_r, dash_d, dash_rpos, dash_dpos,
+  size_t status, rec_head, rec_tail, seg_ang, seg_ok, scan, tile_link, desc, dash_r, dash_d, dash_rpos, dash_dpos,
       dash_scan, total;
   int64_t max_tiles, n_links, max_ribs, nb_links, nb_ribs;
 };
@@ -64,7 +64,8 @@ WsLayout ws_layout(int64_t n_links, int64_t vertex_capacity, int n_dash) {
   w.nb_ribs = (w.max_ribs + kScanTile - 1) / kScanTile + 1;
   size_t o = 0;
   w.status = o; o = align_up(o + 256, 256);
-  w.rec = o; o = align_up(o + (size_t)n_links * sizeof(LinkRec), 256);
+  w.rec_head = o; o = align_up(o + (size_t)n_links * kHeadPieces * 16, 256);
+  w.rec_tail = o; o = align_up(o + (size_t)n_links * kTailPieces * 16, 256);
   w.seg_ang = o; o = align_up(o + (size_t)n_links * 16, 256);   // n_links >= n_segs
   w.seg_ok = o; o = align_up(o + (size_t)n_links, 256);
   w.scan = o; o = align_up(o + (size_t)(w.nb_links + 1) * 8, 256);
@@ -89,7 +90,8 @@ struct CountArgs {
   ps_batch B;
   double q;
   int32_t* link_ribs;
-  LinkRec* rec;
+  v4u32* head;   // record heads, kHeadPieces per link slot
+  v4u32* tail;   // record tails, kTailPieces per link slot
   double2* seg_ang;
   uint8_t* seg_ok;
   DevStatus* st;
@@ -277,9 +279,10 @@ __device__ int segment_setup(const ps_batch& B, int i, F q, F psi_start, F psi_e
 }
 
 // The parameter of each split interval of segment i: the solve (in F) at its
-// middle angle, stored into the record already written at *out.
+// middle angle, stored into the interval boundaries p_1..p_4 (at pt) of the
+// record already written.
 template <typename F>
-__device__ void finish_splits(const ps_batch& B, int i, const SplitSolves<F>& sp, LinkRec* out) {
+__device__ void finish_splits(const ps_batch& B, int i, const SplitSolves<F>& sp, double* pt) {
   const SegT<F> s = load_seg<F>(B, i);
   float X[4], Y[4];
   const int64_t S = B.n_segs;
@@ -294,7 +297,7 @@ __device__ void finish_splits(const ps_batch& B, int i, const SplitSolves<F>& sp
     if constexpr (sizeof(F) == 8) sincos(m ? sp.psi1 : sp.psi0, &sn, &cs);
     else sincosf(m ? sp.psi1 : sp.psi0, &sn, &cs);
     const SolveOut<F> so = solve_t<F>(h, -sn, cs, cs, sn, m ? sp.lo1 : sp.lo0, m ? sp.hi1 : sp.hi0);
-    out->p[m ? sp.idx1 : sp.idx0] = (double)so.t;
+    pt[m ? sp.idx1 : sp.idx0] = (double)so.t;
   }
 }
 
@@ -362,11 +365,9 @@ __device__ inline void clear_rec(LinkRec& r) {
 }
 
 // A pivot link (join or cap) with J steps from psi0 through psi1 = psi0 + delta;
-// `cap` is the cap style of a cap and the join style of a join.  Records are
-// built in registers and stored whole (nine 16-byte stores).
-__device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slot, uint8_t role,
-                                   double psi0, double psi1, int J, float px, float py,
-                                   uint8_t cap, float half_w, bool first) {
+// `cap` is the cap style of a cap and the join style of a join.
+__device__ inline LinkRec make_pivot(uint8_t role, double psi0, double psi1, int J, float px, float py,
+                                     uint8_t cap, float half_w, bool first) {
   LinkRec r;
   clear_rec(r);
   r.role = J > 0 ? role : (uint8_t)ROLE_EMPTY;
@@ -375,88 +376,125 @@ __device__ inline void write_pivot(LinkRec* rec, int32_t* link_ribs, int64_t slo
   r.r = half_w;
   r.dsum[0] = J; r.psi[0] = psi0; r.psi[1] = psi1;
   r.x[0] = px; r.y[0] = py;
-  if (role == ROLE_JOIN && (cap == PS_JOIN_MITER || cap == PS_JOIN_MITER_CLIP)) {
+  if (J > 0 && role == ROLE_JOIN && (cap == PS_JOIN_MITER || cap == PS_JOIN_MITER_CLIP)) {
     // unit normals n = (-sin, cos) at both ends, for the miter vertices
     double s0, c0, s1, c1;
     sincos(psi0, &s0, &c0);
     sincos(psi1, &s1, &c1);
     r.p[0] = -s0; r.p[1] = c0; r.p[2] = -s1; r.p[3] = c1;
+    r.flags |= kHasTail;
   }
-  rec[slot] = r;
-  link_ribs[slot] = J > 0 ? J + 1 : 0;
+  return r;
 }
 
-// Second count pass, one thread per segment and then one per path.  A
-// segment's thread writes its record and step count (Eqs. p-value, Psi,
-// continuous-delta, Delta_i) and the join or end cap after it; a path's
-// thread writes its start cap.  Link slots: path p's start cap at 2 b + p,
-// segment i at 2 i + p + 1, the link after it at 2 i + p + 2 (b: the path's
-// first segment).
-template <typename F>
-__global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
-  const ps_batch& B = A.B;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int S = B.n_segs, P = B.n_paths;
-  if (tid < A.scan_nb) A.scan_desc[tid] = 0ull;   // scan_nb <= S + P threads
-  // The workgroup's segments are handed to its threads grouped by form
-  // (unusable, line, quadratic, conic, cubic), so that a wavefront mostly
-  // runs one form's setup instead of all of them one after another.  Which
-  // thread takes a segment changes nothing in what is written.
-  __shared__ int form_count[8];
-  __shared__ int form_order[256];
-  const int i0 = (int)blockIdx.x * 256;
-  const int nseg = S - i0 < 256 ? S - i0 : 256;   // <= 0 in the path workgroups
-  int seg = -1;
-  if (nseg > 0) {
-    if (threadIdx.x < 8) form_count[threadIdx.x] = 0;
-    __syncthreads();
-    int form = -1, rank = 0;
-    if ((int)threadIdx.x < nseg) {
-      const int k = B.kind[i0 + threadIdx.x];
-      form = !(A.seg_ok[i0 + threadIdx.x] & kSegUsable) ? 0
-           : (k == PS_KIND_CUBIC ? 4 : (k == PS_KIND_CONIC ? 3 : (k == PS_KIND_QUAD ? 2 : 1)));
-      rank = atomicAdd(&form_count[form], 1);
-    }
-    __syncthreads();
-    if (form >= 0) {
-      int at = rank;
-      for (int f = 0; f < form; ++f) at += form_count[f];
-      form_order[at] = (int)threadIdx.x;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nseg) seg = i0 + form_order[threadIdx.x];
+// The record heads of a count workgroup's link slots are gathered in LDS and
+// written to memory with consecutive lanes on consecutive 16-byte pieces (a
+// thread's own records lie 144 bytes apart or more, so storing them from the
+// thread that built them costs a memory request per 16 bytes).  Stage
+// position 0 is link slot sb = 2 i0 + p0 (i0: the workgroup's first segment,
+// p0 its path); the workgroup's links come after it, with the start caps of
+// any paths without segments in between, which the path threads write.  A
+// slot past the stage is written directly.
+constexpr int kCountThreads = 256;
+constexpr int kStageSlots = 576;   // 2 x 256 segment and pivot links, and up to 64 start caps (36 KB)
+
+struct HeadStage {
+  v4u32* lds;        // kStageSlots x kHeadPieces
+  unsigned* valid;   // a bit per stage slot: written by this workgroup
+  int64_t sb;
+};
+
+// Record r of link slot `slot` with `ribs` ribs: its head into the stage (or
+// to memory), its tail (if it has one) and its rib count to memory.
+__device__ __forceinline__ void put_rec(const CountArgs& A, const HeadStage& hs, int64_t slot,
+                                        const LinkRec& r, int ribs) {
+  v4u32 pc[kRecPieces];
+  __builtin_memcpy(pc, &r, sizeof(LinkRec));
+  const int64_t rel = slot - hs.sb;
+  if (rel >= 0 && rel < kStageSlots) {
+#pragma unroll
+    for (int k = 0; k < kHeadPieces; ++k) hs.lds[rel * kHeadPieces + k] = pc[head_piece(k)];
+    atomicOr(&hs.valid[rel >> 5], 1u << (rel & 31));
+  } else {
+    v4u32* h = A.head + slot * kHeadPieces;
+#pragma unroll
+    for (int k = 0; k < kHeadPieces; ++k) h[k] = pc[head_piece(k)];
   }
-  if (seg >= 0) {
-    const int i = seg;
-    const uint8_t state = A.seg_ok[i];
-    if (state & kSegBadValue) set_flag(A.st, PS_STATUS_BAD_VALUE);
-    if (state & kSegNonFinite) set_flag(A.st, PS_STATUS_NONFINITE);
-    const bool ok_i = state & kSegUsable;
-    const double2 ang = A.seg_ang[i];   // F values
-    const int p = path_of_seg(B.seg_begin, P, i);
-    const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
-    const int64_t slot = 2 * (int64_t)i + p + 1;
-    const float wd = B.width[p];
-    const bool wok = isfinite(wd) && wd > 0;
-    const bool sok = (B.join[p] <= PS_JOIN_MITER_CLIP) && (B.cap[p] <= PS_CAP_TRIANGLE);
-    const bool closed = B.closed && B.closed[p];
-    if (!isfinite(wd)) set_flag(A.st, PS_STATUS_NONFINITE);
-    else if (!wok || !sok) set_flag(A.st, PS_STATUS_BAD_VALUE);
-    const bool usable = wok && sok && ok_i;
-    const float half_w = 0.5f * wd;
+  if (r.flags & kHasTail) {
+    v4u32* t = A.tail + slot * kTailPieces;
+#pragma unroll
+    for (int k = 0; k < kTailPieces; ++k) t[k] = pc[tail_piece(k)];
+  }
+  A.link_ribs[slot] = ribs;
+}
+
+// p_1..p_4 of the tail of link slot `slot`
+__device__ __forceinline__ double* tail_p(const CountArgs& A, int64_t slot) {
+  return reinterpret_cast<double*>(A.tail + slot * kTailPieces + 3);
+}
+
+// The start cap of path p (segments b..e-1, b < e): from the reversed start
+// tangent of its first usable segment, +pi round to it; none on a closed
+// contour, a path of bad width or style, or one without usable segments.
+template <typename F>
+__device__ LinkRec start_cap(const CountArgs& A, int p, int b, int e, int& ribs) {
+  const ps_batch& B = A.B;
+  const float wd = B.width[p];
+  const bool ok = isfinite(wd) && wd > 0 && B.cap[p] <= PS_CAP_TRIANGLE && B.join[p] <= PS_JOIN_MITER_CLIP;
+  ribs = 0;
+  if (ok && !(B.closed && B.closed[p])) {
+    for (int k = b; k < e; ++k) {
+      if (!(A.seg_ok[k] & kSegUsable)) continue;
+      const F q = (F)A.q;
+      const int J = cap_steps<F>(B.cap[p], q);
+      const F c0 = (F)A.seg_ang[k].x - (F)kPi;
+      ribs = J > 0 ? J + 1 : 0;
+      return make_pivot(ROLE_SCAP, c0, c0 + (F)kPi, J, B.cx[k], B.cy[k], B.cap[p], 0.5f * wd, true);
+    }
+  }
+  return make_pivot(ROLE_SCAP, 0, 0, 0, 0, 0, 0, 0.5f * wd, false);
+}
+
+// The links of segment i: its own record and step count (Eqs. p-value, Psi,
+// continuous-delta, Delta_i), the join or end cap after it, and the start cap
+// of its path when it is the path's first segment.  Link slots: path p's
+// start cap at 2 b + p, segment i at 2 i + p + 1, the link after it at
+// 2 i + p + 2 (b: the path's first segment).
+template <typename F>
+__device__ void count_segment(const CountArgs& A, const HeadStage& hs, int i) {
+  const ps_batch& B = A.B;
+  const int S = B.n_segs, P = B.n_paths;
+  const uint8_t state = A.seg_ok[i];
+  if (state & kSegBadValue) set_flag(A.st, PS_STATUS_BAD_VALUE);
+  if (state & kSegNonFinite) set_flag(A.st, PS_STATUS_NONFINITE);
+  const bool ok_i = state & kSegUsable;
+  const double2 ang = A.seg_ang[i];   // F values
+  const int p = path_of_seg(B.seg_begin, P, i);
+  const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
+  const int64_t slot = 2 * (int64_t)i + p + 1;
+  const float wd = B.width[p];
+  const bool wok = isfinite(wd) && wd > 0;
+  const bool sok = (B.join[p] <= PS_JOIN_MITER_CLIP) && (B.cap[p] <= PS_CAP_TRIANGLE);
+  const bool closed = B.closed && B.closed[p];
+  if (!isfinite(wd)) set_flag(A.st, PS_STATUS_NONFINITE);
+  else if (!wok || !sok) set_flag(A.st, PS_STATUS_BAD_VALUE);
+  const bool usable = wok && sok && ok_i;
+  const float half_w = 0.5f * wd;
+  const F q = (F)A.q;
+  const F psi_e = (F)ang.y;
+  {
     LinkRec r;
     clear_rec(r);
     r.kind = B.kind[i];
     r.r = half_w;
     int ribs = 0;
-    const F q = (F)A.q;
-    const F psi_e = (F)ang.y;
     SplitSolves<F> sp;
     if (usable) {
       const int N = segment_setup<F>(B, i, q, (F)ang.x, psi_e, r, sp, A.st);
       if (N > 0) {
         ribs = N + 1;
         r.role = ROLE_SEG;
+        if (r.n_iv > 1) r.flags |= kHasTail;
         const int npts = npts_of(r.kind);
         for (int k = 0; k < 4; ++k) {
           const int kk = k < npts ? k : npts - 1;
@@ -472,15 +510,19 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
         if (first_seg && (closed || cap_steps<F>(B.cap[p], q) == 0)) r.flags |= kFirstInPath;
       }
     }
-    A.rec[slot] = r;
-    A.link_ribs[slot] = ribs;
-    if (sp.n > 0 && ribs > 0) finish_splits<F>(B, i, sp, A.rec + slot);
-    // the join after this segment, or the end cap
-    const int64_t jslot = slot + 1;
-    if (!usable) {
-      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, 0, 0, 0, 0, 0, 0, half_w, false);
-      return;
-    }
+    put_rec(A, hs, slot, r, ribs);
+    if (sp.n > 0 && ribs > 0) finish_splits<F>(B, i, sp, tail_p(A, slot));
+  }
+  if (i == b) {
+    int ribs;
+    const LinkRec c = start_cap<F>(A, p, b, e, ribs);
+    put_rec(A, hs, slot - 1, c, ribs);
+  }
+  // the join after this segment, or the end cap
+  const int64_t jslot = slot + 1;
+  LinkRec pv;
+  int J = 0;
+  if (usable) {
     const int n = npts_of(B.kind[i]);
     const float ex = B.cx[(int64_t)(n - 1) * S + i], ey = B.cy[(int64_t)(n - 1) * S + i];
     // the next usable segment; after the last one a closed contour joins
@@ -493,35 +535,83 @@ __global__ void __launch_bounds__(256) count_kernel(CountArgs A) {
     if (next >= 0) {
       F d = adiff((F)A.seg_ang[next].x, psi_e);
       if (d == -(F)kPi) d = (F)kPi;   // antiparallel: turn +pi
-      const int J = join_steps<F>(B.join[p], d, q);
-      write_pivot(A.rec, A.link_ribs, jslot, ROLE_JOIN, psi_e, psi_e + d, J, ex, ey, B.join[p], half_w, false);
-      return;
+      J = join_steps<F>(B.join[p], d, q);
+      pv = make_pivot(ROLE_JOIN, psi_e, psi_e + d, J, ex, ey, B.join[p], half_w, false);
+    } else {
+      J = cap_steps<F>(B.cap[p], q);
+      pv = make_pivot(ROLE_ECAP, psi_e, psi_e - (F)kPi, J, ex, ey, B.cap[p], half_w, false);
     }
-    const int J = cap_steps<F>(B.cap[p], q);
-    write_pivot(A.rec, A.link_ribs, jslot, ROLE_ECAP, psi_e, psi_e - (F)kPi, J, ex, ey, B.cap[p], half_w, false);
-    return;
+  } else {
+    pv = make_pivot(ROLE_JOIN, 0, 0, 0, 0, 0, 0, half_w, false);
   }
-  if (tid < (int64_t)S + P) {
-    const int p = (int)(tid - S);
-    const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
-    const int64_t slot = 2 * (int64_t)b + p;
-    const float wd = B.width[p];
-    const bool ok = isfinite(wd) && wd > 0 && B.cap[p] <= PS_CAP_TRIANGLE &&
-                    B.join[p] <= PS_JOIN_MITER_CLIP;
-    if (ok && !(B.closed && B.closed[p])) {   // a closed contour has no caps
-      for (int k = b; k < e; ++k) {
-        if (!(A.seg_ok[k] & kSegUsable)) continue;
-        const F psi_s = (F)A.seg_ang[k].x;
-        const F q = (F)A.q;
-        const int J = cap_steps<F>(B.cap[p], q);
-        // start cap: from the reversed start tangent, +pi round to it
-        const F c0 = psi_s - (F)kPi;
-        write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, c0, c0 + (F)kPi, J, B.cx[k], B.cy[k],
-                    B.cap[p], 0.5f * wd, true);
-        return;
+  put_rec(A, hs, jslot, pv, J > 0 ? J + 1 : 0);
+}
+
+// Second count pass.  Workgroups of 256 segments (each thread writes the
+// links of one segment, count_segment), then workgroups of paths, whose
+// threads write the start cap of each path without segments.
+template <typename F>
+__global__ void __launch_bounds__(kCountThreads) count_kernel(CountArgs A) {
+  const ps_batch& B = A.B;
+  const int64_t tid = (int64_t)blockIdx.x * kCountThreads + threadIdx.x;
+  const int S = B.n_segs, P = B.n_paths;
+  if (tid < A.scan_nb) A.scan_desc[tid] = 0ull;   // scan_nb <= S + P threads
+  const int seg_blocks = (S + kCountThreads - 1) / kCountThreads;
+  if ((int)blockIdx.x >= seg_blocks) {
+    const int64_t pt = tid - (int64_t)seg_blocks * kCountThreads;
+    if (pt < P) {
+      const int p = (int)pt;
+      const int b = B.seg_begin[p];
+      if (b == B.seg_begin[p + 1]) {
+        const LinkRec c = make_pivot(ROLE_SCAP, 0, 0, 0, 0, 0, 0, 0.5f * B.width[p], false);
+        v4u32 pc[kRecPieces];
+        __builtin_memcpy(pc, &c, sizeof(LinkRec));
+        const int64_t slot = 2 * (int64_t)b + p;
+        for (int k = 0; k < kHeadPieces; ++k) A.head[slot * kHeadPieces + k] = pc[head_piece(k)];
+        A.link_ribs[slot] = 0;
       }
     }
-    write_pivot(A.rec, A.link_ribs, slot, ROLE_SCAP, 0, 0, 0, 0, 0, 0, 0.5f * wd, false);
+    return;
+  }
+  __shared__ v4u32 stage[kStageSlots * kHeadPieces];
+  __shared__ unsigned stage_valid[kStageSlots / 32];
+  __shared__ int stage_p0;
+  // The workgroup's segments are handed to its threads grouped by form
+  // (unusable, line, quadratic, conic, cubic), so that a wavefront mostly
+  // runs one form's setup instead of all of them one after another.  Which
+  // thread takes a segment changes nothing in what is written.
+  __shared__ int form_count[8];
+  __shared__ int form_order[kCountThreads];
+  const int i0 = (int)blockIdx.x * kCountThreads;
+  const int nseg = S - i0 < kCountThreads ? S - i0 : kCountThreads;
+  if (threadIdx.x < 8) form_count[threadIdx.x] = 0;
+  if (threadIdx.x < kStageSlots / 32) stage_valid[threadIdx.x] = 0;
+  if (threadIdx.x == 0) stage_p0 = path_of_seg(B.seg_begin, P, i0);
+  __syncthreads();
+  int form = -1, rank = 0;
+  if ((int)threadIdx.x < nseg) {
+    const int k = B.kind[i0 + threadIdx.x];
+    form = !(A.seg_ok[i0 + threadIdx.x] & kSegUsable) ? 0
+         : (k == PS_KIND_CUBIC ? 4 : (k == PS_KIND_CONIC ? 3 : (k == PS_KIND_QUAD ? 2 : 1)));
+    rank = atomicAdd(&form_count[form], 1);
+  }
+  __syncthreads();
+  if (form >= 0) {
+    int at = rank;
+    for (int f = 0; f < form; ++f) at += form_count[f];
+    form_order[at] = (int)threadIdx.x;
+  }
+  __syncthreads();
+  HeadStage hs;
+  hs.lds = stage;
+  hs.valid = stage_valid;
+  hs.sb = 2 * (int64_t)i0 + stage_p0;
+  if ((int)threadIdx.x < nseg) count_segment<F>(A, hs, i0 + form_order[threadIdx.x]);
+  __syncthreads();
+  v4u32* const out = A.head + hs.sb * kHeadPieces;
+  for (int c = threadIdx.x; c < kStageSlots * kHeadPieces; c += kCountThreads) {
+    const int rel = c / kHeadPieces;
+    if (stage_valid[rel >> 5] & (1u << (rel & 31))) out[c] = stage[c];
   }
 }
 
@@ -857,7 +947,8 @@ __global__ void __launch_bounds__(kLinkScanThreads) link_scan_kernel(LinkScanArg
 // Emit (Eqs. func_t, func_N, RibVertices-N/P, arc-length-approximation)
 // ===========================================================================
 struct EmitArgs {
-  const LinkRec* rec;
+  const v4u32* head;   // record heads and tails (LinkRec)
+  const v4u32* tail;
   const int64_t* off;
   int64_t n_links;
   float* vx;
@@ -1339,6 +1430,21 @@ struct TileRounds {
 // Arc length is accumulated in 64-bit fixed point (2^-32 px per unit): each
 // chord is rounded once and every sum after that is an integer sum, so s does
 // not depend on the tiling, the mapping or the order tiles finish in.
+// Records of n (<= 12) consecutive link slots into LDS: the heads, then the
+// tails of the links that have one (their flags are in the heads just
+// written; a wavefront's LDS accesses complete in order), or INT_MAX for
+// dsum[1..4] of the others.
+__device__ __forceinline__ void stage_recs(const v4u32* head, const v4u32* tail, int n, LinkRec* rec,
+                                           int lane) {
+  v4u32* dst = reinterpret_cast<v4u32*>(rec);
+  if (lane < n * kHeadPieces) dst[(lane >> 2) * kRecPieces + head_piece(lane & 3)] = head[lane];
+  if (lane < n * kTailPieces) {
+    const int i = lane / kTailPieces, k = lane - kTailPieces * i;
+    if (rec[i].flags & kHasTail) dst[i * kRecPieces + tail_piece(k)] = tail[lane];
+    else if (k == 0) dst[i * kRecPieces + 1] = (v4u32){INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+  }
+}
+
 constexpr int kWin = 12;
 struct SplitLDS {
   long long off[kWin + 1];
@@ -1474,9 +1580,7 @@ emit_split_kernel(EmitArgs A) {
           // offsets do not decrease) have ribs in it; the others keep stale
           // records, which nothing reads
           const int n_rec = __popcll(__ballot(lane < kWin && idx < L && o_i < r1));
-          const int4* src = reinterpret_cast<const int4*>(A.rec + base);
-          int4* dst = reinterpret_cast<int4*>(w.rec);
-          for (int c = lane; c < n_rec * (int)(sizeof(LinkRec) / 16); c += 64) dst[c] = src[c];
+          stage_recs(A.head + base * kHeadPieces, A.tail + base * kTailPieces, n_rec, w.rec, lane);
         }
         // ---- each slot's ribs inside the tile; the link holding r0 also
         // gives rib r0 - 1 when it is a segment begun earlier (first chord)
@@ -1663,6 +1767,30 @@ __device__ __forceinline__ T load_uniform(const T* p) {
   return v;
 }
 
+// Record of link l as scalar loads (l wave-uniform): the head, then the tail
+// when the head's flags say it has one.
+__device__ __forceinline__ LinkRec load_rec_uniform(const v4u32* head, const v4u32* tail, int64_t l) {
+  typedef __attribute__((address_space(4))) const unsigned int* CU32;
+  unsigned int w[kRecPieces * 4];
+  const CU32 h = (CU32)(head + l * kHeadPieces);
+#pragma unroll
+  for (int k = 0; k < kHeadPieces; ++k)
+    for (int d = 0; d < 4; ++d) w[head_piece(k) * 4 + d] = h[k * 4 + d];
+  if ((w[0] >> 24) & kHasTail) {
+    const CU32 t = (CU32)(tail + l * kTailPieces);
+#pragma unroll
+    for (int k = 0; k < kTailPieces; ++k)
+      for (int d = 0; d < 4; ++d) w[tail_piece(k) * 4 + d] = t[k * 4 + d];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kTailPieces; ++k)
+      for (int d = 0; d < 4; ++d) w[tail_piece(k) * 4 + d] = k == 0 ? (unsigned)INT_MAX : 0u;
+  }
+  LinkRec r;
+  __builtin_memcpy(&r, w, sizeof(LinkRec));
+  return r;
+}
+
 __host__ __device__ constexpr size_t emit_links_lds_per_wave(int K, bool ws) {
   return ws ? 2 * (size_t)K * 64 * sizeof(long long) : 16;
 }
@@ -1741,7 +1869,7 @@ emit_links_kernel(EmitArgs A) {
         const long long a = load_uniform(A.off + l), b = load_uniform(A.off + l + 1);
         if (a >= r1) break;
         if (b <= r0 || b == a) continue;   // no rib in the tile
-        const LinkRec rp = load_uniform(A.rec + l);
+        const LinkRec rp = load_rec_uniform(A.head, A.tail, l);
         if (rp.role == ROLE_SEG) {
           // a segment begun in an earlier tile also gives rib r0 - 1, the
           // first chord's other end
@@ -1826,7 +1954,8 @@ emit_links_kernel(EmitArgs A) {
 // Parametric Tessellation")
 // ===========================================================================
 struct UniformArgs {
-  const LinkRec* rec;
+  const v4u32* head;
+  const v4u32* tail;
   const int64_t* off;
   int64_t n_links;
   float* vx;
@@ -1858,7 +1987,19 @@ __global__ void __launch_bounds__(256) uniform_emit_kernel(UniformArgs A) {
        r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = rib_link(A.off, A.n_links, r);
     const int j = (int)(r - A.off[l]);
-    const LinkRec& rp = A.rec[l];
+    LinkRec rp;
+    {
+      // the record of link l: its head, and its tail or INT_MAX for dsum[1..4]
+      v4u32 pc[kRecPieces];
+      const bool tl = (A.head[l * kHeadPieces][0] >> 24) & kHasTail;
+#pragma unroll
+      for (int k = 0; k < kHeadPieces; ++k) pc[head_piece(k)] = A.head[l * kHeadPieces + k];
+#pragma unroll
+      for (int k = 0; k < kTailPieces; ++k)
+        pc[tail_piece(k)] = tl ? A.tail[l * kTailPieces + k]
+                               : (k == 0 ? (v4u32){INT_MAX, INT_MAX, INT_MAX, INT_MAX} : (v4u32){0, 0, 0, 0});
+      __builtin_memcpy(&rp, pc, sizeof(LinkRec));
+    }
     float2 ox, oy;
     if (rp.role != ROLE_SEG) {
       RibOut o;
@@ -2561,7 +2702,8 @@ int check_ws(const void* ws, size_t have, size_t need) {
 
 struct WsView {
   DevStatus* st;
-  LinkRec* rec;
+  v4u32* head;
+  v4u32* tail;
   double2* seg_ang;   // per segment: start and end tangent angles (usable segments)
   uint8_t* seg_ok;    // per segment: state (usable, or the status bit its problem raises)
   long long* scan;
@@ -2578,7 +2720,8 @@ WsView ws_view(void* ws, const WsLayout& w) {
   char* b = (char*)ws;
   WsView v;
   v.st = (DevStatus*)(b + w.status);
-  v.rec = (LinkRec*)(b + w.rec);
+  v.head = (v4u32*)(b + w.rec_head);
+  v.tail = (v4u32*)(b + w.rec_tail);
   v.seg_ang = (double2*)(b + w.seg_ang);
   v.seg_ok = (uint8_t*)(b + w.seg_ok);
   v.scan = (long long*)(b + w.scan);
@@ -2715,15 +2858,18 @@ int launch_count(const ps_batch* b, const ps_params* p, int32_t* link_ribs, cons
   if (b->n_segs == 0) hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, v.st);
   const int64_t n = (int64_t)b->n_segs + b->n_paths;
   if (n > 0) {
-    CountArgs a{*b, p->q, link_ribs, v.rec, v.seg_ang, v.seg_ok, v.st, (unsigned long long*)v.scan,
+    CountArgs a{*b, p->q, link_ribs, v.head, v.tail, v.seg_ang, v.seg_ok, v.st, (unsigned long long*)v.scan,
                 link_scan_blocks(n_links_of(b))};
     // the setup in FP64, or in FP32 for the single-precision study mode
     const bool f32 = p->precision == PS_PREC_FP32;
     if (b->n_segs > 0)
       hipLaunchKernelGGL(f32 ? count_angles_kernel<float> : count_angles_kernel<double>,
                          dim3((unsigned)((b->n_segs + 255) / 256)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(f32 ? count_kernel<float> : count_kernel<double>, dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, s, a);
+    // workgroups of segments, then of paths (launch bound kCountThreads)
+    const int64_t blocks = ((int64_t)b->n_segs + kCountThreads - 1) / kCountThreads +
+                           ((int64_t)b->n_paths + kCountThreads - 1) / kCountThreads;
+    hipLaunchKernelGGL(f32 ? count_kernel<float> : count_kernel<double>, dim3((unsigned)blocks),
+                       dim3(kCountThreads), 0, s, a);
   }
   PS_HIP(hipGetLastError());
   return PS_OK;
@@ -2745,7 +2891,7 @@ int launch_emit(const ps_batch* b, const ps_params* p, const int64_t* off, float
                        v.desc, v.st, cap, w.max_tiles);
   }
   EmitArgs a;
-  a.rec = v.rec; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
+  a.head = v.head; a.tail = v.tail; a.off = off; a.n_links = L; a.vx = vx; a.vy = vy; a.vs = vs;
   a.capacity = cap; a.tile_link = v.tile_link; a.desc = v.desc; a.st = v.st;
   a.max_tiles = w.max_tiles;
   a.fix_tol = fixup_tolerance();
@@ -2994,7 +3140,7 @@ int ps_emit_uniform(const ps_batch* b, const ps_params* p, const int64_t* offset
   if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
   const WsView v = ws_view(ws, w);
   UniformArgs a;
-  a.rec = v.rec; a.off = offsets; a.n_links = n_links_of(b); a.vx = vx; a.vy = vy;
+  a.head = v.head; a.tail = v.tail; a.off = offsets; a.n_links = n_links_of(b); a.vx = vx; a.vy = vy;
   a.capacity = cap; a.miter_limit = p->miter_limit;
   if (a.n_links > 0)
     hipLaunchKernelGGL(uniform_emit_kernel, dim3(num_cus() * 8), dim3(256), 0,
