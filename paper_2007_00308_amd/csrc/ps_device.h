@@ -63,6 +63,10 @@ constexpr uint8_t kFirstInPath = 1;     // first link with ribs of its path
 constexpr uint8_t kFirstSegInPath = 2;  // first segment with ribs of its path
 constexpr uint8_t kHasTail = 4;         // the link's record has a tail
 
+// A segment of two or three intervals needs only tail pieces 0, 1 and 3
+// (dsum[1..4], psi[2..3], p[0..1]); a longer one, or a miter join, all five.
+__host__ __device__ inline bool tail_whole(const LinkRec& r) { return r.n_iv > 3 || r.role != ROLE_SEG; }
+
 // Device status word kept at the start of the workspace.
 struct DevStatus {
   unsigned int flags;

@@ -400,12 +400,13 @@ constexpr int kStageSlots = 576;   // 2 x 256 segment and pivot links, and up to
 
 struct HeadStage {
   v4u32* lds;        // kStageSlots x kHeadPieces
+  int* ribs;         // kStageSlots rib counts
   unsigned* valid;   // a bit per stage slot: written by this workgroup
   int64_t sb;
 };
 
-// Record r of link slot `slot` with `ribs` ribs: its head into the stage (or
-// to memory), its tail (if it has one) and its rib count to memory.
+// Record r of link slot `slot` with `ribs` ribs: its head and rib count into
+// the stage (or to memory), its tail (if it has one) to memory.
 __device__ __forceinline__ void put_rec(const CountArgs& A, const HeadStage& hs, int64_t slot,
                                         const LinkRec& r, int ribs) {
   v4u32 pc[kRecPieces];
@@ -414,18 +415,19 @@ __device__ __forceinline__ void put_rec(const CountArgs& A, const HeadStage& hs,
   if (rel >= 0 && rel < kStageSlots) {
 #pragma unroll
     for (int k = 0; k < kHeadPieces; ++k) hs.lds[rel * kHeadPieces + k] = pc[head_piece(k)];
+    hs.ribs[rel] = ribs;
     atomicOr(&hs.valid[rel >> 5], 1u << (rel & 31));
   } else {
     v4u32* h = A.head + slot * kHeadPieces;
 #pragma unroll
     for (int k = 0; k < kHeadPieces; ++k) h[k] = pc[head_piece(k)];
+    A.link_ribs[slot] = ribs;
   }
   if (r.flags & kHasTail) {
     v4u32* t = A.tail + slot * kTailPieces;
-#pragma unroll
-    for (int k = 0; k < kTailPieces; ++k) t[k] = pc[tail_piece(k)];
+    t[0] = pc[tail_piece(0)]; t[1] = pc[tail_piece(1)]; t[3] = pc[tail_piece(3)];
+    if (tail_whole(r)) { t[2] = pc[tail_piece(2)]; t[4] = pc[tail_piece(4)]; }
   }
-  A.link_ribs[slot] = ribs;
 }
 
 // p_1..p_4 of the tail of link slot `slot`
@@ -574,6 +576,7 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(CountArgs A) {
     return;
   }
   __shared__ v4u32 stage[kStageSlots * kHeadPieces];
+  __shared__ int stage_ribs[kStageSlots];
   __shared__ unsigned stage_valid[kStageSlots / 32];
   __shared__ int stage_p0;
   // The workgroup's segments are handed to its threads grouped by form
@@ -604,6 +607,7 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(CountArgs A) {
   __syncthreads();
   HeadStage hs;
   hs.lds = stage;
+  hs.ribs = stage_ribs;
   hs.valid = stage_valid;
   hs.sb = 2 * (int64_t)i0 + stage_p0;
   if ((int)threadIdx.x < nseg) count_segment<F>(A, hs, i0 + form_order[threadIdx.x]);
@@ -613,6 +617,8 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(CountArgs A) {
     const int rel = c / kHeadPieces;
     if (stage_valid[rel >> 5] & (1u << (rel & 31))) out[c] = stage[c];
   }
+  for (int rel = threadIdx.x; rel < kStageSlots; rel += kCountThreads)
+    if (stage_valid[rel >> 5] & (1u << (rel & 31))) A.link_ribs[hs.sb + rel] = stage_ribs[rel];
 }
 
 // Scratch memory of ps_stroke_static: the workspace of one count -> scan ->
@@ -1330,14 +1336,22 @@ __device__ __forceinline__ void piv_rib(const LinkRec& rp, int j, double miter_l
   }
 }
 
-// round(x) to int64 for 0 <= x < 2^63 (ties to even, as llrint), with no
-// branch: the rounded value split at 2^32 (both parts exact in FP64) and each
-// half converted on its own.
-__device__ __forceinline__ long long fix_round(double x) {
-  const double xr = rint(x);
-  const double hi = trunc(xr * 0x1p-32);
-  const double lo = fma(-hi, 4294967296.0, xr);
-  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+// A chord |(dx, dy)| in FP32 (Eq. arc-length-approximation sums chords; they
+// are taken in FP32 and their sums kept exact), as a whole number of 2^-32 px:
+// dx and dy rounded to FP32, the hardware square root of dx^2 + dy^2 (each
+// step within an ulp, so the chord within 2^-22 of its length), then scaled by
+// 2^32.  A float of at least 2^-9 is already a whole number of units (its
+// last bit is worth 2^-32 or more): its significand shifted into place.  A
+// smaller one is rounded to the nearest unit in FP32, where the scaling is
+// exact and the result is below 2^23.
+__device__ __forceinline__ long long chord_fix(double dx, double dy) {
+  const float fx = (float)dx, fy = (float)dy;
+  const float c = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fy * fy));
+  const unsigned bits = __float_as_uint(c);
+  const int sh = (int)(bits >> 23) - 118;   // the exponent less 127 + 23 - 32
+  const unsigned long long m = (bits & 0x7fffffu) | 0x800000u;
+  const unsigned small = (unsigned)rintf(c * 0x1p32f);
+  return sh >= 0 ? (long long)(m << (sh & 63)) : (long long)small;
 }
 
 // Cross-lane moves on the VALU (DPP) rather than through the LDS crossbar.
@@ -1415,6 +1429,22 @@ struct TileRounds {
   }
 };
 
+// Records of n (<= 12) consecutive link slots into LDS: the heads, then the
+// tail pieces of the links that have a tail (the flags and interval counts
+// are in the heads just written; a wavefront's LDS accesses complete in
+// order), or INT_MAX for dsum[1..4] of the others.
+__device__ __forceinline__ void stage_recs(const v4u32* head, const v4u32* tail, int n, LinkRec* rec,
+                                           int lane) {
+  v4u32* dst = reinterpret_cast<v4u32*>(rec);
+  if (lane < n * kHeadPieces) dst[(lane >> 2) * kRecPieces + head_piece(lane & 3)] = head[lane];
+  if (lane < n * kTailPieces) {
+    const int i = lane / kTailPieces, k = lane - kTailPieces * i;
+    if ((rec[i].flags & kHasTail) && (tail_whole(rec[i]) || k == 0 || k == 1 || k == 3))
+      dst[i * kRecPieces + tail_piece(k)] = tail[lane];
+    else if (k == 0) dst[i * kRecPieces + 1] = (v4u32){INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+  }
+}
+
 // Role-split emit.  Persistent workgroups of W wavefronts take one ticket per
 // round and their wavefronts tiles ticket * W + w, so every tile a wavefront
 // waits on belongs to a wavefront already running.  Tile T stores ribs
@@ -1430,21 +1460,6 @@ struct TileRounds {
 // Arc length is accumulated in 64-bit fixed point (2^-32 px per unit): each
 // chord is rounded once and every sum after that is an integer sum, so s does
 // not depend on the tiling, the mapping or the order tiles finish in.
-// Records of n (<= 12) consecutive link slots into LDS: the heads, then the
-// tails of the links that have one (their flags are in the heads just
-// written; a wavefront's LDS accesses complete in order), or INT_MAX for
-// dsum[1..4] of the others.
-__device__ __forceinline__ void stage_recs(const v4u32* head, const v4u32* tail, int n, LinkRec* rec,
-                                           int lane) {
-  v4u32* dst = reinterpret_cast<v4u32*>(rec);
-  if (lane < n * kHeadPieces) dst[(lane >> 2) * kRecPieces + head_piece(lane & 3)] = head[lane];
-  if (lane < n * kTailPieces) {
-    const int i = lane / kTailPieces, k = lane - kTailPieces * i;
-    if (rec[i].flags & kHasTail) dst[i * kRecPieces + tail_piece(k)] = tail[lane];
-    else if (k == 0) dst[i * kRecPieces + 1] = (v4u32){INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-  }
-}
-
 constexpr int kWin = 12;
 struct SplitLDS {
   long long off[kWin + 1];
@@ -1648,7 +1663,7 @@ emit_split_kernel(EmitArgs A) {
             long long c = 0;
             if (mine && chord_ok && o.t >= pt) {
               const double dx = o.gx - pgx, dy = o.gy - pgy;
-              c = fix_round(sqrt64(dx * dx + dy * dy) * kFix);
+              c = chord_fix(dx, dy);
             }
             int f = (mine && path_start) ? 1 : 0;
             if (__ballot(f != 0 || c >= (1ll << 50)) == 0ull) {
@@ -1895,7 +1910,7 @@ emit_links_kernel(EmitArgs A) {
               long long c = 0;
               if (mine && j > 0 && o.t >= pt) {
                 const double dx = o.gx - pgx, dy = o.gy - pgy;
-                c = fix_round(sqrt64(dx * dx + dy * dy) * kFix);
+                c = chord_fix(dx, dy);
               }
               // a path restarts at the first rib of its first segment
               if (q0 == a && (rp.flags & kFirstSegInPath)) { run = 0; seen_start = true; }

@@ -30,18 +30,23 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-# Arc length per rib (Eq. arc-length-approximation): the GPU sums chords of its
-# FP64 rib points, each rounded to 2^-32 px (at most 2^-33 off), as exact
-# integers, and rounds the sum once to FP32.  The bound at a rib k chords into
-# its path is one FP32 spacing of s (the final rounding, counted in full to
-# cover the oracle's own FP64 sum) plus 2^-30 px per chord (the fixed-point
-# rounding and the FP64 chord difference between the two sides' points).
+# Arc length per rib (Eq. arc-length-approximation): the GPU takes each chord
+# of its FP64 rib points in FP32 (dx, dy rounded to FP32, the sum of squares
+# and the hardware square root each within an ulp: the chord within 2^-22 of
+# its length), as a whole number of 2^-32 px (at most 2^-33 off), sums them as
+# exact integers and rounds the sum once to FP32.  The bound at a rib k chords
+# into its path, whose oracle arc length is s, is one FP32 spacing of s (the
+# final rounding, counted in full to cover the oracle's own FP64 sum), plus
+# 2^-22 s (the FP32 chords), plus 2^-30 px per chord (the fixed-point rounding
+# and the FP64 difference between the two sides' points).
 ARC_PER_CHORD = 2.0 ** -30
+ARC_REL = 2.0 ** -22
 
 
 def _arc_tol(ref_s, k):
-    ref_s = np.asarray(ref_s, np.float64)
-    return np.spacing(np.abs(ref_s).astype(np.float32)).astype(np.float64) + (k + 1) * ARC_PER_CHORD
+    ref_s = np.abs(np.asarray(ref_s, np.float64))
+    return (np.spacing(ref_s.astype(np.float32)).astype(np.float64) + ARC_REL * ref_s
+            + (k + 1) * ARC_PER_CHORD)
 
 
 def _rib_index_in_path(b, off):
