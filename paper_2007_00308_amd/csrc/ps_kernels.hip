@@ -106,14 +106,18 @@ __device__ __forceinline__ void reset_status(DevStatus* st) {
   st->tile_counter = 0; st->dash_tile_counter = 0; st->scan_ticket = 0;
 }
 
-__device__ __forceinline__ int path_of_seg(const int32_t* seg_begin, int n_paths, int i) {
-  // largest p with seg_begin[p] <= i (the path that owns segment i)
-  int a = 0, b = n_paths - 1;
+// largest p in [a, b] with seg_begin[p] <= i, given seg_begin[a] <= i
+__device__ __forceinline__ int path_in(const int32_t* seg_begin, int a, int b, int i) {
   while (a < b) {
     const int m = (a + b + 1) >> 1;
     if (seg_begin[m] <= i) a = m; else b = m - 1;
   }
   return a;
+}
+
+__device__ __forceinline__ int path_of_seg(const int32_t* seg_begin, int n_paths, int i) {
+  // largest p with seg_begin[p] <= i (the path that owns segment i)
+  return path_in(seg_begin, 0, n_paths - 1, i);
 }
 
 // A segment contributes ribs if its values are finite and valid and it is
@@ -463,15 +467,15 @@ __device__ LinkRec start_cap(const CountArgs& A, int p, int b, int e, int& ribs)
 // start cap at 2 b + p, segment i at 2 i + p + 1, the link after it at
 // 2 i + p + 2 (b: the path's first segment).
 template <typename F>
-__device__ void count_segment(const CountArgs& A, const HeadStage& hs, int i) {
+__device__ void count_segment(const CountArgs& A, const HeadStage& hs, int i, int p_lo, int p_hi) {
   const ps_batch& B = A.B;
-  const int S = B.n_segs, P = B.n_paths;
+  const int S = B.n_segs;
   const uint8_t state = A.seg_ok[i];
   if (state & kSegBadValue) set_flag(A.st, PS_STATUS_BAD_VALUE);
   if (state & kSegNonFinite) set_flag(A.st, PS_STATUS_NONFINITE);
   const bool ok_i = state & kSegUsable;
   const double2 ang = A.seg_ang[i];   // F values
-  const int p = path_of_seg(B.seg_begin, P, i);
+  const int p = path_in(B.seg_begin, p_lo, p_hi, i);
   const int b = B.seg_begin[p], e = B.seg_begin[p + 1];
   const int64_t slot = 2 * (int64_t)i + p + 1;
   const float wd = B.width[p];
@@ -578,7 +582,7 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(CountArgs A) {
   __shared__ v4u32 stage[kStageSlots * kHeadPieces];
   __shared__ int stage_ribs[kStageSlots];
   __shared__ unsigned stage_valid[kStageSlots / 32];
-  __shared__ int stage_p0;
+  __shared__ int stage_p[2];   // the paths of the workgroup's first and last segments
   // The workgroup's segments are handed to its threads grouped by form
   // (unusable, line, quadratic, conic, cubic), so that a wavefront mostly
   // runs one form's setup instead of all of them one after another.  Which
@@ -589,7 +593,7 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(CountArgs A) {
   const int nseg = S - i0 < kCountThreads ? S - i0 : kCountThreads;
   if (threadIdx.x < 8) form_count[threadIdx.x] = 0;
   if (threadIdx.x < kStageSlots / 32) stage_valid[threadIdx.x] = 0;
-  if (threadIdx.x == 0) stage_p0 = path_of_seg(B.seg_begin, P, i0);
+  if (threadIdx.x < 2) stage_p[threadIdx.x] = path_of_seg(B.seg_begin, P, threadIdx.x ? i0 + nseg - 1 : i0);
   __syncthreads();
   int form = -1, rank = 0;
   if ((int)threadIdx.x < nseg) {
@@ -609,8 +613,8 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(CountArgs A) {
   hs.lds = stage;
   hs.ribs = stage_ribs;
   hs.valid = stage_valid;
-  hs.sb = 2 * (int64_t)i0 + stage_p0;
-  if ((int)threadIdx.x < nseg) count_segment<F>(A, hs, i0 + form_order[threadIdx.x]);
+  hs.sb = 2 * (int64_t)i0 + stage_p[0];
+  if ((int)threadIdx.x < nseg) count_segment<F>(A, hs, i0 + form_order[threadIdx.x], stage_p[0], stage_p[1]);
   __syncthreads();
   v4u32* const out = A.head + hs.sb * kHeadPieces;
   for (int c = threadIdx.x; c < kStageSlots * kHeadPieces; c += kCountThreads) {
