@@ -330,6 +330,47 @@ def test_edge_empty_paths_and_batches():
     assert r["R"] == 0
 
 
+def _tiny_paths(seed, n_paths):
+    """Thousands of paths of 0 to 3 segments: empty paths, zero-length and
+    collinear (folding) segments, closed paths, miter and round joins, round
+    and square caps."""
+    rng = np.random.default_rng(seed)
+    out, closed, joins, caps = [], [], [], []
+    for _ in range(n_paths):
+        n = int(rng.choice([0, 1, 1, 1, 2, 2, 3]))
+        segs = []
+        x, y = rng.uniform(0, 512, 2)
+        for _ in range(n):
+            r = rng.random()
+            if r < 0.1:
+                segs.append((W.KIND_C, [(x, y)] * 4, 1.0))   # a point: no ribs
+                continue
+            if r < 0.25:
+                d = rng.uniform(20, 60)
+                pts = [(x, y), (x + 1.5 * d, y), (x + 1.2 * d, y), (x + 2 * d, y)]   # folds twice
+                segs.append((W.KIND_C, pts, 1.0))
+            else:
+                k = int(rng.choice([W.KIND_L, W.KIND_Q, W.KIND_K, W.KIND_C]))
+                pts = [(x, y)] + [tuple(rng.uniform(0, 512, 2)) for _ in range(W.NPTS[k] - 1)]
+                segs.append((k, pts, float(rng.uniform(0.3, 3.0)) if k == W.KIND_K else 1.0))
+            x, y = segs[-1][1][-1]
+        out.append(segs)
+        closed.append(1 if (n and rng.random() < 0.2) else 0)
+        joins.append(int(rng.choice([W.JOIN_MITER, W.JOIN_MITER_CLIP, W.JOIN_ROUND, W.JOIN_BEVEL])))
+        caps.append(int(rng.choice([W.CAP_ROUND, W.CAP_SQUARE, W.CAP_BUTT])))
+    widths = list(rng.uniform(1.0, 12.0, n_paths))
+    return W.paths(out, widths=widths, q=math.pi / 16, joins=joins, caps=caps, closed=closed)
+
+
+def test_count_workgroups_with_many_paths():
+    # about 170 path starts per 256 segments: a count workgroup's link slots
+    # overrun its LDS stage of 576, so the later ones are written directly;
+    # record tails for miter joins and for segments of up to 5 intervals
+    b = _tiny_paths(77, 3000)
+    assert b.n_segs > 1024
+    _compare(b)
+
+
 @pytest.mark.parametrize("q", [math.pi, 1e-3])
 def test_edge_extreme_q(q):
     b = W.random_mixed(5, n_paths=4, max_segs=3, extent=300.0, q=q)
