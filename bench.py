@@ -73,6 +73,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-per-path", action="store_true", help="skip the per-path form")
     ap.add_argument("--no-c5", action="store_true", help="skip the 2^20-segment leg at q = pi/256")
+    ap.add_argument("--no-c1c3", action="store_true", help="skip the single-path legs (C1, C3)")
     ap.add_argument("--profile", action="store_true", help="few steps, no oracle (for rocprofv3)")
     ap.add_argument("--emit-config", default=None, metavar="M,K,W",
                     help="fixed emit mapping (PS_MAP_* mapping, ribs per lane, waves per group) "
@@ -94,6 +95,7 @@ def main() -> int:
         args.no_cpu = True
         args.no_per_path = True
         args.no_c5 = True
+        args.no_c1c3 = True
 
     import torch
     import paper_2007_00308_amd as ps
@@ -241,6 +243,15 @@ def main() -> int:
         log(f"errors: {errors}")
         del ref
 
+    c1 = c3 = None
+    if not args.no_c1c3:
+        # the single-path configurations: latency of one path through the same chain
+        log("C1 and C3 ...")
+        c1 = c1_leg(torch, ps, W, dev, args.steps, args.warmup)
+        c3 = c3_leg(torch, ps, W, dev, args.steps, args.warmup)
+        log(f"C1: {c1}")
+        log(f"C3: {c3}")
+
     c5 = None
     if not args.no_c5:
         # the largest configuration: same chain, 2^20 segments, the finest q
@@ -279,6 +290,8 @@ def main() -> int:
         "per_path": per_path,
         "cpu_baseline": cpu,
         "errors": errors,
+        "c1": c1,
+        "c3": c3,
         "c5": c5,
     }
     plan.close()
@@ -379,24 +392,34 @@ def study_precision(args, torch, ps, W, dev):
     return 0
 
 
-def study_c3(args, torch, ps, W, dev):
+def c3_leg(torch, ps, W, dev, steps: int, warmup: int) -> dict:
     """One 5,000-cubic random-walk path: stroke with arc length, then dashing."""
     b = W.config3()
     db = ps.DeviceBatch(b, device=dev)
     first = ps.stroke(db, b.q)
     R = first["total_ribs"]
+    del first
     rcap, dcap = 4 * R, R
     plan = ps.Plan(db, b.q, vertex_capacity=2 * R, dash=b.dash, dash_phase=b.dash_phase,
                    dash_rib_capacity=rcap, dash_capacity=dcap)
-    ms = _time_plan(torch, plan, args.steps, args.warmup)
+    ms = _time_plan(torch, plan, steps, warmup)
     st = plan.status()
+    assert st.flags == 0, f"status flags {st.flags}"
     plain = ps.Plan(db, b.q, vertex_capacity=2 * R)
-    ms_plain = _time_plan(torch, plain, args.steps, args.warmup)
-    res = {"study": "c3", "workload": b.name, "ribs": R, "vertices": 2 * R,
+    ms_plain = _time_plan(torch, plain, steps, warmup)
+    res = {"workload": "C3: 1 path x 5000 C1 cubics (random walk), width 2, q=pi/128, dash [10, 5]",
+           "ribs": R, "vertices": 2 * R,
            "ms_stroke": ms_plain, "ms_stroke_and_dash": ms, "ms_dash": ms - ms_plain,
            "dash_ribs": int(st.dash_ribs), "dashes": int(st.dash_count),
            "path_length_px": float(plan.vs[2 * R - 1].item()),
            "dash_bytes": 12 * 2 * int(st.dash_ribs) + 12 * 2 * R}
+    plan.close()
+    plain.close()
+    return res
+
+
+def study_c3(args, torch, ps, W, dev):
+    res = dict(study="c3", **c3_leg(torch, ps, W, dev, args.steps, args.warmup))
     log(str(res))
     print(json.dumps(res), flush=True)
     return 0
@@ -562,7 +585,7 @@ def study_mappings(args, torch, ps, W, dev):
     return 0
 
 
-def study_c1(args, torch, ps, W, dev):
+def c1_leg(torch, ps, W, dev, steps: int, warmup: int) -> dict:
     """C1, one path of 64 cubics: latency of the whole chain per path (one plan
     replay, and the three unplanned calls) and its vertices/s."""
     b = W.config1()
@@ -571,7 +594,7 @@ def study_c1(args, torch, ps, W, dev):
     R = first["total_ribs"]
     del first
     plan = ps.Plan(db, b.q, vertex_capacity=2 * R)
-    ms = _time_plan(torch, plan, max(args.steps, 50), args.warmup)
+    ms = _time_plan(torch, plan, max(steps, 50), warmup)
     lr = torch.empty(db.n_links, dtype=torch.int32, device=dev)
     of = torch.empty(db.n_links + 1, dtype=torch.int64, device=dev)
 
@@ -583,16 +606,22 @@ def study_c1(args, torch, ps, W, dev):
     for _ in range(5):
         calls()
     torch.cuda.synchronize()
-    n = max(args.steps, 50)
+    n = max(steps, 50)
     t0 = time.perf_counter()
     for _ in range(n):
         calls()
     torch.cuda.synchronize()
     ms_calls = 1e3 * (time.perf_counter() - t0) / n
+    st = plan.status()
+    assert st.flags == 0, f"status flags {st.flags}"
     plan.close()
-    row = {"study": "c1", "workload": "C1: 1 path x 64 cubics, q=pi/90, round joins", "ribs": R,
-           "us_per_path_plan": 1e3 * ms, "us_per_path_calls": 1e3 * ms_calls,
-           "vertices_per_s_plan": 2 * R / (ms * 1e-3)}
+    return {"workload": "C1: 1 path x 64 cubics, q=pi/90, round joins", "ribs": R,
+            "us_per_path_plan": 1e3 * ms, "us_per_path_calls": 1e3 * ms_calls,
+            "vertices_per_s_plan": 2 * R / (ms * 1e-3)}
+
+
+def study_c1(args, torch, ps, W, dev):
+    row = dict(study="c1", **c1_leg(torch, ps, W, dev, args.steps, args.warmup))
     log(str(row))
     print(json.dumps(row), flush=True)
     return 0
