@@ -821,6 +821,10 @@ __device__ __forceinline__ bool look_back(const unsigned long long* desc, int64_
 // 64-word read, 14.8 us: fewer blocks leave most CUs idle)
 constexpr int kLinkScanThreads = 256;
 constexpr int kLinkScanTile = kLinkScanThreads * kScanItems;
+// the workspace holds ceil(L / kScanTile) + 1 look-back words for the link
+// scan (WsLayout::nb_links), which covers its L / kLinkScanTile + 1 blocks
+// only if its blocks are no smaller
+static_assert(kLinkScanTile >= kScanTile, "link scan blocks must cover at least kScanTile links");
 
 struct LinkScanArgs {
   const int32_t* link_ribs;
