@@ -1178,6 +1178,39 @@ __device__ __forceinline__ double emit_solve64(const Hodo<double>& h, double nx,
   return t;
 }
 
+// The same isolation in FP32 (the hardware square root and reciprocal) for
+// the fix-up mode, whose FP64 Newton step then polishes the root: the root
+// chosen by the rules of emit_solve64, and `found` false when no root lies
+// in [lo, hi] (the rib then goes to the FP64 solve, which applies the end
+// rule).
+__device__ __forceinline__ float emit_solve32(const Hodo<float>& h, float nx, float ny, float lo, float hi,
+                                              bool& found) {
+  const float al = h.e0x * nx + h.e0y * ny;
+  const float be = h.e1x * nx + h.e1y * ny;
+  const float ga = h.e2x * nx + h.e2y * ny;
+  const float A = al - 2.0f * be + ga, B = 2.0f * (be - al), C = al;
+  const bool quad = A == 0.0f;
+  const float disc = fmaf(B, B, -4.0f * A * C);
+  const bool real = disc >= 0.0f;
+  const float sq = quad ? fabsf(B) : __builtin_amdgcn_sqrtf(real ? disc : 0.0f);
+  const float qq = -0.5f * (B + (B >= 0.0f ? sq : -sq));
+  const float inv = __builtin_amdgcn_rcpf(quad ? qq : A * qq);
+  const float r1 = real ? (quad ? C : C * A) * inv : -1.0f;
+  const float r0 = real ? (quad ? r1 : qq * qq * inv) : -1.0f;
+  const bool in0 = r0 >= lo && r0 <= hi;
+  const bool in1 = r1 >= lo && r1 <= hi && r1 != r0;
+  float t = in0 ? r0 : r1;
+  if (__ballot(in0 && in1)) {
+    const float tx = ny, ty = -nx;
+    const float a0 = h.e0x * tx + h.e0y * ty, b0 = h.e1x * tx + h.e1y * ty, c0 = h.e2x * tx + h.e2y * ty;
+    const float aT = a0 - 2.0f * b0 + c0, bT = 2.0f * (b0 - a0);
+    const float s0 = fmaf(fmaf(aT, r0, bT), r0, a0), s1 = fmaf(fmaf(aT, r1, bT), r1, a0);
+    if (in0 && in1 && s1 > s0) t = r1;
+  }
+  found = in0 || in1;
+  return t;
+}
+
 // Segment rib j of interval v (Eqs. func_t, func_N): the tangent angle
 // psi_j = psi_{k-1} + (j - Delta_Sigma(k-1)) delta_k / Delta_k (the boundary
 // angles exactly at the interval ends), n(psi) = (-sin psi, cos psi), t from
@@ -1227,37 +1260,32 @@ __device__ __forceinline__ void seg_rib(const LinkRec& rp, int j, const RibIval&
     for (int i = 0; i < 4; ++i) { Xd[i] = (double)X[i]; Yd[i] = (double)Y[i]; }
     double t = at1 ? v.hi : v.lo;
     if (solve) {
-      bool need64 = PREC == PS_PREC_FP64;
+      const Hodo<double> hd = hodo_of<double>(kind, Xd, Yd, (double)rp.w);
       if constexpr (PREC == PS_PREC_FP32_FIXUP) {
         // the FP32 quadratic isolates and selects the root, one FP64 Newton
         // step on g'(t).n polishes it; no FP32 root, a step above fix_tol or
         // a step out of the interval (a root close to a cusp or to the other
         // root) sends the rib to the FP64 solve
-        const Hodo<float> h = hodo_of<float>(kind, X, Y, rp.w);
-        const SolveOut<float> so = solve_t<float>(h, (float)nx, (float)ny, (float)ny, (float)-nx,
-                                                  (float)v.lo, (float)v.hi);
-        need64 = true;
-        if (so.found) {
-          const Hodo<double> hd = hodo_of<double>(kind, Xd, Yd, (double)rp.w);
-          const double al = hd.e0x * nx + hd.e0y * ny;
-          const double be = hd.e1x * nx + hd.e1y * ny;
-          const double ga = hd.e2x * nx + hd.e2y * ny;
-          const double Aq = al - 2.0 * be + ga, Bq = 2.0 * (be - al);
-          const double t0 = (double)so.t;
-          const double hv = (Aq * t0 + Bq) * t0 + al;
-          const float dv = (float)(2.0 * Aq * t0 + Bq);
-          const double step = (double)__builtin_amdgcn_rcpf(dv) * hv;
-          const double t1 = t0 - step;
-          if (dv != 0.0f && fabs(step) <= (double)fix_tol && t1 >= v.lo && t1 <= v.hi) {
-            t = t1;
-            need64 = false;
-          }
-        }
+        bool found;
+        const float t0f = emit_solve32(hodo_of<float>(kind, X, Y, rp.w), (float)nx, (float)ny,
+                                       (float)v.lo, (float)v.hi, found);
+        const double al = hd.e0x * nx + hd.e0y * ny;
+        const double be = hd.e1x * nx + hd.e1y * ny;
+        const double ga = hd.e2x * nx + hd.e2y * ny;
+        const double Aq = al - 2.0 * be + ga, Bq = 2.0 * (be - al);
+        const double t0 = (double)t0f;
+        const double hv = (Aq * t0 + Bq) * t0 + al;
+        const float dv = (float)(2.0 * Aq * t0 + Bq);
+        const double step = (double)__builtin_amdgcn_rcpf(dv) * hv;
+        const double t1 = t0 - step;
+        const bool need64 = !(found && dv != 0.0f && fabs(step) <= (double)fix_tol && t1 >= v.lo && t1 <= v.hi);
+        t = t1;
         o.fixed = need64;
-      }
-      if (need64) {
-        const Hodo<double> h = hodo_of<double>(kind, Xd, Yd, (double)rp.w);
-        t = emit_solve64(h, nx, ny, v.lo, v.hi);
+        if (__ballot(need64)) {
+          if (need64) t = emit_solve64(hd, nx, ny, v.lo, v.hi);
+        }
+      } else {
+        t = emit_solve64(hd, nx, ny, v.lo, v.hi);
       }
     }
     eval_point(kind, Xd, Yd, (double)rp.w, t, o.gx, o.gy);
