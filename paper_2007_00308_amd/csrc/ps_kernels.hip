@@ -392,9 +392,10 @@ __device__ inline LinkRec make_pivot(uint8_t role, double psi0, double psi1, int
 }
 
 // The record heads of a count workgroup's link slots are gathered in LDS and
-// written to memory with consecutive lanes on consecutive 16-byte pieces (a
-// thread's own records lie 144 bytes apart or more, so storing them from the
-// thread that built them costs a memory request per 16 bytes).  Stage
+// written to memory with consecutive lanes on consecutive 16-byte pieces (the
+// lanes of a wavefront hold segments of one form, scattered over the
+// workgroup's links, so one store instruction from the threads that built
+// the records would write 64 pieces far apart: a memory request each).  Stage
 // position 0 is link slot sb = 2 i0 + p0 (i0: the workgroup's first segment,
 // p0 its path); the workgroup's links come after it, with the start caps of
 // any paths without segments in between, which the path threads write.  A

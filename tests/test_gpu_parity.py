@@ -371,6 +371,26 @@ def test_count_workgroups_with_many_paths():
     _compare(b)
 
 
+def test_many_paths_every_record_reader():
+    # the same records read by the links mapping (scalar loads of head and
+    # tail) and by the uniform baseline (per-lane loads): bits equal to the
+    # tiles mapping, and the baseline against the oracle
+    import torch
+    b = _tiny_paths(78, 1500)
+    _, tiles = _gpu(b)
+    db, links = _gpu(b, emit=(ps.PS_MAP_LINKS, 7, 4))
+    for k in ("vx", "vy", "vs"):
+        assert torch.equal(tiles[k], links[k]), k
+    ref = oracle.stroke(b, uniform=True)
+    vx, vy = torch.empty_like(links["vx"]), torch.empty_like(links["vy"])
+    ps.ps_emit_uniform(db, links["params"], links["offsets"], vx, vy, links["capacity"], links["ws"])
+    torch.cuda.synchronize()
+    R = links["total_ribs"]
+    assert R == int(ref["offsets"][-1])
+    err = np.hypot(_np(vx)[:2 * R] - ref["vx"], _np(vy)[:2 * R] - ref["vy"])
+    assert err.max() <= VERTEX_TOL, err.max()
+
+
 @pytest.mark.parametrize("q", [math.pi, 1e-3])
 def test_edge_extreme_q(q):
     b = W.random_mixed(5, n_paths=4, max_segs=3, extent=300.0, q=q)
