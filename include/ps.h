@@ -65,8 +65,9 @@ enum { PS_CAP_BUTT = 0, PS_CAP_ROUND = 1, PS_CAP_SQUARE = 2, PS_CAP_TRIANGLE = 3
  *               counts, vertices within the FP32 rounding of the FP64 result,
  *               and the fastest of the two modes that are).
  * Join and cap ribs take an FP32 direction in every mode (their vertices lie
- * within r sqrt 2 of an exact pivot point); the arc length is FP64 chords
- * summed in 64-bit fixed point. */
+ * within r sqrt 2 of an exact pivot point); the arc length is FP32 chords of
+ * the FP64 rib points (each within 2^-22 of its length), summed exactly in
+ * 64-bit fixed point. */
 enum { PS_PREC_FP32 = 0, PS_PREC_FP32_FIXUP = 1, PS_PREC_FP64 = 2 };
 
 enum {
@@ -210,7 +211,10 @@ int ps_scan(const int32_t* link_ribs, int64_t n_links, int64_t* offsets, void* w
  * vx, vy [vertex_capacity] float.  vs [vertex_capacity] float receives the arc
  * length at the rib for both of its vertices: a chord sum from 0 at the first
  * rib of each path, constant across joins and caps, with a step whose t
- * decreases adding nothing.  Consecutive ribs of a path form its quads.
+ * decreases adding nothing.  The sums are exact integers of 2^-32 px, so s
+ * has the same bits whatever the mapping; they hold a path of up to 2^30 px
+ * (about 1.07e9 px: longer paths wrap) with chords below 2^31 px.
+ * Consecutive ribs of a path form its quads.
  * Requires ws from ps_count (same batch and params) and offsets from ps_scan.
  * If 2*R > vertex_capacity nothing is written and PS_STATUS_OVERFLOW is set;
  * each call clears that bit first, so a retry with enough capacity reports
